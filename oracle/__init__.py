@@ -1,0 +1,252 @@
+"""FP64 reference oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark use this
+package; the library never imports it. The arithmetic lives in ``fsmt_oracle.c`` (plain C,
+FP64, compiled with gcc, no FMA contraction) and, for the tiny brute-force pins, in
+``brute.py`` (pure Python / numpy). Paper references are given per function in the C file.
+
+Parity unpinned: the annealing driver ``anneal`` (Alg. "CLS with Annealing") has no printed
+trace in the paper; it is pinned only by replaying its steps from identical inputs.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fsmt_oracle.c")
+_LIB = os.path.join(_HERE, "libfsmt_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OProblem(ct.Structure):
+    _fields_ = [("n_bool", ct.c_int32), ("n_real", ct.c_int32), ("n_atoms", ct.c_int32),
+                ("n_cons", ct.c_int32)] + [(k, ct.c_void_p) for k in (
+                    "atom_ptr", "atom_var", "atom_coef", "atom_rhs", "atom_op", "con_kind",
+                    "con_ptr", "con_lit", "con_param", "expr_ptr", "expr_ops")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ct.CDLL(_LIB)
+        vp, i32, dbl = ct.c_void_p, ct.c_int, ct.c_double
+        L.oracle_objective.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
+        L.oracle_check.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.oracle_pgd.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
+        L.oracle_pgd.restype = None
+        L.oracle_erwa.argtypes = [i32, i32, vp, i32, dbl, dbl, i32, i32, vp, vp]
+        L.oracle_erwa.restype = None
+        L.oracle_cop_enum.argtypes = [vp, i32, vp, vp, vp]
+        L.oracle_cop_one.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.oracle_eval_formula.argtypes = [vp, i32, vp]
+        L.oracle_atom_probs.argtypes = [vp, vp, dbl, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(x: Optional[np.ndarray]):
+    return None if x is None else x.ctypes.data
+
+
+class OracleProblem:
+    """Contiguous copies of a :class:`workloads.Problem` plus the C view of them."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self.n, self.m, self.C = prob.n_bool, prob.n_real, prob.n_cons
+        self.A = prob.n_atoms
+        self._keep = {}
+        s = _OProblem()
+        s.n_bool, s.n_real, s.n_atoms, s.n_cons = self.n, self.m, self.A, self.C
+        for name, dt in (("atom_ptr", np.int64), ("atom_var", np.int32), ("atom_coef", np.float64),
+                         ("atom_rhs", np.float64), ("atom_op", np.int8), ("con_kind", np.int32),
+                         ("con_ptr", np.int64), ("con_lit", np.int32), ("con_param", np.int32),
+                         ("expr_ptr", np.int64), ("expr_ops", np.int32)):
+            arr = np.ascontiguousarray(getattr(prob, name), dtype=dt)
+            if arr.size == 0:
+                arr = np.zeros(1, dt)
+            self._keep[name] = arr
+            setattr(s, name, arr.ctypes.data)
+        self.s = s
+        self.lo = np.ascontiguousarray(prob.real_lo, np.float64)
+        self.hi = np.ascontiguousarray(prob.real_hi, np.float64)
+
+    @property
+    def ref(self):
+        return ct.byref(self.s)
+
+
+def _as(prob) -> OracleProblem:
+    return prob if isinstance(prob, OracleProblem) else OracleProblem(prob)
+
+
+def _f32(x, shape):
+    x = np.asarray(x, np.float32)
+    if shape[0] == -1 and shape[1] == 0:          # no variables of this kind: keep R
+        shape = (x.shape[0] if x.ndim == 2 else 1, 0)
+    return np.ascontiguousarray(x.reshape(shape))
+
+
+def objective(prob, a, b, kappa: float, w=None, grad: bool = True, per_constraint: bool = True,
+              sel=None):
+    """U[R], unsat/sat [R][C], grad_a [R][n], grad_b [R][m], |contribution| sums (FP64)."""
+    op = _as(prob)
+    a = _f32(a, (-1, op.n))
+    R = a.shape[0]
+    b = _f32(b, (R, op.m))
+    wv = None if w is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(w, np.float64), (R, op.C)))
+    out = dict(U=np.zeros(R))
+    if per_constraint:
+        out["unsat"] = np.full((R, op.C), np.nan)
+        out["sat"] = np.full((R, op.C), np.nan)
+    if grad:
+        for k, d in (("grad_a", op.n), ("grad_b", op.m), ("absg_a", op.n), ("absg_b", op.m)):
+            out[k] = np.zeros((R, d))
+    selv = None if sel is None else np.ascontiguousarray(sel, np.int32)
+    rc = lib().oracle_objective(
+        op.ref, R, _p(a), _p(b), float(kappa), _p(wv), _p(out["U"]), _p(out.get("unsat")),
+        _p(out.get("sat")), _p(out.get("grad_a")), _p(out.get("grad_b")), _p(out.get("absg_a")),
+        _p(out.get("absg_b")), _p(selv), 0 if selv is None else len(selv))
+    if rc != 0:
+        raise ValueError(f"oracle_objective failed ({rc})")
+    return out
+
+
+def check(prob, a, b):
+    """Rounded x [R][n] (int8 +-1), sat_bits [R][ceil(C/32)], n_unsat [R], verdict [R]."""
+    op = _as(prob)
+    a = _f32(a, (-1, op.n))
+    R = a.shape[0]
+    b = _f32(b, (R, op.m))
+    nw = (op.C + 31) // 32
+    x = np.zeros((R, op.n), np.int8)
+    bits = np.zeros((R, max(nw, 1)), np.uint32)
+    nu = np.zeros(R, np.int32)
+    ver = np.zeros(R, np.int32)
+    rc = lib().oracle_check(op.ref, R, _p(a), _p(b), _p(x), _p(bits), _p(nu), _p(ver))
+    if rc != 0:
+        raise ValueError(f"oracle_check failed ({rc})")
+    return dict(x=x, sat_bits=bits[:, :nw], n_unsat=nu, verdict=ver)
+
+
+def pgd(prob, a, b, ga, gb, eta_a: float, eta_b: float):
+    op = _as(prob)
+    a = _f32(a, (-1, op.n))
+    R = a.shape[0]
+    b, ga, gb = _f32(b, (R, op.m)), _f32(ga, (R, op.n)), _f32(gb, (R, op.m))
+    ao, bo, gsq = np.zeros((R, op.n)), np.zeros((R, op.m)), np.zeros(R)
+    lib().oracle_pgd(R, op.n, op.m, _p(a), _p(b), _p(ga), _p(gb), float(eta_a), float(eta_b),
+                     _p(op.lo), _p(op.hi), _p(ao), _p(bo), _p(gsq))
+    return dict(a=ao, b=bo, gsq=gsq)
+
+
+def erwa(sat_bits, n_cons: int, t: int, h, w, rho=0.5, gamma=2.0, tau=1, normalize=True):
+    """In-place ERWA update of h, w ([R][C] float64) from the satisfied-constraint bits."""
+    bits = np.ascontiguousarray(sat_bits, np.uint32)
+    R = bits.shape[0]
+    assert h.dtype == np.float64 and w.dtype == np.float64 and h.flags.c_contiguous
+    lib().oracle_erwa(R, n_cons, _p(bits), int(t), float(rho), float(gamma), int(tau),
+                      int(normalize), _p(h), _p(w))
+    return h, w
+
+
+def cop_enum(prob, c: int, pvar):
+    op = _as(prob)
+    pv = np.ascontiguousarray(pvar, np.float64)
+    PT, PF = ct.c_double(), ct.c_double()
+    rc = lib().oracle_cop_enum(op.ref, int(c), _p(pv), ct.byref(PT), ct.byref(PF))
+    if rc != 0:
+        raise ValueError(f"oracle_cop_enum failed ({rc})")
+    return PT.value, PF.value
+
+
+def cop_one(prob, c: int, pvar):
+    """(P_true, P_false, {var id: dP_false/dp}) of constraint c at variable probabilities."""
+    op = _as(prob)
+    pv = np.ascontiguousarray(pvar, np.float64)
+    PT, PF, k = ct.c_double(), ct.c_double(), ct.c_int()
+    dF = np.zeros(64)
+    ids = np.zeros(64, np.int32)
+    rc = lib().oracle_cop_one(op.ref, int(c), _p(pv), ct.byref(PT), ct.byref(PF), _p(dF),
+                              _p(ids), ct.byref(k))
+    if rc != 0:
+        raise ValueError(f"oracle_cop_one failed ({rc})")
+    return PT.value, PF.value, dict(zip(ids[:k.value].tolist(), dF[:k.value].tolist()))
+
+
+def eval_formula(prob, c: int, truth) -> int:
+    op = _as(prob)
+    t = np.ascontiguousarray(truth, np.int8)
+    return int(lib().oracle_eval_formula(op.ref, int(c), _p(t)))
+
+
+def atom_probs(prob, b, kappa: float):
+    op = _as(prob)
+    bb = _f32(b, (op.m,))
+    p, d, z = np.zeros(op.A), np.zeros(op.A), np.zeros(op.A)
+    rc = lib().oracle_atom_probs(op.ref, _p(bb), float(kappa), _p(p), _p(d), _p(z))
+    if rc != 0:
+        raise ValueError(f"oracle_atom_probs failed ({rc})")
+    return p, d, z
+
+
+def variable_probs(prob, a, b, kappa: float) -> np.ndarray:
+    """P[variable True] by variable id (Booleans, then atoms) at one point."""
+    p_atoms, _, _ = atom_probs(prob, b, kappa)
+    return np.concatenate([(1.0 - np.asarray(a, np.float32).astype(np.float64)) / 2.0, p_atoms])
+
+
+def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float = 1e-2,
+           rho=0.5, gamma=2.0, tau=1, normalize=True, w0=None):
+    """Alg. "CLS with Annealing" literally, with the PGD of Alg. "FourierSMT" inside.
+
+    Per level t (kappa_t): up to ``steps_per_level`` projected-gradient steps on U (stop
+    early once ||g||^2 <= eps^2), then rounding, exact check and the ERWA update. The
+    iterates are kept in float32 between steps (as the library stores them). Returns the
+    per-level trace. Parity unpinned (no printed trace in the paper).
+    """
+    op = _as(prob)
+    a = _f32(a0, (-1, op.n)).copy()
+    R = a.shape[0]
+    b = _f32(b0, (R, op.m)).copy()
+    w = np.ones((R, op.C)) if w0 is None else np.array(np.broadcast_to(w0, (R, op.C)), np.float64)
+    h = np.zeros((R, op.C))
+    trace = []
+    done = np.zeros(R, bool)
+    for t, kap in enumerate(kappas, start=1):
+        for _ in range(steps_per_level):
+            o = objective(op, a, b, kap, w=w, per_constraint=False)
+            st = pgd(op, a, b, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32),
+                     eta_a, eta_b)
+            a = np.where(done[:, None], a, st["a"].astype(np.float32))
+            b = np.where(done[:, None], b, st["b"].astype(np.float32))
+            if np.all((st["gsq"] <= eps * eps) | done):
+                break
+        ch = check(op, a, b)
+        erwa(ch["sat_bits"], op.C, t, h, w, rho, gamma, tau, normalize)
+        done |= ch["verdict"] == 1
+        trace.append(dict(level=t, kappa=kap, n_unsat=ch["n_unsat"].copy(), a=a.copy(),
+                          b=b.copy(), w=w.copy()))
+        if np.all(done):
+            break
+    return trace
