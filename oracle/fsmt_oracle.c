@@ -245,33 +245,30 @@ static int validate_expr(const cview *V)
 
 /* ------------------------------------------------- Shannon expansion with gradients */
 
-/* Returns P_true, P_false of the formula given the assignment of slots < depth, and
- * their derivatives in p[s] for s >= depth (dT, dF have k entries). */
-static void shannon(cview *V, int depth, double *PT, double *PF, double *dT, double *dF)
+/* Returns P_true, P_false of the formula given the assignment of slots < depth, and the
+ * derivatives of P_false in p[s] for s >= depth (dF has k entries). */
+static void shannon(cview *V, int depth, double *PT, double *PF, double *dF)
 {
     int v = eval3(V);
-    for (int s = depth; s < V->k; ++s) { dT[s] = 0.0; dF[s] = 0.0; }
+    for (int s = depth; s < V->k; ++s) dF[s] = 0.0;
     if (v >= 0) {
         *PT = v ? 1.0 : 0.0;
         *PF = v ? 0.0 : 1.0;
         return;
     }
     double AT, AF, BT, BF;
-    double dAT[MAX_SHANNON], dAF[MAX_SHANNON], dBT[MAX_SHANNON], dBF[MAX_SHANNON];
+    double dAF[MAX_SHANNON], dBF[MAX_SHANNON];
     V->val[depth] = 1;
-    shannon(V, depth + 1, &AT, &AF, dAT, dAF);
+    shannon(V, depth + 1, &AT, &AF, dAF);
     V->val[depth] = 0;
-    shannon(V, depth + 1, &BT, &BF, dBT, dBF);
+    shannon(V, depth + 1, &BT, &BF, dBF);
     V->val[depth] = -1;
     double p = V->p[depth];
     *PT = p * AT + (1.0 - p) * BT;
     *PF = p * AF + (1.0 - p) * BF;
-    dT[depth] = AT - BT;
     dF[depth] = AF - BF;
-    for (int s = depth + 1; s < V->k; ++s) {
-        dT[s] = p * dAT[s] + (1.0 - p) * dBT[s];
+    for (int s = depth + 1; s < V->k; ++s)
         dF[s] = p * dAF[s] + (1.0 - p) * dBF[s];
-    }
 }
 
 /* Count-distribution evaluation for symmetric kinds whose literals use distinct variables. */
@@ -301,7 +298,7 @@ static void count_dist(const double *pi, int L, int skip, double *dist)
     }
 }
 
-static void symmetric_eval(const cview *V, double *PT, double *PF, double *dT, double *dF)
+static void symmetric_eval(const cview *V, double *PT, double *PF, double *dF)
 {
     int L = V->n_lits;
     double pi[MAX_LITS], dist[MAX_LITS + 2];
@@ -316,32 +313,29 @@ static void symmetric_eval(const cview *V, double *PT, double *PF, double *dT, d
     }
     *PT = st;
     *PF = sf;
-    for (int s = 0; s < V->k; ++s) { dT[s] = 0.0; dF[s] = 0.0; }
+    for (int s = 0; s < V->k; ++s) dF[s] = 0.0;
     for (int l = 0; l < L; ++l) {
         count_dist(pi, L, l, dist);   /* distribution of the other L-1 literals */
-        double gt = 0.0, gf = 0.0;    /* d/d pi_l */
+        double gf = 0.0;              /* d P_false / d pi_l */
         for (int t = 0; t <= L - 1; ++t) {
             int with = symmetric_value(V->kind, V->param, L, t + 1);
             int without = symmetric_value(V->kind, V->param, L, t);
-            gt += dist[t] * ((double)with - (double)without);
             gf += dist[t] * ((double)(!with) - (double)(!without));
         }
-        double sgn = V->neg[l] ? -1.0 : 1.0;
-        dT[V->slot[l]] += sgn * gt;
-        dF[V->slot[l]] += sgn * gf;
+        dF[V->slot[l]] += (V->neg[l] ? -1.0 : 1.0) * gf;
     }
 }
 
-static int constraint_cop(cview *V, double *PT, double *PF, double *dT, double *dF)
+static int constraint_cop(cview *V, double *PT, double *PF, double *dF)
 {
     int rc = validate_expr(V);
     if (rc) return rc;
     if (V->k <= 12 || (V->k <= MAX_SHANNON && (V->kind == K_EXPR || V->k != V->n_lits))) {
-        shannon(V, 0, PT, PF, dT, dF);
+        shannon(V, 0, PT, PF, dF);
         return ORC_OK;
     }
     if (V->kind != K_EXPR && V->k == V->n_lits) {
-        symmetric_eval(V, PT, PF, dT, dF);
+        symmetric_eval(V, PT, PF, dF);
         return ORC_OK;
     }
     return ORC_ELIMIT;
@@ -382,8 +376,8 @@ int oracle_cop_one(const oproblem *P, int c, const double *pvar, double *PT, dou
     int rc = make_view(P, c, &V);
     if (rc) return rc;
     for (int s = 0; s < V.k; ++s) V.p[s] = pvar[V.ids[s]];
-    double dT[MAX_SUPPORT], dF[MAX_SUPPORT];
-    rc = constraint_cop(&V, PT, PF, dT, dF);
+    double dF[MAX_SUPPORT];
+    rc = constraint_cop(&V, PT, PF, dF);
     if (rc) return rc;
     for (int s = 0; s < V.k; ++s) { dF_out[s] = dF[s]; ids_out[s] = V.ids[s]; }
     *k_out = V.k;
@@ -448,8 +442,8 @@ int oracle_objective(const oproblem *P, int R, const float *a, const float *b, d
             cview V;
             if ((rc = make_view(P, c, &V))) break;
             for (int s = 0; s < V.k; ++s) V.p[s] = pv[V.ids[s]];
-            double PT, PF, dT[MAX_SUPPORT], dF[MAX_SUPPORT];
-            if ((rc = constraint_cop(&V, &PT, &PF, dT, dF))) break;
+            double PT, PF, dF[MAX_SUPPORT];
+            if ((rc = constraint_cop(&V, &PT, &PF, dF))) break;
             double wc = w ? w[(size_t)r * C + c] : 1.0;
             if (unsat) unsat[(size_t)r * C + c] = PF;
             if (sat) sat[(size_t)r * C + c] = PT;

@@ -128,6 +128,17 @@ def test_symmetric_closed_forms(L):
     np.testing.assert_allclose(o["sat"][0], expect_sat, rtol=1e-11, atol=1e-14)
     # clause unsat is the product of the literal-false probabilities (no subtraction)
     assert o["unsat"][0, 0] == pytest.approx(np.prod(1.0 - pl), rel=1e-12)
+    # gradient (count-distribution path for L > 12): U is affine in each a_i
+    a = (np.round(a * 1024) / 1024).astype(np.float32)
+    o = oracle.objective(p, a[None], np.zeros((1, 1), np.float32), 1.0)
+    for i in range(0, L, max(1, L // 5)):
+        ap, am = a.copy(), a.copy()
+        ap[i] += 2.0 ** -6
+        am[i] -= 2.0 ** -6
+        fd = (oracle.objective(p, ap[None], np.zeros((1, 1), np.float32), 1.0, grad=False)["U"][0]
+              - oracle.objective(p, am[None], np.zeros((1, 1), np.float32), 1.0, grad=False)["U"][0]
+              ) / 2.0 ** -5
+        assert o["grad_a"][0, i] == pytest.approx(fd, rel=1e-9, abs=1e-12)
 
 
 # ------------------------------------------------------------------ Monte Carlo
