@@ -1,0 +1,249 @@
+/*
+ * fsmt.h - C ABI of the MI355X (gfx950) FourierSMT hot-path library.
+ *
+ * The library evaluates the relaxed SMT(LRA) objective of FourierSMT (arXiv 2603.22877)
+ * as the circuit-output probability (COP) of each constraint's extended binary decision
+ * diagram (xBDD), its gradient by a reverse sweep, a projected-gradient step, and the
+ * rounding plus exact satisfaction check, for a batch of R candidate points ("restarts").
+ *
+ * Conventions (paper, Supplementary Note 1, Cor. "xWFE"; Eq. "rounding"; Eq. "sampling"):
+ *  - Truth values: -1 = True, +1 = False. A relaxed Boolean a_i in [-1, 1] is True with
+ *    probability p_i = (1 - a_i)/2.
+ *  - An atom q.y (op) q0 is True under Gaussian smoothing y' ~ N(b, sigma^2 I) with
+ *    probability p = erfc(kappa z / (sqrt(2) |q|)) / 2, z = q.b - q0 written in "<=" form
+ *    (">=" and ">" atoms are negated), kappa = 1/sigma in [0, +inf]. kappa = 0 gives
+ *    p = 1/2; kappa = +inf gives the exact indicator (and no gradient in b).
+ *  - Atoms inside one constraint are treated as independent events (product of their
+ *    marginal probabilities), as the message-passing algorithm of Supplementary Note 5
+ *    (Alg. "Forward Traversal of XBDDs") does.
+ *  - Library objective: U_r = sum_c w_{r,c} * P[c False]  (>= 0, zero exactly at satisfying
+ *    vertices). The paper's objective is C_sigma = sum_c w_c E[f_c] = 2 U - sum_c w_c
+ *    (Eq. "objective"). Gradients returned are grad U (not -grad C_sigma).
+ *
+ * Memory: every pointer named in a fsmt_view, and obj / gmap_sq / x / sat_bits / n_unsat /
+ * verdict, is DEVICE memory on the handle's device, owned by the caller and only read or
+ * written while the stream executes the call. fsmt_problem arrays are HOST memory, read
+ * only during xbdd_compile. Calls are asynchronous on the given HIP stream (NULL = the
+ * default stream) except xbdd_compile / xbdd_free / xbdd_info, which synchronize.
+ *
+ * Errors: every call returns an fsmt_status (0 = OK, < 0 = error) and never throws;
+ * fsmt_last_error() returns the text of the calling thread's last failure. Shape, stride,
+ * null-pointer and device checks happen on the host before anything is launched; on an
+ * error nothing is launched and outputs are untouched.
+ */
+#ifndef FSMT_H
+#define FSMT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fsmt_status;
+enum {
+    FSMT_OK = 0,
+    FSMT_EINVAL = -1,       /* invalid argument (shape, stride, pointer, value) */
+    FSMT_ENOMEM = -2,       /* host or device allocation failed */
+    FSMT_EUNSUPPORTED = -3, /* valid input the library does not handle ("=" atoms, ...) */
+    FSMT_ELIMIT = -4,       /* a size limit was exceeded (diagram nodes, support size) */
+    FSMT_EHIP = -5          /* a HIP runtime call failed */
+};
+
+/* atom comparison operators */
+enum { FSMT_LE = 0, FSMT_LT = 1, FSMT_GE = 2, FSMT_GT = 3, FSMT_EQ = 4 };
+/* constraint kinds: OR of literals, AND, odd parity, not-all-equal, #true <= k, #true >= k,
+ * postfix expression over the literal list */
+enum { FSMT_CLAUSE = 0, FSMT_AND = 1, FSMT_XOR = 2, FSMT_NAE = 3, FSMT_CARD_LE = 4,
+       FSMT_CARD_GE = 5, FSMT_EXPR = 6 };
+/* EXPR connectives (negative ops); an op v >= 0 pushes literal v of the constraint.
+ * ITE pops else, then, cond (pushed in the order cond, then, else). */
+enum { FSMT_X_AND = -1, FSMT_X_OR = -2, FSMT_X_XOR = -3, FSMT_X_NOT = -4, FSMT_X_ITE = -5,
+       FSMT_X_TRUE = -6, FSMT_X_FALSE = -7 };
+
+/* SMT(LRA) formula F = AND_c c (paper, "Satisfiability Modulo Theories"; atoms as in the
+ * "Walsh-Fourier Expansions" section). Host arrays, caller-owned, read during compile. */
+typedef struct {
+    int32_t n_bool, n_real, n_atoms, n_cons;
+    const int64_t *atom_ptr;   /* [n_atoms+1] CSR offsets into atom_var / atom_coef */
+    const int32_t *atom_var;   /* real-variable ids */
+    const double *atom_coef;   /* q_ij */
+    const double *atom_rhs;    /* [n_atoms] q_i0 */
+    const int8_t *atom_op;     /* [n_atoms] FSMT_LE..FSMT_GT (FSMT_EQ -> FSMT_EUNSUPPORTED) */
+    const int32_t *con_kind;   /* [n_cons] */
+    const int64_t *con_ptr;    /* [n_cons+1] offsets into con_lit */
+    const int32_t *con_lit;    /* literal = 2*id + negated; id < n_bool Boolean, else atom id-n_bool */
+    const int32_t *con_param;  /* [n_cons] k of the cardinality kinds (may be NULL) */
+    const int64_t *expr_ptr;   /* [n_cons+1] offsets into expr_ops (may be NULL if no EXPR) */
+    const int32_t *expr_ops;   /* postfix programs of EXPR constraints */
+    const double *real_lo;     /* [n_real] box of b, the feasible set of the projection */
+    const double *real_hi;     /* [n_real] */
+} fsmt_problem;
+
+#define FSMT_HOST_ONLY (-2)   /* compile_opts.device: keep tables on the host (inspection only) */
+
+typedef struct {
+    int32_t device;            /* HIP device that holds the tables (-1 = current device,
+                                  FSMT_HOST_ONLY = no upload: only xbdd_info and
+                                  xbdd_export_diagram accept such a handle) */
+    int32_t max_nodes;         /* reject diagrams with more decision nodes (0 = 1024) */
+    int32_t reserved[6];
+} fsmt_compile_opts;
+
+typedef struct {
+    int32_t n_bool, n_real, n_atoms, n_cons;
+    int64_t total_nodes;       /* sum over constraints of decision nodes |V_c| */
+    int32_t n_templates;       /* distinct diagram shapes */
+    int32_t max_nodes;         /* largest |V_c| */
+    int32_t max_slots;         /* largest support */
+    int32_t n_positions;       /* constraint slots after padding each shape bucket to 64 */
+    int64_t table_bytes;       /* device bytes of the compiled tables */
+    int64_t atom_nnz;
+} fsmt_xbdd_stats;
+
+/* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at
+ * data[r*stride_r + v*stride_v] (strides in elements). stride_r = 0 broadcasts one row
+ * (allowed for the weight view only). */
+typedef struct {
+    float *data;
+    int32_t rows, cols;
+    int64_t stride_r, stride_v;
+} fsmt_view;
+
+typedef struct fsmt_xbdd fsmt_xbdd;   /* opaque compiled instance */
+
+/* Text of the calling thread's last error ("" if none). Valid until the next call. */
+const char *fsmt_last_error(void);
+
+/*
+ * Compile every constraint into an xBDD (Supplementary Note 3, Def. "xBDD": decision nodes
+ * are Booleans or atoms; atoms are treated as propositional variables, no pruning), i.e. a
+ * reduced ordered BDD over the constraint's distinct variables (Booleans by id, then atoms
+ * by id). Nodes are stored in topological order (Alg. "Forward Traversal of XBDDs" visits
+ * them sorted); constraints with the same diagram shape share one node table and are
+ * grouped in buckets. Tables are uploaded to the device. *out receives a handle owned by
+ * the caller (release with xbdd_free). Errors: FSMT_EINVAL (malformed arrays),
+ * FSMT_EUNSUPPORTED ("=" atoms), FSMT_ELIMIT (diagram larger than opts->max_nodes),
+ * FSMT_ENOMEM, FSMT_EHIP. opts may be NULL.
+ */
+fsmt_status xbdd_compile(const fsmt_problem *problem, const fsmt_compile_opts *opts,
+                         fsmt_xbdd **out);
+void xbdd_free(fsmt_xbdd *handle);                          /* NULL is ignored */
+fsmt_status xbdd_info(const fsmt_xbdd *handle, fsmt_xbdd_stats *stats);
+
+/*
+ * Copy constraint c's compiled diagram to host memory (inspection and tests).
+ * nodes: [3*max_nodes] int32 receiving (slot, hi, lo) per decision node in topological
+ * order (root first); child index n_nodes is the True terminal, n_nodes+1 the False one.
+ * support: [max_slots] int32 receiving the variable id of each slot (Booleans first, then
+ * n_bool + atom id). *root is 0, or the terminal index for a constant constraint.
+ * Errors: FSMT_EINVAL (bad c, null pointer), FSMT_ELIMIT (buffers too small).
+ */
+fsmt_status xbdd_export_diagram(const fsmt_xbdd *handle, int32_t c, int32_t max_nodes, int32_t max_slots,
+                                int32_t *n_nodes, int32_t *n_slots, int32_t *n_bslots, int32_t *root,
+                                int32_t *nodes, int32_t *support);
+
+/* call flags */
+enum {
+    FSMT_ACCUMULATE = 1   /* add into obj / grads instead of overwriting them */
+};
+
+/*
+ * Forward pass (Alg. "Forward Traversal of XBDDs"; Supplementary Note 5, Lemma "forward"):
+ * literal probabilities from a [R][n_bool] and b [R][n_real] (Eq. "rounding", "sampling"),
+ * top-down path masses m_td, and per constraint P[c False] = mass reaching the false
+ * terminal. obj[r] = U_r = sum_c w[r][c] P[c False] ([R] device floats, required).
+ * w: [R][n_cons] or broadcast [1][n_cons] (stride_r = 0). unsat: optional [R][n_cons]
+ * output of P[c False] (data = NULL to skip). kappa = 1/sigma in [0, +inf].
+ */
+fsmt_status cop_forward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double kappa, fsmt_view w,
+                        float *obj, fsmt_view unsat, int32_t flags, void *stream);
+
+/*
+ * Forward + reverse sweep (Alg. "Backward Traversal of XBDD"; Supplementary Note 5, Lemma
+ * "backward", Thm. "Differentiation"): bottom-up masses m_bu(v) = P[reach False from v],
+ * dU/dp_v = w_c * sum_{nodes of v} m_td * (m_bu[true child] - m_bu[false child]), then the
+ * chain rule dp/da = -1/2 and dp/db_j = -kappa q_j exp(-u^2) / (sqrt(2 pi) |q|)
+ * (Supplementary Note 6). grad_a [R][n_bool], grad_b [R][n_real] receive grad U; obj
+ * (optional, NULL to skip) receives U. Without FSMT_ACCUMULATE the outputs are zeroed
+ * first. Gradient sums use float atomics, so the last bits vary between runs.
+ */
+fsmt_status cop_backward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double kappa,
+                         fsmt_view w, float *obj, fsmt_view grad_a, fsmt_view grad_b,
+                         int32_t flags, void *stream);
+
+/*
+ * Projected gradient step (Methods, Eq. "pg1"/"pg2", Def. "Projection" with the feasible
+ * set the box [-1,1]^n x [real_lo, real_hi]; the coordinate-wise clamp is the Euclidean
+ * projection onto a box), in place on a and b:
+ *   a <- clamp(a - eta_a grad_a), b <- clamp(b - eta_b grad_b),
+ * and gmap_sq[r] = ||g||^2 of the gradient map g = ((a-a+)/eta_a, (b-b+)/eta_b)
+ * (Eq. "grad_map", "critical"); gmap_sq may be NULL. grad_a / grad_b are zeroed after use
+ * (so the next cop_backward can run with FSMT_ACCUMULATE). NaN inputs stay NaN.
+ */
+fsmt_status pgd_step(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, fsmt_view grad_a,
+                     fsmt_view grad_b, float eta_a, float eta_b, float *gmap_sq, int32_t flags,
+                     void *stream);
+
+/*
+ * Rounding and exact check (Alg. "FourierSMT", last lines; Thm. "Soundness"):
+ * x_i = True (-1) iff a_i < 0 (so +-0 and NaN round to False); y = b. Atoms are decided
+ * exactly: z = sum_j q_j y_j - q0 in FP64 from the float32 y, multiply then add in the
+ * input's coefficient order (no fused multiply-add), True iff z <= 0 (z < 0 for strict
+ * atoms); NaN compares false. Each diagram is walked from its root.
+ * Outputs ([R] leading dimension, contiguous, device):
+ *   x [R][n_bool] int8 (+-1; NULL to skip), sat_bits [R][ceil(n_cons/32)] (bit c%32 of word
+ *   c/32 set iff constraint c is satisfied), n_unsat [R], verdict [R] (1 = SAT, 0 = UNKNOWN).
+ */
+fsmt_status round_and_check(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, int8_t *x,
+                            uint32_t *sat_bits, int32_t *n_unsat, int32_t *verdict,
+                            void *stream);
+
+/* ------------------------------------------------------------------ batched solver */
+
+/* Options of the annealed solver (Alg. "CLS with Annealing" around Alg. "FourierSMT"). */
+typedef struct {
+    const double *kappas;     /* host [n_levels] annealing schedule kappa_t = 1/sigma_t */
+    int32_t n_levels;
+    int32_t steps_per_level;  /* PGD iterations per level (cap) */
+    float eta_a, eta_b;       /* step sizes on U */
+    float eps;                /* stop a level early when ||g||^2 <= eps^2 (eps <= 0: never) */
+    float rho, gamma;         /* ERWA decay and scaling base */
+    int32_t tau;              /* ERWA update period in levels */
+    int32_t normalize;        /* renormalize weights to sum n_cons after each update */
+    int32_t stop_on_sat;      /* a restart stops once SAT; 0 = keep iterating (benchmarks) */
+    int32_t schedule;         /* 0 = automatic, 1 = persistent restart-per-workgroup,
+                                 2 = graph of grid-wide step kernels */
+    int32_t reserved[5];
+} fsmt_solve_opts;
+
+/* Per-instance solver state, device memory owned by the caller ([R] rows each). */
+typedef struct {
+    fsmt_view a, b;           /* [R][n_bool], [R][n_real] in/out (row stride >= cols, unit column stride) */
+    float *w;                 /* [R][n_cons] in/out weights */
+    float *hist;              /* [R][n_cons] in/out ERWA history h */
+    float *grad_a, *grad_b;   /* [R][n_bool], [R][n_real] scratch (same strides as a, b) */
+    uint32_t *sat_bits;       /* [R][ceil(n_cons/32)] out: last check */
+    int32_t *n_unsat;         /* [R] out */
+    int32_t *verdict;         /* [R] out: 1 = SAT found (state a, b holds the assignment) */
+    int32_t *level_done;      /* [R] out: levels completed */
+    int32_t *steps_done;      /* [R] out: PGD steps executed */
+    float *obj;               /* [R] out: U after the last step */
+} fsmt_solve_state;
+
+/*
+ * Run the annealed PGD solver for n_inst instances at once, each with its own R restarts,
+ * fusing forward, reverse sweep, projection, check and ERWA on the device. For every
+ * level kappa_t: up to steps_per_level PGD steps (stopping early at ||g||^2 <= eps^2),
+ * then rounding + exact check and the ERWA update (h = rho h + [violated]; every tau
+ * levels w *= gamma^h, h = 1, optional renormalization). A restart whose check reports
+ * no violated constraint is SAT (Thm. "Soundness"). Asynchronous on the stream.
+ */
+fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst,
+                               const fsmt_solve_opts *opts, const fsmt_solve_state *states,
+                               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSMT_H */

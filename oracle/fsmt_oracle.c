@@ -427,9 +427,23 @@ int oracle_objective(const oproblem *P, int R, const float *a, const float *b, d
     for (int r = 0; r < R && rc == ORC_OK; ++r) {
         const float *ar = a + (size_t)r * n, *br = b + (size_t)r * m;
         for (int i = 0; i < n; ++i) pv[i] = (1.0 - (double)ar[i]) / 2.0;
-        for (int k = 0; k < P->n_atoms; ++k) {
-            if (P->atom_op[k] == O_EQ) { rc = ORC_EUNSUPPORTED; break; }
-            pv[n + k] = atom_prob(P, k, br, kappa, &dz[k]);
+        if (!sel) {
+            for (int k = 0; k < P->n_atoms; ++k) {
+                if (P->atom_op[k] == O_EQ) { rc = ORC_EUNSUPPORTED; break; }
+                pv[n + k] = atom_prob(P, k, br, kappa, &dz[k]);
+            }
+        } else {   /* only the atoms of the selected constraints */
+            for (int ci = 0; ci < nc && !rc; ++ci) {
+                int c = sel[ci];
+                if (c < 0 || c >= C) { rc = ORC_EINVAL; break; }
+                for (int64_t l = P->con_ptr[c]; l < P->con_ptr[c + 1]; ++l) {
+                    int id = P->con_lit[l] >> 1;
+                    if (id < n) continue;
+                    int k = id - n;
+                    if (P->atom_op[k] == O_EQ) { rc = ORC_EUNSUPPORTED; break; }
+                    pv[id] = atom_prob(P, k, br, kappa, &dz[k]);
+                }
+            }
         }
         if (rc) break;
         if (grad_a) memset(grad_a + (size_t)r * n, 0, sizeof(double) * n);

@@ -1,0 +1,87 @@
+// Internal layout of a compiled instance (host compiler <-> HIP kernels).
+//
+// HBM layout (all arrays device-resident, read-only after xbdd_compile):
+//  * Diagram shapes ("templates"): constraints whose reduced ordered BDDs are identical up to
+//    renaming of their support variables share one node table. A node is 8 bytes
+//    {slot, hi, lo, pad} (u16 each); nodes are in topological order with the root at index
+//    0; child index n_nodes is the True terminal, n_nodes+1 the False terminal. Slots index
+//    the constraint's sorted support (Booleans first, then atoms).
+//  * Buckets: constraints of one template, in original order, padded to a multiple of 64
+//    "positions" so that a 64-lane wavefront never straddles two templates. The support ids
+//    of a bucket are stored slot-major (sup[sup_base + s*n_pos + local]) so that lanes
+//    working on consecutive constraints read consecutive words.
+//  * Atoms in "<=" form: ">=" / ">" atoms are stored negated (exact in floating point), with
+//    FP64 coefficients and right-hand side, the smoothing scale 1/(sqrt(2)|q|), and a
+//    strictness flag for the exact test.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fsmt.h"
+
+namespace fsmt {
+
+struct TplInfo {
+    int32_t node_off;   // first node in the node table
+    int32_t n_nodes;    // decision nodes (terminals excluded)
+    int32_t n_slots;    // support size
+    int32_t n_bslots;   // Boolean slots (slots [0, n_bslots) are Booleans)
+    int32_t root;       // 0, or n_nodes / n_nodes+1 for constant constraints
+    int32_t pad[3];
+};
+
+struct BucketInfo {
+    int32_t tpl;        // template id
+    int32_t pos_begin;  // first position (multiple of 64)
+    int32_t n_pos;      // positions, a multiple of 64 (>= constraints in the bucket)
+    int32_t n_con;      // real constraints in the bucket
+    int64_t sup_base;   // offset of the bucket's support block (n_slots * n_pos ids)
+    int64_t pad;
+};
+
+struct Node {
+    uint16_t slot, hi, lo, pad;
+};
+
+struct DeviceTables {
+    TplInfo *tpl = nullptr;
+    Node *nodes = nullptr;
+    BucketInfo *bucket = nullptr;
+    int32_t *bucket_start = nullptr;  // [n_buckets+1] position prefix
+    int32_t *pos_con = nullptr;       // [n_pos] original constraint id or -1 (padding)
+    int32_t *sup = nullptr;           // support ids, slot-major per bucket
+    int32_t *con_bucket = nullptr;    // [C]
+    int32_t *con_local = nullptr;     // [C] index inside its bucket
+    int32_t *atom_ptr = nullptr;      // [A+1]
+    int32_t *atom_var = nullptr;      // [nnz]
+    double *atom_coef = nullptr;      // [nnz] ("<=" form)
+    double *atom_rhs = nullptr;       // [A]   ("<=" form)
+    double *atom_scale = nullptr;     // [A]   1/(sqrt(2)|q|)
+    uint8_t *atom_strict = nullptr;   // [A]
+    float *real_lo = nullptr;         // [m]
+    float *real_hi = nullptr;         // [m]
+};
+
+}  // namespace fsmt
+
+struct fsmt_xbdd {
+    int device = 0;
+    int n_bool = 0, n_real = 0, n_atoms = 0, n_cons = 0;
+    int n_tpl = 0, n_buckets = 0, n_pos = 0;
+    int max_nodes = 0, max_slots = 0;
+    int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
+    std::vector<fsmt::TplInfo> h_tpl;
+    std::vector<fsmt::BucketInfo> h_bucket;
+    std::vector<int32_t> h_bucket_start;
+    std::vector<fsmt::Node> h_nodes;
+    std::vector<int32_t> h_sup, h_con_bucket, h_con_local;
+    bool host_only = false;
+    fsmt::DeviceTables d;
+    std::vector<void *> allocations;
+};
+
+namespace fsmt {
+// error reporting shared by the ABI entry points
+fsmt_status set_error(fsmt_status code, const char *fmt, ...);
+void clear_error();
+}  // namespace fsmt

@@ -1,0 +1,564 @@
+// Host compiler: constraint -> xBDD (paper, Supplementary Note 3, Def. "xBDD").
+//
+// Each constraint's formula is built as a reduced ordered BDD over its distinct variables
+// (Booleans by id, then atoms by id; atoms are propositional variables and no LP pruning
+// is done, as the paper prescribes for xBDDs). The paper uses the CUDD package for this
+// step; here a small ROBDD package (unique table + computed table + ITE) is written for
+// the purpose. Constraints whose formula has the same structure over the same pattern of
+// support slots share one compiled diagram ("template"), so a 720,000-constraint placement
+// instance compiles a handful of diagrams. Nodes are emitted in topological order
+// (ascending variable level, root first), the order in which the forward traversal visits
+// them (Alg. "Forward Traversal of XBDDs").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "fsmt_internal.hpp"
+
+namespace fsmt {
+
+// ------------------------------------------------------------------ error state
+static thread_local char g_err[512] = "";
+
+fsmt_status set_error(fsmt_status code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+void clear_error() { g_err[0] = 0; }
+const char *last_error() { return g_err; }
+
+// ------------------------------------------------------------------ ROBDD package
+class Robdd {
+  public:
+    static constexpr uint32_t kFalse = 0, kTrue = 1;
+    static constexpr uint32_t kTermVar = 0xFFFFFFFFu;
+
+    Robdd() {
+        var_ = {kTermVar, kTermVar};
+        hi_ = {kFalse, kTrue};
+        lo_ = {kFalse, kTrue};
+    }
+    uint32_t var(uint32_t f) const { return var_[f]; }
+    uint32_t hi(uint32_t f) const { return hi_[f]; }
+    uint32_t lo(uint32_t f) const { return lo_[f]; }
+    size_t size() const { return var_.size(); }
+
+    uint32_t literal(uint32_t v, bool neg) { return neg ? mk(v, kFalse, kTrue) : mk(v, kTrue, kFalse); }
+
+    uint32_t ite(uint32_t f, uint32_t g, uint32_t h) {
+        if (f == kTrue) return g;
+        if (f == kFalse) return h;
+        if (g == h) return g;
+        if (g == kTrue && h == kFalse) return f;
+        Key k{f, g, h};
+        auto it = computed_.find(k);
+        if (it != computed_.end()) return it->second;
+        uint32_t v = std::min(var_[f], std::min(var_[g], var_[h]));
+        uint32_t r = mk(v, ite(cof(f, v, true), cof(g, v, true), cof(h, v, true)),
+                        ite(cof(f, v, false), cof(g, v, false), cof(h, v, false)));
+        computed_.emplace(k, r);
+        return r;
+    }
+    uint32_t NOT(uint32_t f) { return ite(f, kFalse, kTrue); }
+    uint32_t AND(uint32_t f, uint32_t g) { return ite(f, g, kFalse); }
+    uint32_t OR(uint32_t f, uint32_t g) { return ite(f, kTrue, g); }
+    uint32_t XOR(uint32_t f, uint32_t g) { return ite(f, NOT(g), g); }
+
+  private:
+    struct Key {
+        uint32_t a, b, c;
+        bool operator==(const Key &o) const { return a == o.a && b == o.b && c == o.c; }
+    };
+    struct KeyHash {
+        size_t operator()(const Key &k) const {
+            uint64_t x = (uint64_t)k.a * 0x9E3779B97F4A7C15ull ^ (uint64_t)k.b * 0xC2B2AE3D27D4EB4Full ^
+                         (uint64_t)k.c * 0x165667B19E3779F9ull;
+            return (size_t)(x ^ (x >> 29));
+        }
+    };
+    uint32_t cof(uint32_t f, uint32_t v, bool high) const {
+        if (var_[f] != v) return f;
+        return high ? hi_[f] : lo_[f];
+    }
+    uint32_t mk(uint32_t v, uint32_t h, uint32_t l) {
+        if (h == l) return h;
+        Key k{v, h, l};
+        auto it = unique_.find(k);
+        if (it != unique_.end()) return it->second;
+        uint32_t id = (uint32_t)var_.size();
+        var_.push_back(v);
+        hi_.push_back(h);
+        lo_.push_back(l);
+        unique_.emplace(k, id);
+        return id;
+    }
+    std::vector<uint32_t> var_, hi_, lo_;
+    std::unordered_map<Key, uint32_t, KeyHash> unique_, computed_;
+};
+
+// ------------------------------------------------------------------ constraint structure
+
+struct ConView {
+    int kind = 0, param = 0;
+    std::vector<int32_t> ids;        // sorted distinct variable ids (the support)
+    std::vector<int32_t> lit_slot;   // literal position -> slot
+    std::vector<uint8_t> lit_neg;
+    const int32_t *ops = nullptr;
+    int64_t n_ops = 0;
+    int n_bslots = 0;
+};
+
+static bool symmetric_value(int kind, int param, int L, int t) {
+    switch (kind) {
+    case FSMT_CLAUSE: return t >= 1;
+    case FSMT_AND: return t == L;
+    case FSMT_XOR: return (t & 1) != 0;
+    case FSMT_NAE: return t > 0 && t < L;
+    case FSMT_CARD_LE: return t <= param;
+    case FSMT_CARD_GE: return t >= param;
+    }
+    return false;
+}
+
+// Builds the constraint's BDD over slot variables; returns the root.
+static uint32_t build_formula(Robdd &B, const ConView &cv) {
+    const int L = (int)cv.lit_slot.size();
+    std::vector<uint32_t> lits(L);
+    for (int t = 0; t < L; ++t) lits[t] = B.literal((uint32_t)cv.lit_slot[t], cv.lit_neg[t] != 0);
+    if (cv.kind == FSMT_EXPR) {
+        std::vector<uint32_t> st;
+        for (int64_t i = 0; i < cv.n_ops; ++i) {
+            int op = cv.ops[i];
+            if (op >= 0) { st.push_back(lits[op]); continue; }
+            if (op == FSMT_X_TRUE) { st.push_back(Robdd::kTrue); continue; }
+            if (op == FSMT_X_FALSE) { st.push_back(Robdd::kFalse); continue; }
+            if (op == FSMT_X_NOT) { st.back() = B.NOT(st.back()); continue; }
+            if (op == FSMT_X_ITE) {
+                uint32_t e = st.back(); st.pop_back();
+                uint32_t th = st.back(); st.pop_back();
+                uint32_t c = st.back(); st.pop_back();
+                st.push_back(B.ite(c, th, e));
+                continue;
+            }
+            uint32_t y = st.back(); st.pop_back();
+            uint32_t x = st.back(); st.pop_back();
+            st.push_back(op == FSMT_X_AND ? B.AND(x, y) : op == FSMT_X_OR ? B.OR(x, y) : B.XOR(x, y));
+        }
+        return st.back();
+    }
+    if (cv.kind == FSMT_CLAUSE) {
+        uint32_t r = Robdd::kFalse;
+        for (int t = L - 1; t >= 0; --t) r = B.OR(lits[t], r);
+        return r;
+    }
+    if (cv.kind == FSMT_AND) {
+        uint32_t r = Robdd::kTrue;
+        for (int t = L - 1; t >= 0; --t) r = B.AND(lits[t], r);
+        return r;
+    }
+    // symmetric kinds: F(i, t) = function of literals i..L-1 given t true literals so far
+    std::vector<uint32_t> next(L + 1), cur(L + 1);
+    for (int t = 0; t <= L; ++t) next[t] = symmetric_value(cv.kind, cv.param, L, t) ? Robdd::kTrue : Robdd::kFalse;
+    for (int i = L - 1; i >= 0; --i) {
+        for (int t = 0; t <= i; ++t) cur[t] = B.ite(lits[i], next[t + 1], next[t]);
+        std::swap(cur, next);
+    }
+    return next[0];
+}
+
+static fsmt_status check_expr(const ConView &cv, int n_lits, int c) {
+    int sp = 0;
+    for (int64_t i = 0; i < cv.n_ops; ++i) {
+        int op = cv.ops[i];
+        if (op >= 0) {
+            if (op >= n_lits) return set_error(FSMT_EINVAL, "constraint %d: EXPR pushes literal %d of %d", c, op, n_lits);
+            ++sp;
+        } else if (op == FSMT_X_TRUE || op == FSMT_X_FALSE) {
+            ++sp;
+        } else if (op == FSMT_X_NOT) {
+            if (sp < 1) return set_error(FSMT_EINVAL, "constraint %d: EXPR stack underflow", c);
+        } else if (op == FSMT_X_ITE) {
+            if (sp < 3) return set_error(FSMT_EINVAL, "constraint %d: EXPR stack underflow", c);
+            sp -= 2;
+        } else if (op == FSMT_X_AND || op == FSMT_X_OR || op == FSMT_X_XOR) {
+            if (sp < 2) return set_error(FSMT_EINVAL, "constraint %d: EXPR stack underflow", c);
+            --sp;
+        } else {
+            return set_error(FSMT_EINVAL, "constraint %d: unknown EXPR op %d", c, op);
+        }
+    }
+    if (sp != 1) return set_error(FSMT_EINVAL, "constraint %d: EXPR leaves %d values", c, sp);
+    return FSMT_OK;
+}
+
+struct Template {
+    int n_nodes = 0, n_slots = 0, n_bslots = 0, root = 0;
+    std::vector<Node> nodes;
+};
+
+// Levelize: nodes reachable from the root sorted by (level, id); root first.
+static fsmt_status emit_template(const Robdd &B, uint32_t root, const ConView &cv, int max_nodes,
+                                 Template &T) {
+    T.n_slots = (int)cv.ids.size();
+    T.n_bslots = cv.n_bslots;
+    if (root == Robdd::kTrue || root == Robdd::kFalse) {
+        T.n_nodes = 0;
+        T.root = root == Robdd::kTrue ? 0 : 1;
+        return FSMT_OK;
+    }
+    std::vector<uint32_t> stack{root}, order;
+    std::unordered_map<uint32_t, int> seen;
+    seen.emplace(root, 0);
+    while (!stack.empty()) {
+        uint32_t f = stack.back();
+        stack.pop_back();
+        order.push_back(f);
+        for (uint32_t ch : {B.hi(f), B.lo(f)})
+            if (ch > Robdd::kTrue && seen.emplace(ch, 0).second) stack.push_back(ch);
+    }
+    if ((int)order.size() > max_nodes)
+        return set_error(FSMT_ELIMIT, "diagram with %zu nodes exceeds max_nodes=%d", order.size(), max_nodes);
+    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return B.var(x) != B.var(y) ? B.var(x) < B.var(y) : x < y;
+    });
+    const int N = (int)order.size();
+    for (int i = 0; i < N; ++i) seen[order[i]] = i;
+    auto child = [&](uint32_t ch) -> uint16_t {
+        if (ch == Robdd::kTrue) return (uint16_t)N;
+        if (ch == Robdd::kFalse) return (uint16_t)(N + 1);
+        return (uint16_t)seen[ch];
+    };
+    T.n_nodes = N;
+    T.root = 0;
+    T.nodes.resize(N);
+    for (int i = 0; i < N; ++i) {
+        uint32_t f = order[i];
+        T.nodes[i] = Node{(uint16_t)B.var(f), child(B.hi(f)), child(B.lo(f)), 0};
+    }
+    return FSMT_OK;
+}
+
+// ------------------------------------------------------------------ device upload helper
+struct Uploader {
+    fsmt_xbdd *h;
+    template <class T>
+    fsmt_status put(T **dst, const std::vector<T> &src, const char *what) {
+        size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess)
+            return set_error(FSMT_ENOMEM, "hipMalloc of %zu bytes for %s failed", bytes, what);
+        h->allocations.push_back(p);
+        if (!src.empty() && hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return set_error(FSMT_EHIP, "hipMemcpy for %s failed", what);
+        h->table_bytes += (int64_t)(src.size() * sizeof(T));
+        *dst = (T *)p;
+        return FSMT_OK;
+    }
+};
+
+static void release(fsmt_xbdd *h) {
+    if (!h) return;
+    if (h->allocations.empty()) {
+        delete h;
+        return;
+    }
+    int prev = 0;
+    bool sw = hipGetDevice(&prev) == hipSuccess && prev != h->device;
+    if (sw) (void)hipSetDevice(h->device);
+    for (void *p : h->allocations) (void)hipFree(p);
+    if (sw) (void)hipSetDevice(prev);
+    delete h;
+}
+
+static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *opts, fsmt_xbdd **out) {
+    if (!P || !out) return set_error(FSMT_EINVAL, "null problem or output pointer");
+    *out = nullptr;
+    const int n = P->n_bool, m = P->n_real, A = P->n_atoms, C = P->n_cons;
+    if (n < 0 || m < 0 || A < 0 || C < 0) return set_error(FSMT_EINVAL, "negative size");
+    if ((A > 0 && (!P->atom_ptr || !P->atom_var || !P->atom_coef || !P->atom_rhs || !P->atom_op)) ||
+        (C > 0 && (!P->con_kind || !P->con_ptr || !P->con_lit)) || (m > 0 && (!P->real_lo || !P->real_hi)))
+        return set_error(FSMT_EINVAL, "null array in problem");
+    const int max_nodes = (opts && opts->max_nodes > 0) ? std::min(opts->max_nodes, 65000) : 1024;
+    const bool host_only = opts && opts->device == FSMT_HOST_ONLY;
+    int device = (opts && opts->device >= 0) ? opts->device : -1;
+    if (!host_only && device < 0 && hipGetDevice(&device) != hipSuccess)
+        return set_error(FSMT_EHIP, "hipGetDevice failed");
+    if ((int64_t)n + A > INT32_MAX / 2) return set_error(FSMT_ELIMIT, "too many variables");
+
+    // ---- atoms: validate and normalize to "<=" form
+    std::vector<int32_t> a_ptr(A + 1, 0), a_var;
+    std::vector<double> a_coef, a_rhs(A), a_scale(A);
+    std::vector<uint8_t> a_strict(A);
+    if (A > 0 && P->atom_ptr[0] != 0) return set_error(FSMT_EINVAL, "atom_ptr[0] != 0");
+    for (int k = 0; k < A; ++k) {
+        int64_t e0 = P->atom_ptr[k], e1 = P->atom_ptr[k + 1];
+        if (e1 <= e0) return set_error(FSMT_EINVAL, "atom %d has no coefficient", k);
+        int op = P->atom_op[k];
+        if (op == FSMT_EQ) return set_error(FSMT_EUNSUPPORTED, "atom %d: '=' atoms are not supported", k);
+        if (op < FSMT_LE || op > FSMT_GT) return set_error(FSMT_EINVAL, "atom %d: bad operator %d", k, op);
+        double sgn = (op == FSMT_GE || op == FSMT_GT) ? -1.0 : 1.0;
+        double nrm = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            int32_t j = P->atom_var[e];
+            if (j < 0 || j >= m) return set_error(FSMT_EINVAL, "atom %d: real variable %d out of range", k, j);
+            double q = P->atom_coef[e];
+            if (!std::isfinite(q)) return set_error(FSMT_EINVAL, "atom %d: non-finite coefficient", k);
+            a_var.push_back(j);
+            a_coef.push_back(sgn * q);
+            nrm += q * q;
+        }
+        if (!(nrm > 0.0)) return set_error(FSMT_EINVAL, "atom %d: all coefficients are zero", k);
+        if (!std::isfinite(P->atom_rhs[k])) return set_error(FSMT_EINVAL, "atom %d: non-finite rhs", k);
+        if ((int64_t)a_var.size() > INT32_MAX) return set_error(FSMT_ELIMIT, "too many atom coefficients");
+        a_ptr[k + 1] = (int32_t)a_var.size();
+        a_rhs[k] = sgn * P->atom_rhs[k];
+        a_scale[k] = 1.0 / (std::sqrt(2.0) * std::sqrt(nrm));
+        a_strict[k] = (op == FSMT_LT || op == FSMT_GT) ? 1 : 0;
+    }
+    for (int j = 0; j < m; ++j)
+        if (!(P->real_lo[j] <= P->real_hi[j])) return set_error(FSMT_EINVAL, "real %d: lo > hi", j);
+
+    // ---- constraints -> templates
+    std::unordered_map<std::string, int> tpl_index;
+    std::vector<Template> tpls;
+    std::vector<int32_t> con_tpl(C);
+    std::vector<int64_t> con_sup_off(C + 1, 0);
+    std::vector<int32_t> con_ids;   // concatenated supports in original order
+    std::vector<int32_t> key;
+    std::vector<std::pair<int32_t, int>> tmp;
+    if (C > 0 && P->con_ptr[0] != 0) return set_error(FSMT_EINVAL, "con_ptr[0] != 0");
+    for (int c = 0; c < C; ++c) {
+        int64_t l0 = P->con_ptr[c], l1 = P->con_ptr[c + 1];
+        if (l1 < l0) return set_error(FSMT_EINVAL, "constraint %d: con_ptr not monotone", c);
+        const int L = (int)(l1 - l0);
+        ConView cv;
+        cv.kind = P->con_kind[c];
+        cv.param = P->con_param ? P->con_param[c] : 0;
+        if (cv.kind < FSMT_CLAUSE || cv.kind > FSMT_EXPR) return set_error(FSMT_EINVAL, "constraint %d: bad kind %d", c, cv.kind);
+        tmp.clear();
+        for (int t = 0; t < L; ++t) {
+            int32_t lit = P->con_lit[l0 + t];
+            if (lit < 0 || (lit >> 1) >= n + A) return set_error(FSMT_EINVAL, "constraint %d: literal %d out of range", c, lit);
+            tmp.emplace_back(lit >> 1, t);
+        }
+        std::sort(tmp.begin(), tmp.end());
+        cv.lit_slot.assign(L, 0);
+        cv.lit_neg.assign(L, 0);
+        for (auto &pr : tmp) {
+            if (cv.ids.empty() || cv.ids.back() != pr.first) cv.ids.push_back(pr.first);
+            cv.lit_slot[pr.second] = (int32_t)cv.ids.size() - 1;
+            cv.lit_neg[pr.second] = (uint8_t)(P->con_lit[l0 + pr.second] & 1);
+        }
+        if (cv.ids.size() > 4096) return set_error(FSMT_ELIMIT, "constraint %d: support of %zu variables", c, cv.ids.size());
+        cv.n_bslots = 0;
+        while (cv.n_bslots < (int)cv.ids.size() && cv.ids[cv.n_bslots] < n) ++cv.n_bslots;
+        if (cv.kind == FSMT_EXPR) {
+            if (!P->expr_ptr || !P->expr_ops) return set_error(FSMT_EINVAL, "EXPR constraint %d without expr arrays", c);
+            cv.ops = P->expr_ops + P->expr_ptr[c];
+            cv.n_ops = P->expr_ptr[c + 1] - P->expr_ptr[c];
+            if (cv.n_ops < 0) return set_error(FSMT_EINVAL, "constraint %d: expr_ptr not monotone", c);
+            fsmt_status rc = check_expr(cv, L, c);
+            if (rc) return rc;
+        }
+        // structural key: kind, param, slot pattern of literals, slot kinds, program
+        key.clear();
+        key.push_back(cv.kind);
+        key.push_back((cv.kind == FSMT_CARD_LE || cv.kind == FSMT_CARD_GE) ? cv.param : 0);
+        key.push_back(L);
+        key.push_back((int32_t)cv.ids.size());
+        key.push_back(cv.n_bslots);
+        for (int t = 0; t < L; ++t) key.push_back(cv.lit_slot[t] * 2 + cv.lit_neg[t]);
+        for (int64_t i = 0; i < cv.n_ops; ++i) key.push_back(cv.ops[i]);
+        std::string ks((const char *)key.data(), key.size() * sizeof(int32_t));
+        auto it = tpl_index.find(ks);
+        int t_id;
+        if (it == tpl_index.end()) {
+            Robdd B;
+            uint32_t root = build_formula(B, cv);
+            Template T;
+            fsmt_status rc = emit_template(B, root, cv, max_nodes, T);
+            if (rc) return set_error(rc, "constraint %d: %s", c, last_error());
+            if (T.n_slots > 65535) return set_error(FSMT_ELIMIT, "constraint %d: support too large", c);
+            t_id = (int)tpls.size();
+            tpls.push_back(std::move(T));
+            tpl_index.emplace(std::move(ks), t_id);
+        } else {
+            t_id = it->second;
+        }
+        con_tpl[c] = t_id;
+        con_ids.insert(con_ids.end(), cv.ids.begin(), cv.ids.end());
+        con_sup_off[c + 1] = (int64_t)con_ids.size();
+    }
+
+    // ---- buckets: template-major, original order inside, padded to 64 positions
+    const int T = (int)tpls.size();
+    std::vector<std::vector<int32_t>> members(T);
+    for (int c = 0; c < C; ++c) members[con_tpl[c]].push_back(c);
+    auto *h = new (std::nothrow) fsmt_xbdd();
+    if (!h) return set_error(FSMT_ENOMEM, "out of host memory");
+    h->device = device;
+    h->n_bool = n;
+    h->n_real = m;
+    h->n_atoms = A;
+    h->n_cons = C;
+    h->n_tpl = T;
+    h->nnz = (int64_t)a_var.size();
+    std::vector<TplInfo> tinfo(T);
+    std::vector<Node> nodes;
+    for (int t = 0; t < T; ++t) {
+        const Template &tp = tpls[t];
+        tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, {0, 0, 0}};
+        nodes.insert(nodes.end(), tp.nodes.begin(), tp.nodes.end());
+        h->max_nodes = std::max(h->max_nodes, tp.n_nodes);
+        h->max_slots = std::max(h->max_slots, tp.n_slots);
+    }
+    std::vector<BucketInfo> buckets;
+    std::vector<int32_t> bstart{0}, pos_con, con_bucket(C), con_local(C), sup;
+    for (int t = 0; t < T; ++t) {
+        if (members[t].empty()) continue;
+        const int nc = (int)members[t].size();
+        const int npos = (nc + 63) / 64 * 64;
+        const int ns = tpls[t].n_slots;
+        BucketInfo bi{t, bstart.back(), npos, nc, (int64_t)sup.size(), 0};
+        const int b_id = (int)buckets.size();
+        sup.resize(sup.size() + (size_t)ns * npos, 0);
+        for (int i = 0; i < npos; ++i) {
+            int c = i < nc ? members[t][i] : -1;
+            pos_con.push_back(c);
+            if (c < 0) continue;
+            con_bucket[c] = b_id;
+            con_local[c] = i;
+            for (int s = 0; s < ns; ++s) sup[bi.sup_base + (int64_t)s * npos + i] = con_ids[con_sup_off[c] + s];
+            h->total_nodes += tpls[t].n_nodes;
+        }
+        if ((int64_t)bstart.back() + npos > INT32_MAX) { release(h); return set_error(FSMT_ELIMIT, "too many constraints"); }
+        bstart.push_back(bstart.back() + npos);
+        buckets.push_back(bi);
+    }
+    h->n_buckets = (int)buckets.size();
+    h->n_pos = bstart.back();
+    h->h_tpl = tinfo;
+    h->h_bucket = buckets;
+    h->h_bucket_start = bstart;
+    h->h_nodes = nodes;
+    h->h_sup = sup;
+    h->h_con_bucket = con_bucket;
+    h->h_con_local = con_local;
+    h->host_only = host_only;
+    if (host_only) {
+        *out = h;
+        return FSMT_OK;
+    }
+
+    std::vector<float> lo(m), hi(m);
+    for (int j = 0; j < m; ++j) {
+        lo[j] = (float)P->real_lo[j];
+        hi[j] = (float)P->real_hi[j];
+    }
+
+    // ---- upload
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+        release(h);
+        return set_error(FSMT_EHIP, "cannot select device %d", device);
+    }
+    Uploader U{h};
+    fsmt_status rc = FSMT_OK;
+    if (!rc) rc = U.put(&h->d.tpl, tinfo, "templates");
+    if (!rc) rc = U.put(&h->d.nodes, nodes, "nodes");
+    if (!rc) rc = U.put(&h->d.bucket, buckets, "buckets");
+    if (!rc) rc = U.put(&h->d.bucket_start, bstart, "bucket starts");
+    if (!rc) rc = U.put(&h->d.pos_con, pos_con, "positions");
+    if (!rc) rc = U.put(&h->d.sup, sup, "supports");
+    if (!rc) rc = U.put(&h->d.con_bucket, con_bucket, "constraint buckets");
+    if (!rc) rc = U.put(&h->d.con_local, con_local, "constraint positions");
+    if (!rc) rc = U.put(&h->d.atom_ptr, a_ptr, "atom offsets");
+    if (!rc) rc = U.put(&h->d.atom_var, a_var, "atom variables");
+    if (!rc) rc = U.put(&h->d.atom_coef, a_coef, "atom coefficients");
+    if (!rc) rc = U.put(&h->d.atom_rhs, a_rhs, "atom rhs");
+    if (!rc) rc = U.put(&h->d.atom_scale, a_scale, "atom scales");
+    if (!rc) rc = U.put(&h->d.atom_strict, a_strict, "atom flags");
+    if (!rc) rc = U.put(&h->d.real_lo, lo, "box lo");
+    if (!rc) rc = U.put(&h->d.real_hi, hi, "box hi");
+    (void)hipSetDevice(prev);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return FSMT_OK;
+}
+
+}  // namespace fsmt
+
+extern "C" {
+
+const char *fsmt_last_error(void) { return fsmt::last_error(); }
+
+fsmt_status xbdd_compile(const fsmt_problem *problem, const fsmt_compile_opts *opts, fsmt_xbdd **out) {
+    fsmt::clear_error();
+    try {
+        return fsmt::compile_impl(problem, opts, out);
+    } catch (const std::bad_alloc &) {
+        return fsmt::set_error(FSMT_ENOMEM, "out of host memory during compile");
+    } catch (...) {
+        return fsmt::set_error(FSMT_EINVAL, "unexpected exception during compile");
+    }
+}
+
+void xbdd_free(fsmt_xbdd *h) { fsmt::release(h); }
+
+fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
+    fsmt::clear_error();
+    if (!h || !s) return fsmt::set_error(FSMT_EINVAL, "null handle or stats");
+    s->n_bool = h->n_bool;
+    s->n_real = h->n_real;
+    s->n_atoms = h->n_atoms;
+    s->n_cons = h->n_cons;
+    s->total_nodes = h->total_nodes;
+    s->n_templates = h->n_tpl;
+    s->max_nodes = h->max_nodes;
+    s->max_slots = h->max_slots;
+    s->n_positions = h->n_pos;
+    s->table_bytes = h->table_bytes;
+    s->atom_nnz = h->nnz;
+    return FSMT_OK;
+}
+
+fsmt_status xbdd_export_diagram(const fsmt_xbdd *h, int32_t c, int32_t max_nodes, int32_t max_slots,
+                                int32_t *n_nodes, int32_t *n_slots, int32_t *n_bslots, int32_t *root,
+                                int32_t *nodes, int32_t *support) {
+    fsmt::clear_error();
+    if (!h || !n_nodes || !n_slots || !n_bslots || !root || !nodes || !support)
+        return fsmt::set_error(FSMT_EINVAL, "null argument");
+    if (c < 0 || c >= h->n_cons) return fsmt::set_error(FSMT_EINVAL, "constraint %d out of range", c);
+    const fsmt::BucketInfo &B = h->h_bucket[h->h_con_bucket[c]];
+    const fsmt::TplInfo &T = h->h_tpl[B.tpl];
+    if (T.n_nodes > max_nodes || T.n_slots > max_slots)
+        return fsmt::set_error(FSMT_ELIMIT, "diagram has %d nodes and %d slots", T.n_nodes, T.n_slots);
+    *n_nodes = T.n_nodes;
+    *n_slots = T.n_slots;
+    *n_bslots = T.n_bslots;
+    *root = T.root;
+    for (int v = 0; v < T.n_nodes; ++v) {
+        const fsmt::Node &x = h->h_nodes[T.node_off + v];
+        nodes[3 * v] = x.slot;
+        nodes[3 * v + 1] = x.hi;
+        nodes[3 * v + 2] = x.lo;
+    }
+    const int local = h->h_con_local[c];
+    for (int s = 0; s < T.n_slots; ++s) support[s] = h->h_sup[B.sup_base + (int64_t)s * B.n_pos + local];
+    return FSMT_OK;
+}
+
+}  // extern "C"

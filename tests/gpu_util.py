@@ -1,0 +1,48 @@
+"""Helpers for the GPU parity tests: tolerances and tensor plumbing."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+# Tolerances (floating point parity, FP32 library vs FP64 oracle on identical inputs):
+#  objective U:       |U - U_ref| <= 1e-5 U_ref + 1e-6 sum(w)       (relative, floor near SAT)
+#  per-constraint:    |u - u_ref| <= 1e-5 u_ref + 1e-7
+#  gradient (vector): ||g - g_ref||_2 <= 1e-5 ||g_ref||_2 (+ tiny absolute floor)
+#  gradient (coord):  |g_i - g_ref_i| <= 1e-5 * sum_c |dU_c/dv_i| + 4e-7 * max_i sum_c |dU_c/dv_i|
+REL = 1e-5
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def T(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x), device=dev(), dtype=dtype)
+
+
+def assert_objective(U, U_ref, wsum):
+    U = np.asarray(U, np.float64)
+    err = np.abs(U - U_ref)
+    tol = REL * np.abs(U_ref) + 1e-6 * np.asarray(wsum)
+    assert np.all(err <= tol), f"objective: max err {err.max():.3e}, worst ratio {(err / tol).max():.3f}"
+
+
+def assert_unsat(u, u_ref):
+    u = np.asarray(u, np.float64)
+    err = np.abs(u - u_ref)
+    tol = REL * np.abs(u_ref) + 1e-7
+    assert np.all(err <= tol), f"unsat: max err {err.max():.3e}, worst ratio {(err / tol).max():.3f}"
+
+
+def assert_gradient(g, g_ref, absg, name="grad"):
+    g = np.asarray(g, np.float64)
+    for r in range(g.shape[0]):
+        nrm = np.linalg.norm(g_ref[r])
+        e = np.linalg.norm(g[r] - g_ref[r])
+        assert e <= REL * nrm + 1e-12, f"{name}[{r}]: ||err|| {e:.3e} vs ||ref|| {nrm:.3e}"
+        if absg is not None and absg.shape[1] > 0:
+            tol = REL * absg[r] + 4e-7 * absg[r].max() + 1e-30
+            err = np.abs(g[r] - g_ref[r])
+            assert np.all(err <= tol), f"{name}[{r}]: coord err ratio {(err / tol).max():.3f}"

@@ -1,0 +1,209 @@
+"""Host compiler and C-ABI surface tests (CPU only: handles compiled with FSMT_HOST_ONLY)."""
+import ctypes as ct
+import os
+import re
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads.format import (KIND_CARD_LE, KIND_CLAUSE, KIND_EXPR, KIND_XOR, OP_EQ, OP_LE, X_AND,
+                              Builder, lit)
+
+fsmt = pytest.importorskip("paper_2603_22877_amd")
+from paper_2603_22877_amd import _abi  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOST = fsmt.FSMT_HOST_ONLY
+
+
+def compile_host(p, **kw):
+    return fsmt.xbdd_compile(p, device=HOST, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(os.path.join(ROOT, "include", "fsmt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\([^;{]*\)\s*;", text, flags=re.M))
+    names -= {"if", "while"}
+    assert names >= {"xbdd_compile", "cop_forward", "cop_backward", "pgd_step", "round_and_check"}
+    lib = ct.CDLL(_abi.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared in fsmt.h but not exported"
+    assert set(_abi.EXPORTED) == names
+
+
+def _host_unsat(d, pvar):
+    """Forward pass over an exported diagram (test-local walker): mass of the False terminal."""
+    N = d["n_nodes"]
+    M = np.zeros(N + 2)
+    M[d["root"]] = 1.0
+    for v in range(N):
+        s, hi, lo = d["nodes"][v]
+        p = pvar[d["support"][s]]
+        M[hi] += p * M[v]
+        M[lo] += (1 - p) * M[v]
+    return M[N + 1]
+
+
+def _host_walk(d, truth):
+    v = d["root"]
+    while v < d["n_nodes"]:
+        s, hi, lo = d["nodes"][v]
+        v = hi if truth[d["support"][s]] else lo
+    return v == d["n_nodes"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_compiled_diagrams_reproduce_oracle_cop(seed):
+    p = W.make_random_formula(900 + seed, n_cons=40, max_len=6)
+    h = compile_host(p)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1, 1, p.n_bool).astype(np.float32)
+    b = rng.uniform(-2, 2, p.n_real).astype(np.float32)
+    pv = oracle.variable_probs(p, a, b, 0.9)
+    o = oracle.objective(p, a[None], b[None], 0.9, grad=False)
+    for c in range(p.n_cons):
+        d = fsmt.xbdd_export_diagram(h, c)
+        nodes = d["nodes"]
+        for v in range(d["n_nodes"]):                      # topological: children come later
+            assert nodes[v, 1] > v and nodes[v, 2] > v
+        assert np.all(np.diff(d["support"]) > 0)          # sorted distinct support
+        assert np.all(d["support"][:d["n_bslots"]] < p.n_bool)
+        assert np.all(d["support"][d["n_bslots"]:] >= p.n_bool)
+        assert _host_unsat(d, pv) == pytest.approx(o["unsat"][0, c], abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_compiled_diagrams_decide_like_the_formula(seed):
+    p = W.make_random_formula(950 + seed, n_cons=40, max_len=6)
+    h = compile_host(p)
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        a = rng.uniform(-1, 1, p.n_bool).astype(np.float32)
+        b = rng.uniform(-2, 2, p.n_real).astype(np.float32)
+        ch = oracle.check(p, a[None], b[None])
+        pv = oracle.variable_probs(p, a, b, float("inf"))   # exact atom truth values
+        truth = np.concatenate([a < 0, pv[p.n_bool:] > 0.5])
+        for c in range(p.n_cons):
+            d = fsmt.xbdd_export_diagram(h, c)
+            assert _host_walk(d, truth) == bool((ch["sat_bits"][0, c >> 5] >> (c & 31)) & 1)
+
+
+def test_diagram_sizes_of_workload_constraints():
+    p1 = W.make_config(1)
+    h1 = compile_host(p1)
+    P = p1.meta["n_pairs"]
+    assert fsmt.xbdd_export_diagram(h1, 0)["n_nodes"] == 2       # 2-literal clause
+    assert fsmt.xbdd_export_diagram(h1, 2 * P)["n_nodes"] == 1   # unit atom
+    p3 = W.make_config(3)
+    h3 = compile_host(p3)
+    sizes = {}
+    for c in range(0, p3.meta["n_pairs"], 97):
+        d = fsmt.xbdd_export_diagram(h3, c)
+        sizes[d["n_slots"]] = d["n_nodes"]
+    assert sizes[10] == 17               # ITE over rotations of 4-atom ORs, no square rectangles
+    info = fsmt.xbdd_info(h3)
+    assert info["n_templates"] <= 8
+    assert info["n_cons"] == p3.n_cons and info["n_positions"] % 64 == 0
+    feas = fsmt.xbdd_export_diagram(h3, p3.meta["n_pairs"])
+    assert feas["n_nodes"] in (1, 3)
+
+
+def test_variable_order_invariance_of_cop():
+    """The same constraint with Boolean ids permuted has the same COP (order does not matter)."""
+    rng = np.random.default_rng(4)
+    b1 = Builder(3, 1, [-1], [1])
+    b1.add(KIND_EXPR, [lit(0), lit(1, True), lit(2)], 0, [0, 1, X_AND, 2, -2])
+    b2 = Builder(3, 1, [-1], [1])
+    b2.add(KIND_EXPR, [lit(2), lit(0, True), lit(1)], 0, [0, 1, X_AND, 2, -2])
+    p1, p2 = b1.build(), b2.build()
+    a = rng.uniform(-1, 1, 3).astype(np.float32)
+    perm = np.array([a[2], a[0], a[1]], np.float32)   # var 0 of p2 carries a[2]... etc.
+    d1 = fsmt.xbdd_export_diagram(compile_host(p1), 0)
+    d2 = fsmt.xbdd_export_diagram(compile_host(p2), 0)
+    u1 = _host_unsat(d1, (1 - a.astype(np.float64)) / 2)
+    u2 = _host_unsat(d2, (1 - np.array([a[1], a[2], a[0]], np.float64)) / 2)
+    assert u1 == pytest.approx(u2, abs=1e-15)
+    del perm
+
+
+def test_shapes_are_shared_by_placement_pairs_and_compile_is_fast():
+    p5 = W.make_config(5)
+    t = time.time()
+    h = compile_host(p5)
+    dt = time.time() - t
+    info = fsmt.xbdd_info(h)
+    assert info["n_cons"] == 721_800 and info["n_templates"] <= 12
+    assert dt < 60.0
+
+
+def test_large_symmetric_constraint_compiles_to_quadratic_diagram():
+    b = Builder(40, 1, [-1], [1])
+    b.add(KIND_CARD_LE, [lit(i, i % 3 == 0) for i in range(40)], 13)
+    b.add(KIND_XOR, [lit(i) for i in range(40)])
+    p = b.build()
+    h = compile_host(p, max_nodes=4096)
+    card = fsmt.xbdd_export_diagram(h, 0)
+    xor = fsmt.xbdd_export_diagram(h, 1)
+    assert card["n_nodes"] <= 40 * 14
+    assert xor["n_nodes"] == 2 * 40 - 1
+    rng = np.random.default_rng(0)
+    a = rng.uniform(-1, 1, 40).astype(np.float32)
+    o = oracle.objective(p, a[None], np.zeros((1, 1), np.float32), 1.0, grad=False)
+    pv = (1 - a.astype(np.float64)) / 2
+    assert _host_unsat(card, pv) == pytest.approx(o["unsat"][0, 0], abs=1e-12)
+    assert _host_unsat(xor, pv) == pytest.approx(o["unsat"][0, 1], abs=1e-12)
+
+
+def test_constant_constraints():
+    b = Builder(2, 1, [-1], [1])
+    b.add(KIND_CLAUSE, [lit(0), lit(0, True)])    # tautology
+    b.add(KIND_CLAUSE, [])                        # empty clause: false
+    b.add(KIND_XOR, [lit(1), lit(1)])             # x xor x: false
+    p = b.build()
+    h = compile_host(p)
+    d = [fsmt.xbdd_export_diagram(h, c) for c in range(3)]
+    assert [x["n_nodes"] for x in d] == [0, 0, 0]
+    assert [x["root"] for x in d] == [0, 1, 1]
+
+
+# ---------------------------------------------------------------------- error paths
+def _err(p, **kw):
+    with pytest.raises(fsmt.FsmtError) as e:
+        compile_host(p, **kw)
+    return e.value.code
+
+
+def test_errors_are_reported_not_thrown():
+    b = Builder(1, 1, [-1], [1])
+    b.add(KIND_CLAUSE, [lit(b.atom([0], [1.0], OP_EQ, 0.0))])
+    assert _err(b.build()) == _abi.FSMT_EUNSUPPORTED
+    p = W.make_config(1)
+    p.con_lit = p.con_lit.copy()
+    p.con_lit[0] = 2 * (p.n_bool + p.n_atoms + 5)
+    assert _err(p) == _abi.FSMT_EINVAL
+    b = Builder(1, 1, [-1], [1])
+    b.add(KIND_CLAUSE, [lit(b.atom([0], [0.0], OP_LE, 0.0))])
+    assert _err(b.build()) == _abi.FSMT_EINVAL
+    b = Builder(2, 1, [-1], [1])
+    b.add(KIND_EXPR, [lit(0), lit(1)], 0, [0, X_AND])
+    assert _err(b.build()) == _abi.FSMT_EINVAL
+    b = Builder(30, 1, [-1], [1])
+    b.add(KIND_CARD_LE, [lit(i) for i in range(30)], 15)
+    assert _err(b.build(), max_nodes=50) == _abi.FSMT_ELIMIT
+    p = W.make_config(1)
+    p.real_lo = p.real_lo.copy()
+    p.real_lo[0] = p.real_hi[0] + 1
+    assert _err(p) == _abi.FSMT_EINVAL
+
+
+def test_runtime_calls_reject_host_only_handles():
+    torch = pytest.importorskip("torch")
+    h = compile_host(W.make_fig2_toy())
+    a = torch.zeros(1, 1)
+    with pytest.raises(fsmt.FsmtError) as e:
+        fsmt.cop_forward(h, a, a, 1.0, torch.ones(2), torch.zeros(1), stream=0)
+    assert e.value.code == _abi.FSMT_EINVAL

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on identical inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from gpu_util import T, assert_gradient, assert_objective, assert_unsat, dev, torch
+
+pytestmark = pytest.mark.gpu
+fsmt = pytest.importorskip("paper_2603_22877_amd")
+
+INF = float("inf")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run_cop(p, h, a, b, kap, w=None, layout="rows", grad=True):
+    R = a.shape[0]
+    wt = T(np.ones(p.n_cons) if w is None else w)
+    if layout == "rows":
+        ta, tb = T(a), T(b)
+        ga = torch.zeros(R, p.n_bool, device=dev())
+        gb = torch.zeros(R, p.n_real, device=dev())
+    else:   # variable-major storage [n][R] viewed as [R][n]
+        ta, tb = T(a.T.copy()).t(), T(b.T.copy()).t()
+        ga = torch.zeros(p.n_bool, R, device=dev()).t()
+        gb = torch.zeros(p.n_real, R, device=dev()).t()
+    obj = torch.zeros(R, device=dev())
+    unsat = torch.zeros(R, p.n_cons, device=dev())
+    fsmt.cop_forward(h, ta, tb, kap, wt, obj, unsat)
+    out = dict(U_fwd=obj.cpu().numpy().copy(), unsat=unsat.cpu().numpy())
+    if grad:
+        obj2 = torch.zeros(R, device=dev())
+        fsmt.cop_backward(h, ta, tb, kap, wt, obj2, ga, gb)
+        out.update(U=obj2.cpu().numpy(), grad_a=ga.cpu().numpy(), grad_b=gb.cpu().numpy())
+    torch.cuda.synchronize()
+    return out
+
+
+def _compare(p, a, b, kap, w=None, layout="rows"):
+    h = fsmt.xbdd_compile(p)
+    g = _run_cop(p, h, a, b, kap, w, layout)
+    o = oracle.objective(p, a, b, kap, w=w)
+    wsum = (np.ones(p.n_cons) if w is None else np.broadcast_to(w, (a.shape[0], p.n_cons))).sum(-1)
+    assert_objective(g["U_fwd"], o["U"], wsum)
+    assert_objective(g["U"], o["U"], wsum)
+    assert_unsat(g["unsat"], o["unsat"])
+    assert_gradient(g["grad_a"], o["grad_a"], o["absg_a"], "grad_a")
+    assert_gradient(g["grad_b"], o["grad_b"], o["absg_b"], "grad_b")
+    h.free()
+    return g, o
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("R", [1, 3, 16, 64, 100])
+@pytest.mark.parametrize("kap", [0.0, 0.4, 2.5, INF])
+def test_random_formulas_all_kinds(seed, R, kap):
+    print(f"random formulas seed={seed} R={R} kappa={kap}", flush=True)
+    p = W.make_random_formula(1000 + seed, n_bool=8, n_real=4, n_atoms=8, n_cons=150, max_len=6)
+    a, b = W.initial_points(p, R, 99, seed)
+    a[0, :2] = [0.0, -1.0]
+    _compare(p, a, b, kap, w=np.random.default_rng(seed).uniform(0.5, 2, (R, p.n_cons)))
+
+
+def test_fig2_toy_values():
+    p = W.make_fig2_toy()
+    a = np.array([[0.3], [-0.9], [1.0]], np.float32)
+    b = np.array([[0.2], [-0.5], [0.0]], np.float32)
+    for kap in (0.0, 0.5, 1.7, INF):
+        _compare(p, a, b, kap)
+
+
+@pytest.mark.parametrize("cfg,R,kap", [(1, 1, 0.3), (1, 1, INF), (2, 64, 0.05), (2, 64, 0.5),
+                                       (3, 16, 0.1), (3, 16, 1.0)])
+def test_workload_configs(cfg, R, kap):
+    print(f"config {cfg} R={R} kappa={kap}", flush=True)
+    p = W.make_config(cfg)
+    a, b = W.initial_points(p, R, cfg, 0)
+    _compare(p, a, b, kap)
+
+
+@pytest.mark.parametrize("cfg,R", [(1, 5), (2, 64), (3, 16)])
+def test_variable_major_layout_matches(cfg, R):
+    p = W.make_config(cfg)
+    a, b = W.initial_points(p, R, cfg, 1)
+    _compare(p, a, b, 0.3, layout="cols")
+
+
+def test_hard_objective_counts_violations_at_vertices():
+    p = W.make_config(3)
+    R = 8
+    a, b = W.initial_points(p, R, 3, 2)
+    a = np.where(a < 0, -1.0, 1.0).astype(np.float32)
+    h = fsmt.xbdd_compile(p)
+    g = _run_cop(p, h, a, b, INF, grad=False)
+    ch = oracle.check(p, a, b)
+    np.testing.assert_array_equal(g["U_fwd"], ch["n_unsat"].astype(np.float32))
+
+
+def test_pgd_step_matches_oracle():
+    p = W.make_config(2)
+    R = 8
+    a, b = W.initial_points(p, R, 2, 3)
+    rng = np.random.default_rng(3)
+    ga = rng.normal(size=a.shape).astype(np.float32) * 3
+    gb = rng.normal(size=b.shape).astype(np.float32) * 50
+    h = fsmt.xbdd_compile(p)
+    ta, tb, tga, tgb = T(a), T(b), T(ga), T(gb)
+    gsq = torch.zeros(R, device=dev())
+    fsmt.pgd_step(h, ta, tb, tga, tgb, 0.25, 2.0, gsq)
+    o = oracle.pgd(p, a, b, ga, gb, 0.25, 2.0)
+    na, nb = ta.cpu().numpy(), tb.cpu().numpy()
+    assert np.all(np.abs(na - o["a"]) <= 2e-7 * np.maximum(1, np.abs(o["a"])))
+    assert np.all(np.abs(nb - o["b"]) <= 2e-7 * np.maximum(1, np.abs(o["b"])) + 1e-6)
+    assert np.all((na >= -1) & (na <= 1)) and np.all((nb >= 0) & (nb <= p.real_hi[0]))
+    np.testing.assert_allclose(gsq.cpu().numpy(), o["gsq"], rtol=1e-4)
+    assert float(tga.abs().max()) == 0.0 and float(tgb.abs().max()) == 0.0
+
+
+def _check_gpu(p, h, a, b):
+    R = a.shape[0]
+    nw = (p.n_cons + 31) // 32
+    x = torch.zeros(R, p.n_bool, dtype=torch.int8, device=dev())
+    bits = torch.zeros(R, nw, dtype=torch.int32, device=dev())
+    nu = torch.zeros(R, dtype=torch.int32, device=dev())
+    ver = torch.zeros(R, dtype=torch.int32, device=dev())
+    fsmt.round_and_check(h, T(a), T(b), x, bits, nu, ver)
+    torch.cuda.synchronize()
+    return dict(x=x.cpu().numpy(), sat_bits=bits.cpu().numpy().view(np.uint32), n_unsat=nu.cpu().numpy(),
+                verdict=ver.cpu().numpy())
+
+
+def _assert_check_equal(g, o):
+    np.testing.assert_array_equal(g["sat_bits"], o["sat_bits"])
+    np.testing.assert_array_equal(g["n_unsat"], o["n_unsat"])
+    np.testing.assert_array_equal(g["verdict"], o["verdict"])
+    np.testing.assert_array_equal(g["x"], o["x"])
+
+
+@pytest.mark.parametrize("cfg,R", [(1, 4), (2, 16), (3, 16)])
+def test_round_and_check_bit_exact(cfg, R):
+    p = W.make_config(cfg)
+    a, b = W.initial_points(p, R, cfg, 4)
+    a[0] = p.cert_x
+    b[0] = p.cert_y
+    a[1] = p.cert_x
+    b[1] = p.cert_y
+    b[1, 0] = b[1, 0] + 0.5
+    a[2, : min(3, p.n_bool)] = [0.0, -0.0, np.nan][: min(3, p.n_bool)]
+    h = fsmt.xbdd_compile(p)
+    g = _check_gpu(p, h, a, b)
+    o = oracle.check(p, a, b)
+    _assert_check_equal(g, o)
+    assert g["verdict"][0] == 1
+
+
+def test_check_boundary_atoms_and_random_formulas():
+    for seed in range(3):
+        p = W.make_random_formula(2000 + seed, n_cons=300, max_len=6)
+        a, b = W.initial_points(p, 10, 77, seed)
+        b[3] = np.round(b[3])
+        h = fsmt.xbdd_compile(p)
+        _assert_check_equal(_check_gpu(p, h, a, b), oracle.check(p, a, b))
+
+
+def test_adjoint_central_differences_config2():
+    """FP32 central differences of the GPU objective on 32 random coordinates."""
+    p = W.make_config(2)
+    R = 4
+    a, b = W.initial_points(p, R, 2, 5)
+    kap = 0.2
+    h = fsmt.xbdd_compile(p)
+    g = _run_cop(p, h, a, b, kap)
+    rng = np.random.default_rng(5)
+    wt = T(np.ones(p.n_cons))
+    obj = torch.zeros(R, device=dev())
+    for _ in range(32):
+        r = int(rng.integers(R))
+        if rng.random() < 0.5:
+            i = int(rng.integers(p.n_bool))
+            hstep = 2.0 ** -6
+            vals = []
+            for s in (1, -1):
+                aa = a.copy()
+                aa[r, i] = np.float32(a[r, i] + s * hstep)
+                fsmt.cop_forward(h, T(aa), T(b), kap, wt, obj)
+                vals.append(float(obj[r]))
+            fd = (vals[0] - vals[1]) / (2 * hstep)
+            ref = g["grad_a"][r, i]
+        else:
+            j = int(rng.integers(p.n_real))
+            hstep = 2.0 ** -2
+            vals = []
+            for s in (1, -1):
+                bb = b.copy()
+                bb[r, j] = np.float32(b[r, j] + s * hstep)
+                fsmt.cop_forward(h, T(a), T(bb), kap, wt, obj)
+                vals.append(float(obj[r]))
+            fd = (vals[0] - vals[1]) / (2 * hstep)
+            ref = g["grad_b"][r, j]
+        # FD error model: FP32 rounding of U (~ U * 2^-23 / h) plus truncation O(h^2)
+        U = float(g["U"][r])
+        tol = 4 * U * 2.0 ** -23 / hstep + 1e-2 * abs(ref) + 1e-6
+        assert abs(fd - ref) <= tol, (fd, ref, tol)
+
+
+def test_config5_sampled_parity():
+    """Paper-scale placement (721,800 constraints, 16 restarts): sampled constraints and
+    sampled gradient coordinates against the oracle, in the launch configuration of the
+    benchmark."""
+    print("config 5 sampled parity", flush=True)
+    p = W.make_config(5)
+    R = 16
+    a, b = W.initial_points(p, R, 5, 0)
+    kap = 0.1
+    h = fsmt.xbdd_compile(p)
+    ta, tb = T(a.T.copy()).t(), T(b.T.copy()).t()
+    ga = torch.zeros(p.n_bool, R, device=dev()).t()
+    gb = torch.zeros(p.n_real, R, device=dev()).t()
+    wt = T(np.ones(p.n_cons))
+    obj = torch.zeros(R, device=dev())
+    unsat = torch.zeros(R, p.n_cons, device=dev())
+    fsmt.cop_forward(h, ta, tb, kap, wt, obj, unsat)
+    fsmt.cop_backward(h, ta, tb, kap, wt, obj, ga, gb)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(p.n_cons, 3000, replace=False)).astype(np.int32)
+    o = oracle.objective(p, a, b, kap, grad=False, sel=sel)
+    assert_unsat(unsat.cpu().numpy()[:, sel], o["unsat"][:, sel])
+    # sampled coordinates: all constraints touching the variable give its exact partial
+    N = p.meta["n_rect"]
+    ii, jj = np.triu_indices(N, 1)
+    gga, ggb = ga.cpu().numpy(), gb.cpu().numpy()
+    for rect in rng.choice(N, 3, replace=False):
+        touch = np.nonzero((ii == rect) | (jj == rect))[0]
+        sel2 = np.concatenate([touch, [len(ii) + 2 * rect, len(ii) + 2 * rect + 1]]).astype(np.int32)
+        o2 = oracle.objective(p, a, b, kap, sel=sel2, per_constraint=False)
+        for r in range(R):
+            tol_a = 1e-5 * o2["absg_a"][r, rect] + 1e-9
+            assert abs(gga[r, rect] - o2["grad_a"][r, rect]) <= tol_a
+            for j in (rect, N + rect):
+                tol = 1e-5 * o2["absg_b"][r, j] + 4e-7 * o2["absg_b"][r, j] + 1e-9
+                assert abs(ggb[r, j] - o2["grad_b"][r, j]) <= tol, (r, j, ggb[r, j], o2["grad_b"][r, j])
+
+
+def test_argument_errors_launch_nothing():
+    p = W.make_config(1)
+    h = fsmt.xbdd_compile(p)
+    a, b = W.initial_points(p, 2, 1, 0)
+    ta, tb = T(a), T(b)
+    obj = torch.full((2,), 7.0, device=dev())
+    with pytest.raises(fsmt.FsmtError) as e:
+        fsmt.cop_forward(h, ta, tb[:, :-1], 1.0, T(np.ones(p.n_cons)), obj)
+    assert e.value.code == fsmt._abi.FSMT_EINVAL
+    with pytest.raises(fsmt.FsmtError):
+        fsmt.cop_forward(h, ta, tb, -1.0, T(np.ones(p.n_cons)), obj)
+    host = torch.zeros(2, p.n_bool)
+    with pytest.raises(fsmt.FsmtError):
+        fsmt.cop_forward(h, host, tb, 1.0, T(np.ones(p.n_cons)), obj)
+    torch.cuda.synchronize()
+    assert float(obj[0]) == 7.0
