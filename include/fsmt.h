@@ -82,12 +82,21 @@ typedef struct {
 
 #define FSMT_HOST_ONLY (-2)   /* compile_opts.device: keep tables on the host (inspection only) */
 
+/* Feasible set D of the projection (Methods, Def. "Projection", Prop. "qp"). */
+enum {
+    FSMT_PROJ_UNIT = 0,   /* box plus every unit atomic constraint (a constraint that is one atom
+                             literal, no Boolean): single-variable ones tighten the box, the
+                             others are half-spaces projected by Dykstra's algorithm (default) */
+    FSMT_PROJ_BOX = 1     /* the box [-1,1]^n x [real_lo, real_hi] only */
+};
+
 typedef struct {
     int32_t device;            /* HIP device that holds the tables (-1 = current device,
                                   FSMT_HOST_ONLY = no upload: only xbdd_info and
                                   xbdd_export_diagram accept such a handle) */
     int32_t max_nodes;         /* reject diagrams with more decision nodes (0 = 1024) */
-    int32_t reserved[6];
+    int32_t projection;        /* FSMT_PROJ_UNIT or FSMT_PROJ_BOX */
+    int32_t reserved[5];
 } fsmt_compile_opts;
 
 typedef struct {
@@ -99,6 +108,8 @@ typedef struct {
     int32_t n_positions;       /* constraint slots after padding each shape bucket to 64 */
     int64_t table_bytes;       /* device bytes of the compiled tables */
     int64_t atom_nnz;
+    int32_t n_box_units;       /* single-variable unit atoms folded into the box */
+    int32_t n_halfspaces;      /* multi-variable unit atoms kept as half-spaces of D */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at
@@ -173,10 +184,14 @@ fsmt_status cop_backward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double ka
                          int32_t flags, void *stream);
 
 /*
- * Projected gradient step (Methods, Eq. "pg1"/"pg2", Def. "Projection" with the feasible
- * set the box [-1,1]^n x [real_lo, real_hi]; the coordinate-wise clamp is the Euclidean
- * projection onto a box), in place on a and b:
- *   a <- clamp(a - eta_a grad_a), b <- clamp(b - eta_b grad_b),
+ * Projected gradient step (Methods, Eq. "pg1"/"pg2", Def. "Projection", Prop. "qp"), in
+ * place on a and b: a <- clamp(a - eta_a grad_a, -1, 1) (the Euclidean projection onto a
+ * box is the coordinate-wise clamp) and b <- proj_D(b - eta_b grad_b), where D is the box
+ * [real_lo, real_hi] tightened by single-variable unit atoms, intersected with the
+ * half-spaces q.b <= q0 - delta of multi-variable unit atoms (delta = 1e-6 (|q0| +
+ * sum_j |q_j| max(|lo_j|, |hi_j|)) keeps the rounded point on the satisfied side). The
+ * intersection is projected by Dykstra's alternating projections (at most 256 sweeps, until
+ * a sweep moves no coordinate by more than 1e-7 (1 + |b|));
  * and gmap_sq[r] = ||g||^2 of the gradient map g = ((a-a+)/eta_a, (b-b+)/eta_b)
  * (Eq. "grad_map", "critical"); gmap_sq may be NULL. grad_a / grad_b are zeroed after use
  * (so the next cop_backward can run with FSMT_ACCUMULATE). NaN inputs stay NaN.
@@ -199,6 +214,17 @@ fsmt_status round_and_check(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, int8_t
                             uint32_t *sat_bits, int32_t *n_unsat, int32_t *verdict,
                             void *stream);
 
+/*
+ * ERWA weight update of Alg. "CLS with Annealing" for level t = level (1-based) from the
+ * satisfied-constraint bits of round_and_check: for every constraint
+ * h = rho h + [c violated]; if t mod tau == 0: w *= gamma^h and h = 1; then, if normalize,
+ * w *= n_cons / sum(w) (keeps the weights finite; the minimizer is scale-invariant).
+ * sat_bits [R][ceil(n_cons/32)], w and hist [R][n_cons]: contiguous device arrays.
+ */
+fsmt_status erwa_update(const fsmt_xbdd *h, int32_t R, const uint32_t *sat_bits, float *w, float *hist,
+                        int32_t level, float rho, float gamma, int32_t tau, int32_t normalize,
+                        void *stream);
+
 /* ------------------------------------------------------------------ batched solver */
 
 /* Options of the annealed solver (Alg. "CLS with Annealing" around Alg. "FourierSMT"). */
@@ -211,18 +237,21 @@ typedef struct {
     float rho, gamma;         /* ERWA decay and scaling base */
     int32_t tau;              /* ERWA update period in levels */
     int32_t normalize;        /* renormalize weights to sum n_cons after each update */
-    int32_t stop_on_sat;      /* a restart stops once SAT; 0 = keep iterating (benchmarks) */
-    int32_t schedule;         /* 0 = automatic, 1 = persistent restart-per-workgroup,
-                                 2 = graph of grid-wide step kernels */
+    int32_t stop_on_sat;      /* 0 = keep iterating (fixed work, benchmarks); 1 = a restart stops
+                                 once its check passes; 2 = additionally every restart of the
+                                 same instance stops at its next level boundary */
+    int32_t schedule;         /* 0 = automatic, 1 = persistent restart-per-workgroup */
     int32_t reserved[5];
 } fsmt_solve_opts;
 
-/* Per-instance solver state, device memory owned by the caller ([R] rows each). */
+/* Per-instance solver state, device memory owned by the caller ([R] rows each). The
+ * counters level_done / steps_done and verdict are read at entry (a call resumes where the
+ * previous one stopped) and written at exit. */
 typedef struct {
     fsmt_view a, b;           /* [R][n_bool], [R][n_real] in/out (row stride >= cols, unit column stride) */
     float *w;                 /* [R][n_cons] in/out weights */
     float *hist;              /* [R][n_cons] in/out ERWA history h */
-    float *grad_a, *grad_b;   /* [R][n_bool], [R][n_real] scratch (same strides as a, b) */
+    float *grad_a, *grad_b;   /* unused by the persistent schedule (may be NULL) */
     uint32_t *sat_bits;       /* [R][ceil(n_cons/32)] out: last check */
     int32_t *n_unsat;         /* [R] out */
     int32_t *verdict;         /* [R] out: 1 = SAT found (state a, b holds the assignment) */
@@ -233,11 +262,16 @@ typedef struct {
 
 /*
  * Run the annealed PGD solver for n_inst instances at once, each with its own R restarts,
- * fusing forward, reverse sweep, projection, check and ERWA on the device. For every
- * level kappa_t: up to steps_per_level PGD steps (stopping early at ||g||^2 <= eps^2),
- * then rounding + exact check and the ERWA update (h = rho h + [violated]; every tau
- * levels w *= gamma^h, h = 1, optional renormalization). A restart whose check reports
- * no violated constraint is SAT (Thm. "Soundness"). Asynchronous on the stream.
+ * fusing forward, reverse sweep, projection, check and ERWA on the device in one
+ * persistent launch (one workgroup per restart; its state, gradient and projection work
+ * arrays stay in LDS). For every level t from level_done[r] to n_levels-1 with
+ * kappa_t = kappas[t]: up to steps_per_level PGD steps (stopping early once
+ * ||g||^2 <= eps^2), then rounding + exact check and the ERWA update of Alg. "CLS with
+ * Annealing" (h = rho h + [violated]; every tau levels w *= gamma^h, h = 1, then optional
+ * renormalization of w to sum n_cons). A restart whose check reports no violated
+ * constraint is SAT (Thm. "Soundness"). Asynchronous on the stream. Errors:
+ * FSMT_EUNSUPPORTED when a restart's state does not fit in LDS, FSMT_ELIMIT for more than
+ * 128 levels, FSMT_EINVAL for bad shapes or options.
  */
 fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst,
                                const fsmt_solve_opts *opts, const fsmt_solve_state *states,

@@ -51,8 +51,8 @@ def lib():
         vp, i32, dbl = ct.c_void_p, ct.c_int, ct.c_double
         L.oracle_objective.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.oracle_check.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
-        L.oracle_pgd.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp]
-        L.oracle_pgd.restype = None
+        L.oracle_pgd.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, i32, vp, vp, vp]
+        L.oracle_project.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
         L.oracle_erwa.argtypes = [i32, i32, vp, i32, dbl, dbl, i32, i32, vp, vp]
         L.oracle_erwa.restype = None
         L.oracle_cop_enum.argtypes = [vp, i32, vp, vp, vp]
@@ -149,15 +149,26 @@ def check(prob, a, b):
     return dict(x=x, sat_bits=bits[:, :nw], n_unsat=nu, verdict=ver)
 
 
-def pgd(prob, a, b, ga, gb, eta_a: float, eta_b: float):
+def pgd(prob, a, b, ga, gb, eta_a: float, eta_b: float, unit_proj: bool = True):
+    """Projected step (clamp a; project b onto the box and, with unit_proj, the unit atoms)."""
     op = _as(prob)
     a = _f32(a, (-1, op.n))
     R = a.shape[0]
     b, ga, gb = _f32(b, (R, op.m)), _f32(ga, (R, op.n)), _f32(gb, (R, op.m))
     ao, bo, gsq = np.zeros((R, op.n)), np.zeros((R, op.m)), np.zeros(R)
-    lib().oracle_pgd(R, op.n, op.m, _p(a), _p(b), _p(ga), _p(gb), float(eta_a), float(eta_b),
-                     _p(op.lo), _p(op.hi), _p(ao), _p(bo), _p(gsq))
-    return dict(a=ao, b=bo, gsq=gsq)
+    nh = lib().oracle_pgd(op.ref, R, _p(a), _p(b), _p(ga), _p(gb), float(eta_a), float(eta_b),
+                          _p(op.lo), _p(op.hi), int(bool(unit_proj)), _p(ao), _p(bo), _p(gsq))
+    return dict(a=ao, b=bo, gsq=gsq, n_halfspaces=nh)
+
+
+def project(prob, y, unit_proj: bool = True):
+    """Euclidean projection of one real point onto the feasible set D; returns (y, lo, hi)."""
+    op = _as(prob)
+    yi = np.ascontiguousarray(np.asarray(y, np.float64).reshape(op.m))
+    yo, lo, hi = np.zeros(op.m), np.zeros(op.m), np.zeros(op.m)
+    nh = lib().oracle_project(op.ref, _p(yi), _p(op.lo), _p(op.hi), int(bool(unit_proj)), _p(yo),
+                              _p(lo), _p(hi))
+    return yo, lo, hi, nh
 
 
 def erwa(sat_bits, n_cons: int, t: int, h, w, rho=0.5, gamma=2.0, tau=1, normalize=True):
@@ -217,7 +228,7 @@ def variable_probs(prob, a, b, kappa: float) -> np.ndarray:
 
 
 def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float = 1e-2,
-           rho=0.5, gamma=2.0, tau=1, normalize=True, w0=None):
+           rho=0.5, gamma=2.0, tau=1, normalize=True, w0=None, unit_proj=True):
     """Alg. "CLS with Annealing" literally, with the PGD of Alg. "FourierSMT" inside.
 
     Per level t (kappa_t): up to ``steps_per_level`` projected-gradient steps on U (stop
@@ -237,7 +248,7 @@ def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float 
         for _ in range(steps_per_level):
             o = objective(op, a, b, kap, w=w, per_constraint=False)
             st = pgd(op, a, b, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32),
-                     eta_a, eta_b)
+                     eta_a, eta_b, unit_proj)
             a = np.where(done[:, None], a, st["a"].astype(np.float32))
             b = np.where(done[:, None], b, st["b"].astype(np.float32))
             if np.all((st["gsq"] <= eps * eps) | done):

@@ -522,13 +522,116 @@ int oracle_check(const oproblem *P, int R, const float *a, const float *b, int8_
     return ORC_OK;
 }
 
-/* Projected gradient step onto the box [-1,1]^n x [lo,hi] (coordinate-wise clamp is the
- * Euclidean projection onto a box), gradient map norm ||g||^2 per point. Comparisons keep
- * NaN as NaN. */
-void oracle_pgd(int R, int n, int m, const float *a, const float *b, const float *ga,
-                const float *gb, double eta_a, double eta_b, const double *lo, const double *hi,
-                double *a_out, double *b_out, double *gsq)
+/* Feasible set of the projection (Def. "Projection", Prop. "qp"): the box [-1,1]^n x
+ * [lo, hi] and, when unit_proj is set, every unit atomic constraint (a constraint that is a
+ * single atom literal, no propositional variable) as the closed half-space it asks for. A
+ * half-space is shifted inward by delta = 1e-6 (|q0| + sum_j |q_j| max(|lo_j|, |hi_j|)) so
+ * that its projected point satisfies the atom after rounding to float32; single-variable
+ * ones are plain bounds and get no shift. Returns the number of half-spaces found. */
+typedef struct { int n; int *ptr; int *var; double *coef; double *rhs; double *inv; } ohs;
+
+static void find_units(const oproblem *P, const double *lo0, const double *hi0, double *lo, double *hi, ohs *H)
 {
+    int n = P->n_bool;
+    H->n = 0;
+    H->ptr = (int *)malloc(sizeof(int) * (size_t)(P->n_cons + 1));
+    int64_t cap = P->atom_ptr[P->n_atoms] + 1;
+    H->var = (int *)malloc(sizeof(int) * (size_t)cap);
+    H->coef = (double *)malloc(sizeof(double) * (size_t)cap);
+    H->rhs = (double *)malloc(sizeof(double) * (size_t)(P->n_cons + 1));
+    H->inv = (double *)malloc(sizeof(double) * (size_t)(P->n_cons + 1));
+    H->ptr[0] = 0;
+    for (int j = 0; j < P->n_real; ++j) { lo[j] = lo0[j]; hi[j] = hi0[j]; }
+    for (int c = 0; c < P->n_cons; ++c) {
+        if (P->con_kind[c] != K_CLAUSE && P->con_kind[c] != K_AND) continue;
+        if (P->con_ptr[c + 1] - P->con_ptr[c] != 1) continue;
+        int lit = P->con_lit[P->con_ptr[c]];
+        if ((lit >> 1) < n) continue;
+        int k = (lit >> 1) - n;
+        int op = P->atom_op[k];
+        /* the constraint asks q.y <= q0 (or its strict / reversed / negated variant):
+         * write the closed half-space as s q.y <= s q0 */
+        double s = (op == O_GE || op == O_GT) ? -1.0 : 1.0;
+        if (lit & 1) s = -s;
+        int64_t e0 = P->atom_ptr[k], e1 = P->atom_ptr[k + 1];
+        if (e1 - e0 == 1) {
+            int j = P->atom_var[e0];
+            double q = s * P->atom_coef[e0], bnd = s * P->atom_rhs[k] / q;
+            double nlo = lo[j], nhi = hi[j];
+            if (q > 0) { if (bnd < nhi) nhi = bnd; } else { if (bnd > nlo) nlo = bnd; }
+            if (nlo <= nhi) { lo[j] = nlo; hi[j] = nhi; }
+            continue;
+        }
+        int t = H->n, base = H->ptr[t];
+        double scale = fabs(P->atom_rhs[k]), q2 = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            int j = P->atom_var[e];
+            double m = fabs(lo0[j]) > fabs(hi0[j]) ? fabs(lo0[j]) : fabs(hi0[j]);
+            scale += fabs(P->atom_coef[e]) * m;
+            H->var[base + (e - e0)] = j;
+            H->coef[base + (e - e0)] = s * P->atom_coef[e];
+            q2 += P->atom_coef[e] * P->atom_coef[e];
+        }
+        H->rhs[t] = s * P->atom_rhs[k] - 1e-6 * scale;
+        H->inv[t] = 1.0 / q2;
+        H->ptr[t + 1] = base + (int)(e1 - e0);
+        H->n = t + 1;
+    }
+}
+
+static void free_units(ohs *H) { free(H->ptr); free(H->var); free(H->coef); free(H->rhs); free(H->inv); }
+
+/* Euclidean projection of y onto box x half-spaces by Dykstra's alternating projections,
+ * iterated until a whole sweep moves nothing by more than 1e-13 (1 + |y|). */
+static void dykstra(double *y, int m, const double *lo, const double *hi, const ohs *H)
+{
+    if (H->n == 0) {
+        for (int j = 0; j < m; ++j) y[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
+        return;
+    }
+    double *pb = (double *)calloc((size_t)m + 1, sizeof(double));
+    double *ph = (double *)calloc((size_t)H->ptr[H->n] + 1, sizeof(double));
+    for (int sweep = 0; sweep < 1000000; ++sweep) {
+        int moved = 0;
+        for (int t = 0; t < H->n; ++t) {
+            double viol = -H->rhs[t];
+            for (int e = H->ptr[t]; e < H->ptr[t + 1]; ++e) viol += H->coef[e] * (y[H->var[e]] + ph[e]);
+            double sh = viol > 0.0 ? viol * H->inv[t] : 0.0;
+            for (int e = H->ptr[t]; e < H->ptr[t + 1]; ++e) {
+                int j = H->var[e];
+                double z = y[j] + ph[e], yp = z - sh * H->coef[e];
+                if (fabs(yp - y[j]) > 1e-13 * (1.0 + fabs(yp))) moved = 1;
+                ph[e] = z - yp;
+                y[j] = yp;
+            }
+        }
+        for (int j = 0; j < m; ++j) {
+            double z = y[j] + pb[j], yp = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);
+            if (fabs(yp - y[j]) > 1e-13 * (1.0 + fabs(yp))) moved = 1;
+            pb[j] = z - yp;
+            y[j] = yp;
+        }
+        if (!moved) break;
+    }
+    free(pb);
+    free(ph);
+}
+
+/* Projected gradient step (Eq. "pg1"/"pg2") and the gradient map norm ||g||^2
+ * (Eq. "grad_map") per point. Comparisons keep NaN as NaN in the clamp. */
+int oracle_pgd(const oproblem *P, int R, const float *a, const float *b, const float *ga,
+               const float *gb, double eta_a, double eta_b, const double *lo0, const double *hi0,
+               int unit_proj, double *a_out, double *b_out, double *gsq)
+{
+    int n = P->n_bool, m = P->n_real;
+    double *lo = (double *)malloc(sizeof(double) * ((size_t)m + 1));
+    double *hi = (double *)malloc(sizeof(double) * ((size_t)m + 1));
+    ohs H = {0, 0, 0, 0, 0, 0};
+    if (unit_proj) {
+        find_units(P, lo0, hi0, lo, hi, &H);
+    } else {
+        for (int j = 0; j < m; ++j) { lo[j] = lo0[j]; hi[j] = hi0[j]; }
+    }
     for (int r = 0; r < R; ++r) {
         double acc = 0.0;
         for (int i = 0; i < n; ++i) {
@@ -539,16 +642,38 @@ void oracle_pgd(int R, int n, int m, const float *a, const float *b, const float
             double g = (x - p) / eta_a;
             acc += g * g;
         }
+        double *y = b_out + (size_t)r * m;
+        for (int j = 0; j < m; ++j) y[j] = (double)b[(size_t)r * m + j] - eta_b * (double)gb[(size_t)r * m + j];
+        dykstra(y, m, lo, hi, &H);
         for (int j = 0; j < m; ++j) {
-            double x = (double)b[(size_t)r * m + j];
-            double y = x - eta_b * (double)gb[(size_t)r * m + j];
-            double p = y < lo[j] ? lo[j] : (y > hi[j] ? hi[j] : y);
-            b_out[(size_t)r * m + j] = p;
-            double g = (x - p) / eta_b;
+            double g = ((double)b[(size_t)r * m + j] - y[j]) / eta_b;
             acc += g * g;
         }
         gsq[r] = acc;
     }
+    int nh = H.n;
+    if (unit_proj) free_units(&H);
+    free(lo);
+    free(hi);
+    return nh;
+}
+
+/* Projection of one point onto D alone (for pinning the projection). */
+int oracle_project(const oproblem *P, const double *y_in, const double *lo0, const double *hi0,
+                   int unit_proj, double *y_out, double *lo_out, double *hi_out)
+{
+    int m = P->n_real;
+    ohs H = {0, 0, 0, 0, 0, 0};
+    if (unit_proj) {
+        find_units(P, lo0, hi0, lo_out, hi_out, &H);
+    } else {
+        for (int j = 0; j < m; ++j) { lo_out[j] = lo0[j]; hi_out[j] = hi0[j]; }
+    }
+    for (int j = 0; j < m; ++j) y_out[j] = y_in[j];
+    dykstra(y_out, m, lo_out, hi_out, &H);
+    int nh = H.n;
+    if (unit_proj) free_units(&H);
+    return nh;
 }
 
 /* ERWA update of Alg. "CLS with Annealing" for one sigma-level t (1-based):

@@ -13,10 +13,10 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import FSMT_ACCUMULATE, FSMT_HOST_ONLY, FsmtError  # noqa: F401
+from ._abi import FSMT_ACCUMULATE, FSMT_HOST_ONLY, FSMT_PROJ_BOX, FSMT_PROJ_UNIT, FsmtError  # noqa: F401
 
 __all__ = ["XBDD", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram", "cop_forward",
-           "cop_backward", "pgd_step", "round_and_check", "fsmt_solve_batched", "FsmtError",
+           "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "FsmtError",
            "FSMT_ACCUMULATE", "FSMT_HOST_ONLY", "view", "lib"]
 
 
@@ -59,10 +59,12 @@ class XBDD:
             pass
 
 
-def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0) -> XBDD:
+def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0,
+                 projection: int = 0) -> XBDD:
     """Compile a problem (object with the ``workloads.format.Problem`` arrays).
 
     ``device``: HIP device index, None for the current one, or FSMT_HOST_ONLY.
+    ``projection``: FSMT_PROJ_UNIT (box + unit atoms, default) or FSMT_PROJ_BOX.
     """
     keep = {}
     s = _abi.Problem()
@@ -77,6 +79,7 @@ def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0) -> X
     o = _abi.CompileOpts()
     o.device = -1 if device is None else int(device)
     o.max_nodes = int(max_nodes)
+    o.projection = int(projection)
     out = ct.c_void_p()
     _abi.check(lib().xbdd_compile(ct.byref(s), ct.byref(o), ct.byref(out)))
     return XBDD(out.value, problem)
@@ -155,6 +158,13 @@ def pgd_step(h: XBDD, a, b, grad_a, grad_b, eta_a: float, eta_b: float, gmap_sq=
 def round_and_check(h: XBDD, a, b, x, sat_bits, n_unsat, verdict, stream=None):
     _abi.check(lib().round_and_check(h.handle, view(a), view(b), _ptr(x), _ptr(sat_bits),
                                      _ptr(n_unsat), _ptr(verdict), _stream(stream)))
+
+
+def erwa_update(h: XBDD, R: int, sat_bits, w, hist, level: int, rho: float = 0.5,
+                gamma: float = 2.0, tau: int = 1, normalize: bool = True, stream=None):
+    _abi.check(lib().erwa_update(h.handle, int(R), _ptr(sat_bits), _ptr(w), _ptr(hist), int(level),
+                                 float(rho), float(gamma), int(tau), int(bool(normalize)),
+                                 _stream(stream)))
 
 
 def fsmt_solve_batched(handles, opts: _abi.SolveOpts, states, stream=None):

@@ -9,10 +9,12 @@ LIB_PATH = os.path.join(HERE, "libfsmt.so")
 
 FSMT_OK, FSMT_EINVAL, FSMT_ENOMEM, FSMT_EUNSUPPORTED, FSMT_ELIMIT, FSMT_EHIP = 0, -1, -2, -3, -4, -5
 FSMT_HOST_ONLY = -2
+FSMT_PROJ_UNIT, FSMT_PROJ_BOX = 0, 1
 FSMT_ACCUMULATE = 1
 
 EXPORTED = ["fsmt_last_error", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram",
-            "cop_forward", "cop_backward", "pgd_step", "round_and_check", "fsmt_solve_batched"]
+            "cop_forward", "cop_backward", "pgd_step", "round_and_check", "erwa_update",
+            "fsmt_solve_batched"]
 
 
 class Problem(ct.Structure):
@@ -24,14 +26,16 @@ class Problem(ct.Structure):
 
 
 class CompileOpts(ct.Structure):
-    _fields_ = [("device", ct.c_int32), ("max_nodes", ct.c_int32), ("reserved", ct.c_int32 * 6)]
+    _fields_ = [("device", ct.c_int32), ("max_nodes", ct.c_int32), ("projection", ct.c_int32),
+                ("reserved", ct.c_int32 * 5)]
 
 
 class Stats(ct.Structure):
     _fields_ = [("n_bool", ct.c_int32), ("n_real", ct.c_int32), ("n_atoms", ct.c_int32),
                 ("n_cons", ct.c_int32), ("total_nodes", ct.c_int64), ("n_templates", ct.c_int32),
                 ("max_nodes", ct.c_int32), ("max_slots", ct.c_int32), ("n_positions", ct.c_int32),
-                ("table_bytes", ct.c_int64), ("atom_nnz", ct.c_int64)]
+                ("table_bytes", ct.c_int64), ("atom_nnz", ct.c_int64), ("n_box_units", ct.c_int32),
+                ("n_halfspaces", ct.c_int32)]
 
 
 class View(ct.Structure):
@@ -84,6 +88,8 @@ def load() -> ct.CDLL:
     L.pgd_step.restype = i32
     L.round_and_check.argtypes = [vp, View, View, vp, vp, vp, vp, vp]
     L.round_and_check.restype = i32
+    L.erwa_update.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, i32, i32, vp]
+    L.erwa_update.restype = i32
     L.fsmt_solve_batched.argtypes = [vp, i32, ct.POINTER(SolveOpts), vp, vp]
     L.fsmt_solve_batched.restype = i32
     _lib = L

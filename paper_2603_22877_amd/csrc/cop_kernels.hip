@@ -25,45 +25,20 @@
 #include <cstdio>
 
 #include "fsmt_internal.hpp"
-#include "kernels_common.hpp"
+#include "eval_task.hpp"
 
 namespace fsmt {
 
 struct CopArgs {
-    const TplInfo *tpl;
-    const Node *nodes;
-    const BucketInfo *bucket;
-    const int32_t *bucket_start;
-    int32_t n_buckets;
-    int32_t n_pos;
-    const int32_t *pos_con;
-    const int32_t *sup;
-    const int32_t *atom_ptr;
-    const int32_t *atom_var;
-    const double *atom_coef;
-    const double *atom_rhs;
-    const double *atom_scale;
-    const uint8_t *atom_strict;
-    int32_t n_bool;
+    TabView T;
     int32_t R, R_pad, log2_rpad;   // log2_rpad valid for R_pad <= 64
     int64_t n_tasks;
     View a, b, w, unsat, ga, gb;
     float *obj;
     double kappa;
     int32_t hard;
-    int32_t do_grad;
     int32_t lds_nodes, lds_slots;  // per-wave LDS geometry (max over templates)
 };
-
-// Find the bucket containing position pos (uniform across the wave).
-__device__ __forceinline__ int find_bucket(const int32_t *start, int nb, int pos) {
-    int lo = 0, hi = nb - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (__builtin_amdgcn_readfirstlane(start[mid]) <= pos) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <bool kGrad>
 __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
@@ -74,82 +49,27 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     const int64_t wave0 = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
     const int NN = A.lds_nodes + 2, SS = A.lds_slots;
-    float *M = lds + (size_t)wib * (2 * NN + 4 * SS) * 64;
-    float *Bm = M + NN * 64;
-    float *Pp = Bm + NN * 64;
-    float *Qp = Pp + SS * 64;
-    float *Dp = Qp + SS * 64;
-    float *Gp = Dp + SS * 64;
+    const WaveScratch W = WaveScratch::at(lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS);
+    const GlobalState st{A.a, A.b};
+    const GlobalScatter sc{A.ga, A.gb};
 
     for (int64_t task = wave0; task < A.n_tasks; task += n_waves) {
         int pos, r;
         if (A.R_pad <= 64) {
-            const int cpw = 64 >> A.log2_rpad;
-            pos = (int)(task * cpw) + (lane >> A.log2_rpad);
+            pos = (int)(task * (64 >> A.log2_rpad)) + (lane >> A.log2_rpad);
             r = lane & (A.R_pad - 1);
         } else {
             const int wpc = A.R_pad >> 6;
             pos = (int)(task / wpc);
             r = (int)(task % wpc) * 64 + lane;
         }
-        const int pos0 = __builtin_amdgcn_readfirstlane(pos);
-        const int bk = find_bucket(A.bucket_start, A.n_buckets, pos0);
-        const BucketInfo B = A.bucket[bk];
-        const TplInfo T = A.tpl[B.tpl];
-        const int N = T.n_nodes, S = T.n_slots, NB = T.n_bslots;
-        const int local = pos - B.pos_begin;
-        const int c = A.pos_con[pos];
-        const bool valid = (c >= 0) && (r < A.R);
-        const int32_t *sup = A.sup + B.sup_base + local;
-
-        // ---- literal probabilities (Eq. "rounding", Eq. "sampling")
-        for (int s = 0; s < NB; ++s) {
-            const int id = valid ? sup[(int64_t)s * B.n_pos] : 0;
-            const float av = valid ? A.a.at(r, id) : 0.0f;
-            Pp[s * 64 + lane] = (1.0f - av) * 0.5f;
-            Qp[s * 64 + lane] = (1.0f + av) * 0.5f;
-        }
-        for (int s = NB; s < S; ++s) {
-            float p = 0.5f, q = 0.5f, d = 0.0f;
-            if (valid) {
-                const int k = sup[(int64_t)s * B.n_pos] - A.n_bool;
-                const double z = atom_z_exact(A.atom_ptr, A.atom_var, A.atom_coef, A.atom_rhs, k, A.b, r);
-                if (A.hard) {
-                    const bool t = A.atom_strict[k] ? (z < 0.0) : (z <= 0.0);
-                    p = t ? 1.0f : 0.0f;
-                    q = t ? 0.0f : 1.0f;
-                } else {
-                    const double ks = A.kappa * A.atom_scale[k];
-                    const float u = (float)(z * ks);
-                    const float e = 0.5f * erfcf(fabsf(u));     // the smaller of p, 1-p
-                    p = (u >= 0.0f) ? e : 1.0f - e;
-                    q = (u >= 0.0f) ? 1.0f - e : e;
-                    if (u != u) { p = u; q = u; }              // NaN in, NaN out
-                    d = -(float)(ks * 0.56418958354775628695) * expf(-u * u);   // dp/dz
-                }
-            }
-            Pp[s * 64 + lane] = p;
-            Qp[s * 64 + lane] = q;
-            Dp[s * 64 + lane] = d;
-        }
-
-        // ---- forward: top-down path masses
-        for (int v = 0; v < N + 2; ++v) M[v * 64 + lane] = 0.0f;
-        M[T.root * 64 + lane] = 1.0f;
-        const Node *nd = A.nodes + T.node_off;
-        for (int v = 0; v < N; ++v) {
-            const Node x = load_node(nd + v);
-            const float mv = M[v * 64 + lane];
-            M[x.hi * 64 + lane] += Pp[x.slot * 64 + lane] * mv;
-            M[x.lo * 64 + lane] += Qp[x.slot * 64 + lane] * mv;
-        }
-        const float unsat = M[(N + 1) * 64 + lane];
-        const float wc = valid ? A.w.at(r, c) : 0.0f;
-        if (valid && A.unsat.data) A.unsat.at(r, c) = unsat;
-
+        const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
+        const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W, lane);
+        const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;
+        if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         // objective: reduce lanes holding the same restart, then one atomic per restart
         if (A.obj) {
-            float contrib = valid ? wc * unsat : 0.0f;
+            float contrib = wc * unsat;
             if (A.R_pad < 64) {
                 for (int off = 32; off >= A.R_pad; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
                 if (lane < A.R_pad && r < A.R) atomic_add_f32(A.obj + r, contrib);
@@ -157,32 +77,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
                 atomic_add_f32(A.obj + r, contrib);
             }
         }
-        if (!kGrad) continue;
-
-        // ---- backward: bottom-up false-reaching masses and slot sensitivities
-        for (int s = 0; s < S; ++s) Gp[s * 64 + lane] = 0.0f;
-        Bm[N * 64 + lane] = 0.0f;
-        Bm[(N + 1) * 64 + lane] = 1.0f;
-        for (int v = N - 1; v >= 0; --v) {
-            const Node x = load_node(nd + v);
-            const float bh = Bm[x.hi * 64 + lane], bl = Bm[x.lo * 64 + lane];
-            Bm[v * 64 + lane] = Pp[x.slot * 64 + lane] * bh + Qp[x.slot * 64 + lane] * bl;
-            Gp[x.slot * 64 + lane] += M[v * 64 + lane] * (bh - bl);
-        }
-        // ---- chain rule and scatter
-        if (valid) {
-            for (int s = 0; s < NB; ++s) {
-                const float g = wc * Gp[s * 64 + lane] * -0.5f;
-                if (g != 0.0f) atomic_add_f32(&A.ga.at(r, sup[(int64_t)s * B.n_pos]), g);
-            }
-            for (int s = NB; s < S; ++s) {
-                const float gz = wc * Gp[s * 64 + lane] * Dp[s * 64 + lane];
-                if (gz == 0.0f) continue;
-                const int k = sup[(int64_t)s * B.n_pos] - A.n_bool;
-                for (int e = A.atom_ptr[k]; e < A.atom_ptr[k + 1]; ++e)
-                    atomic_add_f32(&A.gb.at(r, A.atom_var[e]), gz * (float)A.atom_coef[e]);
-            }
-        }
+        if (kGrad) task_backward(A.T, t, wc, sc, W, lane);
     }
 }
 
@@ -203,9 +98,11 @@ __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = value;
 }
 
-// One block per restart: clamp step, gradient-map norm, zero the gradient.
+// One block per restart: clamp / project step, gradient-map norm, zero the gradient.
 __global__ void __launch_bounds__(256) pgd_kernel(View a, View b, View ga, View gb, const float *lo,
-                                                  const float *hi, float eta_a, float eta_b, float *gsq) {
+                                                  const float *hi, float eta_a, float eta_b, float *gsq,
+                                                  HalfSpaces hs) {
+    extern __shared__ float sm[];
     const int r = blockIdx.x;
     float acc = 0.0f;
     for (int i = threadIdx.x; i < a.cols; i += blockDim.x) {
@@ -217,28 +114,38 @@ __global__ void __launch_bounds__(256) pgd_kernel(View a, View b, View ga, View 
         acc += g * g;
         ga.at(r, i) = 0.0f;
     }
-    for (int j = threadIdx.x; j < b.cols; j += blockDim.x) {
-        const float x = b.at(r, j);
-        const float y = x - eta_b * gb.at(r, j);
-        const float p = y < lo[j] ? lo[j] : (y > hi[j] ? hi[j] : y);
-        b.at(r, j) = p;
-        const float g = (x - p) / eta_b;
-        acc += g * g;
-        gb.at(r, j) = 0.0f;
+    if (hs.n == 0) {
+        for (int j = threadIdx.x; j < b.cols; j += blockDim.x) {
+            const float x = b.at(r, j);
+            const float y = x - eta_b * gb.at(r, j);
+            const float p = y < lo[j] ? lo[j] : (y > hi[j] ? hi[j] : y);
+            b.at(r, j) = p;
+            const float g = (x - p) / eta_b;
+            acc += g * g;
+            gb.at(r, j) = 0.0f;
+        }
+    } else {
+        const int m = b.cols;
+        float *y = sm, *pb = sm + m, *ph = sm + 2 * m;
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            y[j] = b.at(r, j) - eta_b * gb.at(r, j);
+            gb.at(r, j) = 0.0f;
+        }
+        project_dykstra(y, pb, ph, lo, hi, m, hs);
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const float x = b.at(r, j), p = y[j];
+            b.at(r, j) = p;
+            const float g = (x - p) / eta_b;
+            acc += g * g;
+        }
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0 && gsq) gsq[r] = acc;
 }
 
 struct CheckArgs {
-    const TplInfo *tpl;
-    const Node *nodes;
-    const BucketInfo *bucket;
-    const int32_t *con_bucket, *con_local, *sup;
-    const int32_t *atom_ptr, *atom_var;
-    const double *atom_coef, *atom_rhs;
-    const uint8_t *atom_strict;
-    int32_t n_bool, n_cons, n_words;
+    TabView T;
+    int32_t n_words;
     View a, b;
     uint32_t *sat_bits;
     int32_t *n_unsat;
@@ -247,21 +154,45 @@ struct CheckArgs {
 // grid.x over 64-constraint groups (one wave each), grid.y over restarts.
 __global__ void __launch_bounds__(256) check_kernel(CheckArgs A) {
     const int lane = threadIdx.x & 63;
-    const int64_t c64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const int64_t c64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    const int c = (int)c64;
+    const GlobalState st{A.a, A.b};
     bool sat = false;
-    if (c64 < A.n_cons) sat = walk_exact(A.tpl, A.nodes, A.bucket, A.con_bucket, A.con_local, A.sup, A.atom_ptr,
-                                         A.atom_var, A.atom_coef, A.atom_rhs, A.atom_strict, A.n_bool, A.a, A.b,
-                                         c, r);
+    if (c64 < A.T.n_cons) sat = walk_state(A.T, st, (int)c64, r);
     const uint64_t mask = __ballot(sat);
-    const uint64_t valid = __ballot(c64 < A.n_cons);
+    const uint64_t valid = __ballot(c64 < A.T.n_cons);
     if (lane == 0 && valid) {
-        const int64_t w0 = (c64 - 0) >> 5;   // c64 is a multiple of 64 on lane 0
+        const int64_t w0 = c64 >> 5;   // lane 0 holds a multiple of 64
         uint32_t *row = A.sat_bits + (int64_t)r * A.n_words;
         row[w0] = (uint32_t)mask;
         if (w0 + 1 < A.n_words) row[w0 + 1] = (uint32_t)(mask >> 32);
         atomicAdd(A.n_unsat + r, (int)__popcll(valid & ~mask));
+    }
+}
+
+// ERWA update of Alg. "CLS with Annealing" for level t (1-based), one block per restart.
+__global__ void __launch_bounds__(1024) erwa_kernel(int C, const uint32_t *bits, float *w, float *hist, int t, float rho,
+                                                    float gamma, int tau, int normalize) {
+    const int r = blockIdx.x, nw = (C + 31) >> 5;
+    const bool update = (t % tau) == 0;
+    float *wr = w + (int64_t)r * C, *hr = hist + (int64_t)r * C;
+    const uint32_t *br = bits + (int64_t)r * nw;
+    float ws = 0.0f;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const float viol = ((br[c >> 5] >> (c & 31)) & 1u) ? 0.0f : 1.0f;
+        float h = rho * hr[c] + viol, wv = wr[c];
+        if (update) {
+            wv *= powf(gamma, h);
+            h = 1.0f;
+            wr[c] = wv;
+        }
+        hr[c] = h;
+        ws += wv;
+    }
+    ws = block_sum(ws);
+    if (update && normalize) {
+        const float scale = (float)C / ws;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) wr[c] *= scale;
     }
 }
 
@@ -305,6 +236,10 @@ fsmt_status select_device(const fsmt_xbdd *h) {
     return FSMT_OK;
 }
 
+HalfSpaces halfspaces_of(const fsmt_xbdd *h) {
+    return HalfSpaces{h->d.hs_ptr, h->d.hs_var, h->d.hs_coef, h->d.hs_rhs, h->d.hs_inv, h->n_hs, h->hs_nnz};
+}
+
 static fsmt_status launch_status(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(FSMT_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -320,6 +255,12 @@ fsmt_status fill_view(const fsmt_view &v, float value, hipStream_t st) {
     if (!v.data || v.rows == 0 || v.cols == 0) return FSMT_OK;
     hipLaunchKernelGGL(fill_view_kernel, dim3(blocks_for((int64_t)v.rows * v.cols, 256)), dim3(256), 0, st,
                        View::of(v), value);
+    return launch_status("fill");
+}
+
+fsmt_status fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st) {
+    if (!p || n <= 0) return FSMT_OK;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, value);
     return launch_status("fill");
 }
 
@@ -367,21 +308,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     if (h->n_pos == 0) return FSMT_OK;
 
     CopArgs A{};
-    A.tpl = h->d.tpl;
-    A.nodes = h->d.nodes;
-    A.bucket = h->d.bucket;
-    A.bucket_start = h->d.bucket_start;
-    A.n_buckets = h->n_buckets;
-    A.n_pos = h->n_pos;
-    A.pos_con = h->d.pos_con;
-    A.sup = h->d.sup;
-    A.atom_ptr = h->d.atom_ptr;
-    A.atom_var = h->d.atom_var;
-    A.atom_coef = h->d.atom_coef;
-    A.atom_rhs = h->d.atom_rhs;
-    A.atom_scale = h->d.atom_scale;
-    A.atom_strict = h->d.atom_strict;
-    A.n_bool = h->n_bool;
+    A.T = TabView::of(h);
     A.R = R;
     if (R <= 64) {
         int rp = 1, lg = 0;
@@ -403,7 +330,6 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     A.obj = obj;
     A.kappa = kappa;
     A.hard = std::isinf(kappa) ? 1 : 0;
-    A.do_grad = grad ? 1 : 0;
     A.lds_nodes = h->max_nodes;
     A.lds_slots = SS;
     const int64_t max_waves = 256 * 32;
@@ -453,8 +379,11 @@ fsmt_status pgd_step(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, fsmt_view gra
     const char *names[] = {"a", "b", "grad_a", "grad_b", "gmap_sq"};
     for (int i = 0; i < 5; ++i)
         if ((rc = check_device_ptr(ptrs[i], h->device, names[i]))) return rc;
-    hipLaunchKernelGGL(pgd_kernel, dim3(R), dim3(256), 0, (hipStream_t)stream, View::of(a), View::of(b),
-                       View::of(grad_a), View::of(grad_b), h->d.real_lo, h->d.real_hi, eta_a, eta_b, gmap_sq);
+    const HalfSpaces hs = halfspaces_of(h);
+    const size_t lds = hs.n ? (size_t)(2 * h->n_real + hs.nnz) * sizeof(float) : 0;
+    if (lds > 65536) return set_error(FSMT_ELIMIT, "projection onto %d half-spaces over %d reals exceeds LDS", hs.n, h->n_real);
+    hipLaunchKernelGGL(pgd_kernel, dim3(R), dim3(256), lds, (hipStream_t)stream, View::of(a), View::of(b),
+                       View::of(grad_a), View::of(grad_b), h->d.real_lo, h->d.real_hi, eta_a, eta_b, gmap_sq, hs);
     return launch_status("pgd kernel");
 }
 
@@ -477,19 +406,7 @@ fsmt_status round_and_check(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, int8_t
     hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, st, n_unsat, (int64_t)R, 0);
     if ((rc = launch_status("fill"))) return rc;
     CheckArgs A{};
-    A.tpl = h->d.tpl;
-    A.nodes = h->d.nodes;
-    A.bucket = h->d.bucket;
-    A.con_bucket = h->d.con_bucket;
-    A.con_local = h->d.con_local;
-    A.sup = h->d.sup;
-    A.atom_ptr = h->d.atom_ptr;
-    A.atom_var = h->d.atom_var;
-    A.atom_coef = h->d.atom_coef;
-    A.atom_rhs = h->d.atom_rhs;
-    A.atom_strict = h->d.atom_strict;
-    A.n_bool = h->n_bool;
-    A.n_cons = h->n_cons;
+    A.T = TabView::of(h);
     A.n_words = (h->n_cons + 31) / 32;
     A.a = View::of(a);
     A.b = View::of(b);
@@ -502,6 +419,25 @@ fsmt_status round_and_check(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, int8_t
     }
     hipLaunchKernelGGL(verdict_kernel, dim3(R), dim3(256), 0, st, View::of(a), x, n_unsat, verdict);
     return launch_status("verdict kernel");
+}
+
+fsmt_status erwa_update(const fsmt_xbdd *h, int32_t R, const uint32_t *sat_bits, float *w, float *hist, int32_t level,
+                        float rho, float gamma, int32_t tau, int32_t normalize, void *stream) {
+    clear_error();
+    if (!h) return set_error(FSMT_EINVAL, "null handle");
+    if (R <= 0 || R > 65535) return set_error(FSMT_EINVAL, "R must be in [1, 65535]");
+    if (!sat_bits || !w || !hist) return set_error(FSMT_EINVAL, "null pointer");
+    if (tau < 1 || level < 1 || !(gamma > 0.0f) || !(rho >= 0.0f)) return set_error(FSMT_EINVAL, "bad ERWA parameters");
+    fsmt_status rc;
+    if ((rc = select_device(h))) return rc;
+    const void *ptrs[] = {sat_bits, w, hist};
+    const char *names[] = {"sat_bits", "w", "hist"};
+    for (int i = 0; i < 3; ++i)
+        if ((rc = check_device_ptr(ptrs[i], h->device, names[i]))) return rc;
+    if (h->n_cons == 0) return FSMT_OK;
+    hipLaunchKernelGGL(erwa_kernel, dim3(R), dim3(1024), 0, (hipStream_t)stream, h->n_cons, sat_bits, w, hist, level, rho,
+                       gamma, tau, normalize);
+    return launch_status("erwa kernel");
 }
 
 }  // extern "C"

@@ -58,8 +58,13 @@ struct DeviceTables {
     double *atom_rhs = nullptr;       // [A]   ("<=" form)
     double *atom_scale = nullptr;     // [A]   1/(sqrt(2)|q|)
     uint8_t *atom_strict = nullptr;   // [A]
-    float *real_lo = nullptr;         // [m]
+    float *real_lo = nullptr;         // [m] box of D (tightened by single-variable unit atoms)
     float *real_hi = nullptr;         // [m]
+    int32_t *hs_ptr = nullptr;        // [H+1] half-spaces of D: q.y <= rhs (multi-variable unit atoms)
+    int32_t *hs_var = nullptr;
+    float *hs_coef = nullptr;
+    float *hs_rhs = nullptr;          // [H] q0 - delta
+    float *hs_inv = nullptr;          // [H] 1 / |q|^2
 };
 
 }  // namespace fsmt
@@ -70,6 +75,7 @@ struct fsmt_xbdd {
     int n_tpl = 0, n_buckets = 0, n_pos = 0;
     int max_nodes = 0, max_slots = 0;
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
+    int n_box_units = 0, n_hs = 0, hs_nnz = 0;
     std::vector<fsmt::TplInfo> h_tpl;
     std::vector<fsmt::BucketInfo> h_bucket;
     std::vector<int32_t> h_bucket_start;

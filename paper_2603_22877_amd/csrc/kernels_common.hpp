@@ -30,48 +30,6 @@ __device__ __forceinline__ Node load_node(const Node *p) {
     return n;
 }
 
-// z = sum_j q_j y_j - q0 in FP64 from the float32 y, multiply then add in stored order, no
-// fused multiply-add: the exact atom test of the satisfaction check (and, at kappa = inf,
-// of the hard objective) is bit-identical for every evaluator that follows this order.
-__device__ __forceinline__ double atom_z_exact(const int32_t *ptr, const int32_t *var, const double *coef,
-                                               const double *rhs, int k, const View &b, int r) {
-#pragma clang fp contract(off)
-    double acc = 0.0;
-    const int e1 = ptr[k + 1];
-    for (int e = ptr[k]; e < e1; ++e) {
-        const double prod = coef[e] * (double)b.at(r, var[e]);
-        acc = acc + prod;
-    }
-    return acc - rhs[k];
-}
-
-// Deterministic walk of constraint c's diagram at the rounded point of restart r.
-__device__ __forceinline__ bool walk_exact(const TplInfo *tpl, const Node *nodes, const BucketInfo *bucket,
-                                           const int32_t *con_bucket, const int32_t *con_local, const int32_t *sup,
-                                           const int32_t *atom_ptr, const int32_t *atom_var, const double *atom_coef,
-                                           const double *atom_rhs, const uint8_t *atom_strict, int n_bool,
-                                           const View &a, const View &b, int c, int r) {
-    const BucketInfo B = bucket[con_bucket[c]];
-    const TplInfo T = tpl[B.tpl];
-    const int32_t *s = sup + B.sup_base + con_local[c];
-    const int N = T.n_nodes;
-    int v = T.root;
-    while (v < N) {
-        const Node x = nodes[T.node_off + v];
-        const int id = s[(int64_t)x.slot * B.n_pos];
-        bool t;
-        if (x.slot < T.n_bslots) {
-            t = a.at(r, id) < 0.0f;
-        } else {
-            const int k = id - n_bool;
-            const double z = atom_z_exact(atom_ptr, atom_var, atom_coef, atom_rhs, k, b, r);
-            t = atom_strict[k] ? (z < 0.0) : (z <= 0.0);
-        }
-        v = t ? x.hi : x.lo;
-    }
-    return v == N;
-}
-
 // Sum over a block of up to 1024 threads (result valid in every thread).
 __device__ __forceinline__ float block_sum(float v) {
     __shared__ float part[16];
@@ -86,9 +44,56 @@ __device__ __forceinline__ float block_sum(float v) {
     return t;
 }
 
+// Half-spaces q.y <= rhs of the feasible set (multi-variable unit atoms).
+struct HalfSpaces {
+    const int32_t *ptr, *var;
+    const float *coef, *rhs, *inv;
+    int32_t n, nnz;
+};
+
+// Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces, by
+// Dykstra's alternating projections (half-spaces in order, then the box, per sweep; the
+// increments pb[m], ph[nnz] live in LDS). All threads of the block must call it. Stops when a
+// sweep moves no coordinate by more than 4e-7 (1 + |y|), or after 256 sweeps.
+__device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, const float *lo, const float *hi,
+                                                int m, const HalfSpaces &hs) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = 0.0f;
+    for (int e = threadIdx.x; e < hs.nnz; e += blockDim.x) ph[e] = 0.0f;
+    __syncthreads();
+    for (int sweep = 0; sweep < 256; ++sweep) {
+        int moved = 0;
+        if (threadIdx.x == 0) {
+            for (int t = 0; t < hs.n; ++t) {
+                const int e0 = hs.ptr[t], e1 = hs.ptr[t + 1];
+                float viol = -hs.rhs[t];
+                for (int e = e0; e < e1; ++e) viol += hs.coef[e] * (y[hs.var[e]] + ph[e]);
+                const float sh = viol > 0.0f ? viol * hs.inv[t] : 0.0f;
+                for (int e = e0; e < e1; ++e) {
+                    const int j = hs.var[e];
+                    const float z = y[j] + ph[e], yp = z - sh * hs.coef[e];
+                    if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
+                    ph[e] = z - yp;
+                    y[j] = yp;
+                }
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const float z = y[j] + pb[j];
+            const float yp = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);
+            if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
+            pb[j] = z - yp;
+            y[j] = yp;
+        }
+        if (!__syncthreads_or(moved)) break;
+    }
+}
+
 fsmt_status fill_view(const fsmt_view &v, float value, hipStream_t st);
 fsmt_status fill_f32(float *p, int64_t n, float value, hipStream_t st);
+fsmt_status fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st);
 fsmt_status check_device_ptr(const void *p, int device, const char *name);
 fsmt_status select_device(const fsmt_xbdd *h);
+HalfSpaces halfspaces_of(const fsmt_xbdd *h);
 
 }  // namespace fsmt

@@ -1,10 +1,325 @@
-// Batched annealed solver (filled in below the per-call path).
+// Batched annealed solver (Alg. "CLS with Annealing" around the PGD loop of Alg.
+// "FourierSMT"), fused on the device.
+//
+// Persistent schedule: one workgroup per (instance, restart). The restart's relaxed state
+// (a, b), its gradient and the projection work arrays stay in LDS for the whole launch, so
+// the gradient scatter uses LDS atomics and no global atomic is issued. Per PGD step the
+// workgroup's waves sweep the instance's constraint buckets (lane = constraint, uniform
+// diagram shape per wave), then project (clamp a; box + unit atoms for b), and reduce the
+// gradient map norm. At the end of each level the workgroup rounds, checks every
+// constraint exactly, updates the ERWA history and weights of its restart (plain loads and
+// stores: the workgroup owns the row), and stops once no constraint is violated.
 #include <hip/hip_runtime.h>
 
-#include "fsmt_internal.hpp"
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "eval_task.hpp"
+
+namespace fsmt {
+
+constexpr int kMaxLevels = 128;
+
+struct InstDesc {
+    TabView T;
+    HalfSpaces hs;
+    float *a, *b;
+    int64_t a_sr, b_sr;
+    float *w, *hist;
+    uint32_t *sat_bits;
+    int32_t *n_unsat, *verdict, *level_done, *steps_done;
+    float *obj;
+    int32_t R, wg_base;
+};
+
+struct SolveParams {
+    int32_t n_inst, n_levels, steps, tau;
+    int32_t normalize, stop_mode, lds_nodes, lds_slots;
+    float eta_a, eta_b, eps2, rho, gamma;
+    int32_t state_floats;   // LDS floats reserved for state (max over instances)
+    int32_t waves;
+    int32_t pad;
+    double kappas[kMaxLevels];
+};
+
+__device__ __forceinline__ int find_inst(const InstDesc *I, int n, int wg) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__builtin_amdgcn_readfirstlane(I[mid].wg_base) <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ii = find_inst(insts, P.n_inst, blockIdx.x);
+    const InstDesc &I = insts[ii];
+    const TabView T = I.T;
+    const HalfSpaces hs = I.hs;
+    const int r = blockIdx.x - I.wg_base;
+    const int n = T.n_bool, m = T.n_real, C = T.n_cons;
+    const int nw = (C + 31) >> 5;
+    float *sa = lds, *sb = sa + n, *ga = sb + m, *gb = ga + n, *pb = gb + m, *ph = pb + m;
+    const int NN = P.lds_nodes + 2, SS = P.lds_slots;
+    const WaveScratch W = WaveScratch::at(lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS);
+    float *wrow = I.w + (int64_t)r * C, *hrow = I.hist + (int64_t)r * C;
+    uint32_t *brow = I.sat_bits + (int64_t)r * nw;
+
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sa[i] = I.a[(int64_t)r * I.a_sr + i];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) sb[j] = I.b[(int64_t)r * I.b_sr + j];
+    int level = I.level_done[r];
+    int steps_done = I.steps_done[r];
+    int verdict = I.verdict[r];
+    int n_unsat = I.n_unsat[r];
+    float obj = I.obj[r];
+    __syncthreads();
+    const LdsState st{sa, sb};
+    const LdsScatter sc{ga, gb};
+    const int n_tasks = T.n_pos >> 6;
+
+    while (level < P.n_levels && !(verdict == 1 && P.stop_mode != 0)) {
+        const double kappa = P.kappas[level];
+        const bool hard = isinf(kappa);
+        for (int k = 0; k < P.steps; ++k) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) ga[i] = 0.0f;
+            for (int j = threadIdx.x; j < m; j += blockDim.x) gb[j] = 0.0f;
+            __syncthreads();
+            float oacc = 0.0f;
+            for (int task = wave; task < n_tasks; task += P.waves) {
+                const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
+                const float unsat = task_forward(T, t, st, kappa, hard, W, lane);
+                const float wc = t.valid ? wrow[t.c] : 0.0f;
+                oacc += wc * unsat;
+                task_backward(T, t, wc, sc, W, lane);
+            }
+            __syncthreads();
+            obj = block_sum(oacc);
+            // projected step (Eq. pg1/pg2) and the gradient map norm (Eq. grad_map)
+            float acc = 0.0f;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const float x = sa[i], y = x - P.eta_a * ga[i];
+                const float p = y < -1.0f ? -1.0f : (y > 1.0f ? 1.0f : y);
+                sa[i] = p;
+                const float g = (x - p) / P.eta_a;
+                acc += g * g;
+            }
+            if (hs.n == 0) {
+                for (int j = threadIdx.x; j < m; j += blockDim.x) {
+                    const float x = sb[j], y = x - P.eta_b * gb[j];
+                    const float p = y < T.real_lo[j] ? T.real_lo[j] : (y > T.real_hi[j] ? T.real_hi[j] : y);
+                    sb[j] = p;
+                    const float g = (x - p) / P.eta_b;
+                    acc += g * g;
+                }
+            } else {
+                for (int j = threadIdx.x; j < m; j += blockDim.x) gb[j] = sb[j] - P.eta_b * gb[j];
+                project_dykstra(gb, pb, ph, T.real_lo, T.real_hi, m, hs);
+                for (int j = threadIdx.x; j < m; j += blockDim.x) {
+                    const float x = sb[j], p = gb[j];
+                    sb[j] = p;
+                    const float g = (x - p) / P.eta_b;
+                    acc += g * g;
+                }
+            }
+            const float gsq = block_sum(acc);
+            ++steps_done;
+            if (gsq <= P.eps2) break;
+        }
+        // rounding, exact check and ERWA (Alg. "CLS with Annealing")
+        const bool update = ((level + 1) % P.tau) == 0;
+        float nu_acc = 0.0f, wsum = 0.0f;
+        for (int c0 = wave * 64; c0 < C; c0 += P.waves * 64) {
+            const int c = c0 + lane;
+            const bool sat = c < C ? walk_state(T, st, c, r) : false;
+            const uint64_t mask = __ballot(sat);
+            if (lane == 0) {
+                brow[c0 >> 5] = (uint32_t)mask;
+                if ((c0 >> 5) + 1 < nw) brow[(c0 >> 5) + 1] = (uint32_t)(mask >> 32);
+            }
+            if (c < C) {
+                const float viol = sat ? 0.0f : 1.0f;
+                float h = P.rho * hrow[c] + viol;
+                float wv = wrow[c];
+                if (update) {
+                    wv *= powf(P.gamma, h);
+                    h = 1.0f;
+                    wrow[c] = wv;
+                }
+                hrow[c] = h;
+                wsum += wv;
+                nu_acc += viol;
+            }
+        }
+        n_unsat = (int)block_sum(nu_acc);
+        if (update && P.normalize) {
+            const float ws = block_sum(wsum);
+            const float scale = (float)C / ws;
+            for (int c = threadIdx.x; c < C; c += blockDim.x) wrow[c] *= scale;
+        }
+        ++level;
+        if (n_unsat == 0) {
+            verdict = 1;
+            if (P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
+        }
+        if (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) break;
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
+    if (threadIdx.x == 0) {
+        I.level_done[r] = level;
+        I.steps_done[r] = steps_done;
+        I.verdict[r] = verdict;
+        I.n_unsat[r] = n_unsat;
+        I.obj[r] = obj;
+    }
+}
+
+static fsmt_status launch_status(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(FSMT_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return FSMT_OK;
+}
+
+static int lds_budget_bytes() {
+    static int budget = -1;
+    if (budget < 0) {
+        budget = 65536;
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > budget)
+            budget = v;
+        if (budget > 65536 &&
+            hipFuncSetAttribute((const void *)solve_wg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
+            (void)hipGetLastError();
+            budget = 65536;
+        }
+    }
+    return budget;
+}
+
+static size_t state_floats_of(const fsmt_xbdd *h) {
+    size_t f = 2 * (size_t)h->n_bool + 2 * (size_t)h->n_real;
+    if (h->n_hs) f += (size_t)h->n_real + (size_t)h->hs_nnz;
+    return (f + 63) / 64 * 64;
+}
+
+}  // namespace fsmt
+
+using namespace fsmt;
 
 extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
                                           const fsmt_solve_state *states, void *stream) {
-    (void)insts; (void)n_inst; (void)opts; (void)states; (void)stream;
-    return fsmt::set_error(FSMT_EUNSUPPORTED, "batched solver not built yet");
+    clear_error();
+    if (!insts || !opts || !states || n_inst <= 0) return set_error(FSMT_EINVAL, "null argument or no instance");
+    const fsmt_solve_opts &O = *opts;
+    if (O.n_levels < 0 || O.n_levels > kMaxLevels) return set_error(FSMT_ELIMIT, "n_levels must be in [0, %d]", kMaxLevels);
+    if (O.n_levels > 0 && !O.kappas) return set_error(FSMT_EINVAL, "kappas is NULL");
+    if (O.steps_per_level < 0) return set_error(FSMT_EINVAL, "steps_per_level < 0");
+    if (!(O.eta_a > 0.0f) || !(O.eta_b > 0.0f)) return set_error(FSMT_EINVAL, "step sizes must be positive");
+    if (O.tau < 1) return set_error(FSMT_EINVAL, "tau must be >= 1");
+    if (!(O.gamma > 0.0f) || !(O.rho >= 0.0f)) return set_error(FSMT_EINVAL, "bad ERWA parameters");
+    if (O.schedule != 0 && O.schedule != 1) return set_error(FSMT_EUNSUPPORTED, "schedule %d not available", O.schedule);
+    for (int t = 0; t < O.n_levels; ++t)
+        if (!(O.kappas[t] >= 0.0)) return set_error(FSMT_EINVAL, "kappa[%d] must be in [0, +inf]", t);
+
+    SolveParams P{};
+    P.n_inst = n_inst;
+    P.n_levels = O.n_levels;
+    P.steps = O.steps_per_level;
+    P.tau = O.tau;
+    P.normalize = O.normalize ? 1 : 0;
+    P.stop_mode = O.stop_on_sat;
+    P.eta_a = O.eta_a;
+    P.eta_b = O.eta_b;
+    P.eps2 = O.eps > 0.0f ? O.eps * O.eps : -1.0f;
+    P.rho = O.rho;
+    P.gamma = O.gamma;
+    for (int t = 0; t < O.n_levels; ++t) P.kappas[t] = O.kappas[t];
+
+    std::vector<InstDesc> desc(n_inst);
+    int64_t wg = 0;
+    size_t state_f = 0;
+    int maxn = 0, maxs = 1;
+    int device = -1;
+    fsmt_status rc;
+    for (int i = 0; i < n_inst; ++i) {
+        const fsmt_xbdd *h = insts[i];
+        const fsmt_solve_state &S = states[i];
+        if (!h) return set_error(FSMT_EINVAL, "instance %d: null handle", i);
+        if ((rc = select_device(h))) return rc;
+        if (device >= 0 && h->device != device) return set_error(FSMT_EINVAL, "instances on different devices");
+        device = h->device;
+        const int R = S.a.rows;
+        if (R <= 0) return set_error(FSMT_EINVAL, "instance %d: no restarts", i);
+        if (S.a.cols != h->n_bool || S.b.rows != R || S.b.cols != h->n_real)
+            return set_error(FSMT_EINVAL, "instance %d: state shape does not match the instance", i);
+        if ((h->n_bool > 1 && S.a.stride_v != 1) || (h->n_real > 1 && S.b.stride_v != 1) ||
+            (R > 1 && ((h->n_bool > 0 && S.a.stride_r < h->n_bool) || (h->n_real > 0 && S.b.stride_r < h->n_real))))
+            return set_error(FSMT_EINVAL, "instance %d: a and b must be row-major [R][n] with unit column stride", i);
+        const void *ptrs[] = {h->n_bool ? S.a.data : nullptr, h->n_real ? S.b.data : nullptr, S.w, S.hist,
+                              S.sat_bits, S.n_unsat, S.verdict, S.level_done, S.steps_done, S.obj};
+        for (int q = 0; q < 10; ++q) {
+            if (!ptrs[q] && q >= 2) return set_error(FSMT_EINVAL, "instance %d: state pointer %d is NULL", i, q);
+            if ((rc = check_device_ptr(ptrs[q], h->device, "state"))) return rc;
+        }
+        InstDesc &d = desc[i];
+        d.T = TabView::of(h);
+        d.hs = halfspaces_of(h);
+        d.a = S.a.data;
+        d.b = S.b.data;
+        d.a_sr = S.a.stride_r;
+        d.b_sr = S.b.stride_r;
+        d.w = S.w;
+        d.hist = S.hist;
+        d.sat_bits = S.sat_bits;
+        d.n_unsat = S.n_unsat;
+        d.verdict = S.verdict;
+        d.level_done = S.level_done;
+        d.steps_done = S.steps_done;
+        d.obj = S.obj;
+        d.R = R;
+        d.wg_base = (int32_t)wg;
+        wg += R;
+        state_f = std::max(state_f, state_floats_of(h));
+        maxn = std::max(maxn, h->max_nodes);
+        maxs = std::max(maxs, h->max_slots);
+    }
+    if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
+    const int NN = maxn + 2;
+    const size_t wave_bytes = WaveScratch::bytes(NN, maxs);
+    const size_t budget = (size_t)lds_budget_bytes();
+    const size_t state_bytes = state_f * sizeof(float);
+    if (state_bytes + wave_bytes > budget)
+        return set_error(FSMT_EUNSUPPORTED, "restart state (%zu B) does not fit the persistent schedule's LDS (%zu B)",
+                         state_bytes, budget);
+    const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
+    P.lds_nodes = maxn;
+    P.lds_slots = maxs;
+    P.state_floats = (int32_t)state_f;
+    P.waves = waves;
+    const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+
+    hipStream_t st = (hipStream_t)stream;
+    void *dbuf = nullptr;
+    const size_t desc_bytes = sizeof(InstDesc) * (size_t)n_inst;
+    const size_t flag_off = (desc_bytes + 255) / 256 * 256;
+    if (hipMallocAsync(&dbuf, flag_off + sizeof(int32_t) * (size_t)n_inst, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FSMT_ENOMEM, "descriptor allocation failed");
+    }
+    int32_t *flags = (int32_t *)((char *)dbuf + flag_off);
+    if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        fill_i32(flags, n_inst, 0, st) != FSMT_OK) {
+        (void)hipFreeAsync(dbuf, st);
+        return set_error(FSMT_EHIP, "descriptor upload failed");
+    }
+    hipLaunchKernelGGL(solve_wg_kernel, dim3((unsigned)wg), dim3(64 * waves), lds, st, (const InstDesc *)dbuf, P, flags);
+    rc = launch_status("solver kernel");
+    (void)hipFreeAsync(dbuf, st);
+    return rc;
 }

@@ -290,6 +290,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         return set_error(FSMT_EINVAL, "null array in problem");
     const int max_nodes = (opts && opts->max_nodes > 0) ? std::min(opts->max_nodes, 65000) : 1024;
     const bool host_only = opts && opts->device == FSMT_HOST_ONLY;
+    int h_box_units = 0;
     int device = (opts && opts->device >= 0) ? opts->device : -1;
     if (!host_only && device < 0 && hipGetDevice(&device) != hipSuccess)
         return set_error(FSMT_EHIP, "hipGetDevice failed");
@@ -455,15 +456,67 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     h->h_con_bucket = con_bucket;
     h->h_con_local = con_local;
     h->host_only = host_only;
-    if (host_only) {
-        *out = h;
-        return FSMT_OK;
-    }
 
+    // ---- feasible set of the projection (Def. "Projection", Prop. "qp"): the box, plus
+    // unit atomic constraints (one atom literal, no Boolean) when requested.
     std::vector<float> lo(m), hi(m);
     for (int j = 0; j < m; ++j) {
         lo[j] = (float)P->real_lo[j];
         hi[j] = (float)P->real_hi[j];
+    }
+    std::vector<int32_t> hs_ptr{0}, hs_var;
+    std::vector<float> hs_coef, hs_rhs, hs_inv;
+    const bool unit_proj = !(opts && opts->projection == FSMT_PROJ_BOX);
+    for (int c = 0; c < C && unit_proj; ++c) {
+        if (P->con_kind[c] != FSMT_CLAUSE && P->con_kind[c] != FSMT_AND) continue;
+        if (P->con_ptr[c + 1] - P->con_ptr[c] != 1) continue;
+        const int32_t lit = P->con_lit[P->con_ptr[c]];
+        if ((lit >> 1) < n) continue;
+        const int k = (lit >> 1) - n;
+        const bool want = (lit & 1) == 0;                 // the atom must hold (else its negation)
+        const int e0 = a_ptr[k], e1 = a_ptr[k + 1];
+        const bool strict = a_strict[k] != 0;
+        auto holds = [&](float f) {                        // the exact test of the check
+            const double z = (0.0 + a_coef[e0] * (double)f) - a_rhs[k];
+            const bool t = strict ? (z < 0.0) : (z <= 0.0);
+            return t == want;
+        };
+        if (e1 - e0 == 1) {
+            const int j = a_var[e0];
+            const double q = a_coef[e0];
+            // the atom holds for y <= q0/q (q > 0, want) or y >= q0/q, flipped by negation
+            const bool upper = (q > 0.0) == want;
+            float f = (float)(a_rhs[k] / q);
+            for (int it = 0; it < 8 && !holds(f); ++it) f = nextafterf(f, upper ? -INFINITY : INFINITY);
+            if (!holds(f)) continue;
+            const float nlo = upper ? lo[j] : std::max(lo[j], f);
+            const float nhi = upper ? std::min(hi[j], f) : hi[j];
+            if (!(nlo <= nhi)) continue;                   // empty: leave the atom soft
+            lo[j] = nlo;
+            hi[j] = nhi;
+            ++h_box_units;
+        } else {
+            const double sg = want ? 1.0 : -1.0;
+            double scale = std::fabs(a_rhs[k]), q2 = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int j = a_var[e];
+                scale += std::fabs(a_coef[e]) * std::max(std::fabs(P->real_lo[j]), std::fabs(P->real_hi[j]));
+                hs_var.push_back(j);
+                hs_coef.push_back((float)(sg * a_coef[e]));
+                q2 += a_coef[e] * a_coef[e];
+            }
+            hs_rhs.push_back((float)(sg * a_rhs[k] - 1e-6 * scale));
+            hs_inv.push_back((float)(1.0 / q2));
+            hs_ptr.push_back((int32_t)hs_var.size());
+        }
+    }
+
+    h->n_box_units = h_box_units;
+    h->n_hs = (int)hs_rhs.size();
+    h->hs_nnz = (int)hs_var.size();
+    if (host_only) {
+        *out = h;
+        return FSMT_OK;
     }
 
     // ---- upload
@@ -490,6 +543,11 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.atom_strict, a_strict, "atom flags");
     if (!rc) rc = U.put(&h->d.real_lo, lo, "box lo");
     if (!rc) rc = U.put(&h->d.real_hi, hi, "box hi");
+    if (!rc) rc = U.put(&h->d.hs_ptr, hs_ptr, "half-space offsets");
+    if (!rc) rc = U.put(&h->d.hs_var, hs_var, "half-space variables");
+    if (!rc) rc = U.put(&h->d.hs_coef, hs_coef, "half-space coefficients");
+    if (!rc) rc = U.put(&h->d.hs_rhs, hs_rhs, "half-space rhs");
+    if (!rc) rc = U.put(&h->d.hs_inv, hs_inv, "half-space norms");
     (void)hipSetDevice(prev);
     if (rc) {
         release(h);
@@ -532,6 +590,8 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;
+    s->n_box_units = h->n_box_units;
+    s->n_halfspaces = h->n_hs;
     return FSMT_OK;
 }
 

@@ -102,24 +102,36 @@ def test_hard_objective_counts_violations_at_vertices():
     np.testing.assert_array_equal(g["U_fwd"], ch["n_unsat"].astype(np.float32))
 
 
-def test_pgd_step_matches_oracle():
+@pytest.mark.parametrize("projection", ["box", "unit"])
+def test_pgd_step_matches_oracle(projection):
+    """Box projection: the clamp, exact up to FP32 rounding. Box + unit atoms (Prop. qp):
+    Dykstra in FP32 against the FP64 oracle run to convergence."""
     p = W.make_config(2)
     R = 8
     a, b = W.initial_points(p, R, 2, 3)
     rng = np.random.default_rng(3)
     ga = rng.normal(size=a.shape).astype(np.float32) * 3
     gb = rng.normal(size=b.shape).astype(np.float32) * 50
-    h = fsmt.xbdd_compile(p)
+    unit = projection == "unit"
+    h = fsmt.xbdd_compile(p, projection=fsmt.FSMT_PROJ_UNIT if unit else fsmt.FSMT_PROJ_BOX)
+    assert fsmt.xbdd_info(h)["n_halfspaces"] == (5 if unit else 0)
     ta, tb, tga, tgb = T(a), T(b), T(ga), T(gb)
     gsq = torch.zeros(R, device=dev())
     fsmt.pgd_step(h, ta, tb, tga, tgb, 0.25, 2.0, gsq)
-    o = oracle.pgd(p, a, b, ga, gb, 0.25, 2.0)
+    o = oracle.pgd(p, a, b, ga, gb, 0.25, 2.0, unit_proj=unit)
     na, nb = ta.cpu().numpy(), tb.cpu().numpy()
     assert np.all(np.abs(na - o["a"]) <= 2e-7 * np.maximum(1, np.abs(o["a"])))
-    assert np.all(np.abs(nb - o["b"]) <= 2e-7 * np.maximum(1, np.abs(o["b"])) + 1e-6)
+    btol = (2e-6 if unit else 2e-7) * np.maximum(1, np.abs(o["b"])) + 1e-6
+    assert np.all(np.abs(nb - o["b"]) <= btol), np.abs(nb - o["b"]).max()
     assert np.all((na >= -1) & (na <= 1)) and np.all((nb >= 0) & (nb <= p.real_hi[0]))
     np.testing.assert_allclose(gsq.cpu().numpy(), o["gsq"], rtol=1e-4)
     assert float(tga.abs().max()) == 0.0 and float(tgb.abs().max()) == 0.0
+    if unit:   # horizons and precedences hold at the projected float32 point
+        ch = oracle.check(p, na, nb)
+        P = p.meta["n_pairs"]
+        for r in range(R):
+            for c in range(2 * P, p.n_cons):
+                assert (ch["sat_bits"][r, c >> 5] >> (c & 31)) & 1
 
 
 def _check_gpu(p, h, a, b):

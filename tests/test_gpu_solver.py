@@ -1,0 +1,183 @@
+"""GPU tests of the fused batched solver, the plain per-call driver and the autograd wrapper."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from gpu_util import T, assert_objective, dev, torch
+
+pytestmark = pytest.mark.gpu
+fsmt = pytest.importorskip("paper_2603_22877_amd")
+from paper_2603_22877_amd import solver as S  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _bits_of(st):
+    return st.sat_bits.cpu().numpy().view(np.uint32)
+
+
+def _one_step(p, R, kap, eta_a, eta_b, seed):
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 50, seed)
+    st = S.BatchState(h, a0, b0)
+    cfg = S.SolveConfig(kappas=[kap], steps_per_level=1, eta_a=eta_a, eta_b=eta_b, eps=0.0, stop_on_sat=0)
+    S.solve_batched([h], [st], cfg)
+    torch.cuda.synchronize()
+    return h, a0, b0, st
+
+
+def _assert_step(p, a0, b0, st, kap, eta_a, eta_b):
+    o = oracle.objective(p, a0, b0, kap, per_constraint=False)
+    ref = oracle.pgd(p, a0, b0, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32), eta_a, eta_b)
+    a1, b1 = st.a.cpu().numpy(), st.b.cpu().numpy()
+    for r in range(a0.shape[0]):
+        tol_a = eta_a * (1e-5 * o["absg_a"][r] + 4e-7 * o["absg_a"][r].max()) + 3e-7 * (1 + np.abs(ref["a"][r]))
+        assert np.all(np.abs(a1[r] - ref["a"][r]) <= tol_a), np.abs(a1[r] - ref["a"][r]).max()
+        tol_b = eta_b * (1e-5 * o["absg_b"][r] + 4e-7 * o["absg_b"][r].max()) + 2e-6 * (1 + np.abs(ref["b"][r]))
+        assert np.all(np.abs(b1[r] - ref["b"][r]) <= tol_b), np.abs(b1[r] - ref["b"][r]).max()
+    # the objective reported is U at the point where the step started
+    assert_objective(st.obj.cpu().numpy(), o["U"], p.n_cons)
+    # check and ERWA at the GPU's own post-step point: bit-exact / FP32 rounding only
+    ch = oracle.check(p, a1, b1)
+    np.testing.assert_array_equal(_bits_of(st), ch["sat_bits"])
+    np.testing.assert_array_equal(st.n_unsat.cpu().numpy(), ch["n_unsat"])
+    np.testing.assert_array_equal(st.verdict.cpu().numpy(), ch["verdict"])
+    hh, ww = np.zeros((a0.shape[0], p.n_cons)), np.ones((a0.shape[0], p.n_cons))
+    oracle.erwa(ch["sat_bits"], p.n_cons, 1, hh, ww)
+    np.testing.assert_allclose(st.w.cpu().numpy(), ww, rtol=2e-6)
+    np.testing.assert_array_equal(st.hist.cpu().numpy(), hh)
+    assert np.all(st.level_done.cpu().numpy() == 1) and np.all(st.steps_done.cpu().numpy() == 1)
+
+
+@pytest.mark.parametrize("cfg,R,kap,eta_b", [(1, 4, 0.05, 5.0), (2, 8, 0.1, 5.0), (3, 4, 0.2, 8.0)])
+def test_fused_step_matches_oracle(cfg, R, kap, eta_b):
+    print(f"fused step config {cfg} R={R}", flush=True)
+    p = W.make_config(cfg)
+    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg)
+    _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
+
+
+def test_fused_step_random_formulas():
+    for seed in range(3):
+        p = W.make_random_formula(3000 + seed, n_cons=120, max_len=5)
+        h, a0, b0, st = _one_step(p, 5, 0.7, 0.3, 0.4, seed)
+        _assert_step(p, a0, b0, st, 0.7, 0.3, 0.4)
+
+
+def test_multi_instance_batch_equals_single():
+    probs = [W.make_config(1), W.make_random_formula(3100, n_cons=60), W.make_fig2_toy(), W.make_config(2)]
+    Rs = [3, 5, 2, 4]
+    hs = [fsmt.xbdd_compile(p) for p in probs]
+    init = [W.initial_points(p, R, 60, i) for i, (p, R) in enumerate(zip(probs, Rs))]
+    cfg = S.SolveConfig(kappas=[0.3, 0.6], steps_per_level=3, eta_a=0.4, eta_b=1.0, eps=0.0, stop_on_sat=0)
+    batch = [S.BatchState(h, a, b) for h, (a, b) in zip(hs, init)]
+    S.solve_batched(hs, batch, cfg)
+    for h, (a, b), bs in zip(hs, init, batch):
+        single = S.BatchState(h, a, b)
+        S.solve_batched([h], [single], cfg)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(bs.a.cpu().numpy(), single.a.cpu().numpy(), rtol=0, atol=1e-5)
+        np.testing.assert_allclose(bs.b.cpu().numpy(), single.b.cpu().numpy(), rtol=1e-5, atol=1e-5)
+        np.testing.assert_array_equal(bs.level_done.cpu().numpy(), single.level_done.cpu().numpy())
+
+
+def test_levels_replay_erwa_and_check():
+    """Level by level (one call per level, resuming): the check bits equal the oracle's at the
+    GPU point, and the weights equal the oracle's ERWA update of the previous weights."""
+    p = W.make_config(2)
+    R = 8
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 2, 3)
+    st = S.BatchState(h, a0, b0)
+    kappas = S.kappa_schedule(p.meta["mean_duration"], 6)
+    hh = np.zeros((R, p.n_cons))
+    for t in range(1, 4):
+        w_prev = st.w.cpu().numpy().astype(np.float64)
+        cfg = S.SolveConfig(kappas=kappas[:t], steps_per_level=5, eta_a=0.5, eta_b=5.0, eps=0.0, stop_on_sat=0)
+        S.solve_batched([h], [st], cfg)
+        torch.cuda.synchronize()
+        a1, b1 = st.a.cpu().numpy(), st.b.cpu().numpy()
+        ch = oracle.check(p, a1, b1)
+        np.testing.assert_array_equal(_bits_of(st), ch["sat_bits"])
+        ww = w_prev.copy()
+        oracle.erwa(ch["sat_bits"], p.n_cons, t, hh, ww)
+        np.testing.assert_allclose(st.w.cpu().numpy(), ww, rtol=2e-5)
+        np.testing.assert_allclose(st.hist.cpu().numpy(), hh, rtol=1e-6)
+        assert np.all(st.level_done.cpu().numpy() == t)
+        assert np.all(st.steps_done.cpu().numpy() == 5 * t)
+
+
+@pytest.mark.parametrize("cfg,R", [(1, 16), (2, 64)])
+def test_batched_solver_reaches_sat(cfg, R):
+    p = W.make_config(cfg)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, cfg, 0)
+    st = S.BatchState(h, a0, b0)
+    scfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100,
+                         eta_a=0.5, eta_b=5.0, eps=1e-2, stop_on_sat=2)
+    S.solve_batched([h], [st], scfg)
+    torch.cuda.synchronize()
+    ver = st.verdict.cpu().numpy()
+    assert ver.max() == 1, st.n_unsat.cpu().numpy()
+    r = int(np.argmax(ver))
+    ch = oracle.check(p, st.a.cpu().numpy()[r:r + 1], st.b.cpu().numpy()[r:r + 1])
+    assert ch["verdict"][0] == 1
+
+
+def test_plain_solver_reaches_sat_config1():
+    p = W.make_config(1)
+    h = fsmt.xbdd_compile(p)
+    plain = S.PlainSolver(h, R=1)
+    cfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100,
+                        eta_a=0.5, eta_b=5.0, eps=1e-2)
+    found = False
+    for seed in range(4):
+        a0, b0 = W.initial_points(p, 1, 1, 100 + seed)
+        res = plain.run(a0, b0, cfg)
+        if res["verdict"] == 1:
+            ch = oracle.check(p, res["a"].cpu().numpy(), res["b"].cpu().numpy())
+            assert ch["verdict"][0] == 1
+            found = True
+            break
+    assert found
+
+
+def test_autograd_function_matches_reverse_sweep():
+    p = W.make_config(3)
+    R = 4
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 3, 7)
+    a = T(a0).requires_grad_(True)
+    b = T(b0).requires_grad_(True)
+    w = T(np.ones(p.n_cons))
+    U = S.cop_objective(a, b, h, 0.2, w)
+    gout = torch.tensor([1.0, 2.0, -0.5, 3.0], device=dev())
+    U.backward(gout)
+    o = oracle.objective(p, a0, b0, 0.2, per_constraint=False)
+    assert_objective(U.detach().cpu().numpy(), o["U"], p.n_cons)
+    g = gout.cpu().numpy()[:, None]
+    np.testing.assert_allclose(a.grad.cpu().numpy(), g * o["grad_a"], rtol=1e-4, atol=1e-5 * np.abs(o["grad_a"]).max())
+    np.testing.assert_allclose(b.grad.cpu().numpy(), g * o["grad_b"], rtol=1e-4, atol=1e-5 * np.abs(o["grad_b"]).max())
+    with torch.no_grad():
+        U2 = S.cop_objective(a, b, h, 0.2, w)
+    np.testing.assert_allclose(U2.cpu().numpy(), U.detach().cpu().numpy(), rtol=1e-6)
+
+
+def test_solver_rejects_bad_options():
+    p = W.make_config(1)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, 2, 1, 0)
+    st = S.BatchState(h, a0, b0)
+    with pytest.raises(fsmt.FsmtError):
+        S.solve_batched([h], [st], S.SolveConfig(kappas=[0.1] * 200))
+    with pytest.raises(fsmt.FsmtError):
+        S.solve_batched([h], [st], S.SolveConfig(kappas=[0.1], eta_a=0.0))
+    with pytest.raises(fsmt.FsmtError):
+        S.solve_batched([h], [st], S.SolveConfig(kappas=[-1.0]))
+    assert int(st.level_done.max()) == 0

@@ -345,7 +345,7 @@ def test_pgd_projection_closed_form():
     b = rng.uniform(0, p.real_hi[0], (2, p.n_real)).astype(np.float32)
     ga = rng.normal(size=a.shape).astype(np.float32) * 10
     gb = rng.normal(size=b.shape).astype(np.float32) * 100
-    st = oracle.pgd(p, a, b, ga, gb, 0.1, 0.5)
+    st = oracle.pgd(p, a, b, ga, gb, 0.1, 0.5, unit_proj=False)
     ea = np.clip(a.astype(np.float64) - 0.1 * ga.astype(np.float64), -1, 1)
     eb = np.clip(b.astype(np.float64) - 0.5 * gb.astype(np.float64), p.real_lo, p.real_hi)
     np.testing.assert_array_equal(st["a"], ea)
@@ -414,3 +414,82 @@ def test_anneal_solves_fig2_toy_to_global_minimum():
                        eta_a=0.5, eta_b=0.5, steps_per_level=50)
     assert tr[-1]["n_unsat"][0] == 0
     assert tr[-1]["a"][0, 0] < 0 and tr[-1]["b"][0, 0] > 0
+
+
+# ------------------------------------------------------------------ projection onto D
+def _active_set_projection(y0, G, h):
+    """Exact argmin ||y - y0||^2 s.t. G y <= h by enumerating active sets (tiny problems)."""
+    import itertools
+    m = len(y0)
+    best = None
+    for k in range(0, m + 1):
+        for S in itertools.combinations(range(len(h)), k):
+            S = list(S)
+            if S:
+                GS = G[S]
+                M = GS @ GS.T
+                if abs(np.linalg.det(M)) < 1e-12:
+                    continue
+                lam = np.linalg.solve(M, GS @ y0 - h[S])
+                if np.any(lam < -1e-12):
+                    continue
+                y = y0 - GS.T @ lam
+            else:
+                y = y0.copy()
+            if np.all(G @ y <= h + 1e-9):
+                d = np.sum((y - y0) ** 2)
+                if best is None or d < best[0]:
+                    best = (d, y)
+    return best[1]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_projection_onto_unit_atoms_matches_active_set_qp(seed):
+    """Def. Projection / Prop. qp: box plus unit atomic constraints (a single atom literal)."""
+    rng = np.random.default_rng(seed)
+    m = 3
+    bl = Builder(1, m, np.full(m, -2.0), np.full(m, 2.0))
+    rows, rhs = [], []
+    y_star = rng.uniform(-1.5, 0.4, m)                  # a point inside D, so D is not empty
+    for t in range(int(rng.integers(1, 4))):
+        vs = rng.choice(m, 2, replace=False)
+        q = np.round(rng.normal(size=2), 2)
+        q[q == 0] = 0.5
+        op = int(rng.choice([OP_LE, OP_GE]))
+        neg = bool(rng.integers(0, 2))
+        s = (1.0 if op == OP_LE else -1.0) * (-1.0 if neg else 1.0)
+        q0 = float(q @ y_star[vs] + s * rng.uniform(0.1, 1.0))
+        bl.add(KIND_CLAUSE, [lit(bl.atom(vs, q, op, q0), neg)])
+        row = np.zeros(m)
+        row[vs] = s * q
+        delta = 1e-6 * (abs(q0) + np.abs(q).sum() * 2.0)
+        rows.append(row)
+        rhs.append(s * q0 - delta)
+    j = int(rng.integers(m))                            # a single-variable unit atom: a bound
+    bl.add(KIND_CLAUSE, [lit(bl.atom([j], [2.0], OP_LE, 1.0))])
+    bl.add(KIND_CLAUSE, [lit(0), lit(bl.atom([0, 1], [1.0, 1.0], OP_LE, 0.0))])   # not a unit atom
+    p = bl.build()
+    G = np.array(rows + [np.eye(m)[i] for i in range(m)] + [-np.eye(m)[i] for i in range(m)])
+    hi = np.full(m, 2.0)
+    hi[j] = 0.5
+    h = np.array(rhs + list(hi) + [2.0] * m)
+    for _ in range(5):
+        y0 = rng.uniform(-3, 3, m)
+        y, lo_, hi_, nh = oracle.project(p, y0)
+        assert nh == len(rows)
+        assert hi_[j] == 0.5
+        np.testing.assert_allclose(y, _active_set_projection(y0, G, h), atol=1e-9)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_projected_points_satisfy_unit_atoms_after_rounding(cfg):
+    """The shifted half-spaces keep precedences and horizons true at the float32 point."""
+    p = W.make_config(cfg)
+    a, b = W.initial_points(p, 8, cfg, 9)
+    st = oracle.pgd(p, a, b, np.zeros_like(a), np.zeros_like(b), 0.1, 1.0)
+    assert st["n_halfspaces"] == 5
+    ch = oracle.check(p, a, st["b"].astype(np.float32))
+    P = p.meta["n_pairs"]
+    for r in range(8):
+        for c in range(2 * P, p.n_cons):              # horizons and precedences
+            assert (ch["sat_bits"][r, c >> 5] >> (c & 31)) & 1
