@@ -2,18 +2,30 @@
 """Benchmark of the FourierSMT hot path on one MI355X.
 
 Workload: job-shop scheduling, 200 jobs on 10 machines (~2,000 order Booleans, ~4,100
-constraints), 64 restarts, seeded synthetic instance (the paper's instances are not public).
-A step is one pass of the whole hot path over the batch: literal probabilities, forward
-and reverse sweep with gradient scatter (one kernel), the projected-gradient step, and the
-rounding + exact check. Prints one JSON line.
+constraints), 64 restarts, seeded synthetic instances (the paper's instances are not
+public; the generator is in workloads/scheduling.py).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+* value: constraint-evals/s of the fused batched solver. A step is one annealing level:
+  100 PGD iterations, each the literal probabilities, forward + reverse sweep with the
+  gradient scatter, objective, and the projected step, followed by the rounding + exact
+  check and the ERWA weight update. One constraint-eval = one (constraint, restart)
+  forward + backward; evals per step = C x R x 100. Inputs are resident on the device
+  before the timed region; no early exit (eps = 0, no stop on SAT) so the work is fixed.
+* time_to_sat: wall time until a SAT verdict, batched fused (64 restarts in one launch)
+  against the plain per-call path (one restart at a time, separate launches per step),
+  same hyperparameters, median and PAR-2 over instance seeds.
+* roofline: the solver kernel's duration from HIP events on its stream; algorithmic
+  FLOP and byte counts per launch (model in the design doc).
+* cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-tts]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -24,153 +36,209 @@ import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (published)
+STEPS_PER_LEVEL = 100
+ETA_A, ETA_B, EPS = 0.5, 5.0, 1e-2
+LEVELS = 40
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--kappa", type=float, default=0.05)
+    ap.add_argument("--steps", type=int, default=20, help="timed annealing levels (<= 128)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-SAT comparison")
+    ap.add_argument("--tts-seeds", type=int, default=5)
+    ap.add_argument("--tts-cap", type=float, default=30.0, help="time limit per instance (s)")
     ap.add_argument("--pmc-mode", action="store_true",
-                    help="few launches plus a 256 MiB copy kernel, for counter collection")
+                    help="one short solver launch plus a 256 MiB copy, for counter collection")
     return ap.parse_args()
 
 
 def algorithmic_cost(p, stats):
-    """Per-launch algorithmic work of the forward + reverse sweep."""
+    """Slots, atoms and nodes of the instance (per constraint-eval work model)."""
     nnz = np.diff(p.atom_ptr)
-    n_bool_lits = n_atom_lits = 0
+    n_bool = n_atom = nnz_used = 0
     for c in range(p.n_cons):
         ids = np.unique(p.con_lit[p.con_ptr[c]:p.con_ptr[c + 1]] >> 1)
-        n_bool_lits += int((ids < p.n_bool).sum())
-        n_atom_lits += int((ids >= p.n_bool).sum())
-    atom_nnz_per_con = float(nnz.sum())
-    return dict(total_nodes=int(stats["total_nodes"]), bool_slots=n_bool_lits, atom_slots=n_atom_lits,
-                atom_nnz=atom_nnz_per_con, table_bytes=int(stats["table_bytes"]))
+        n_bool += int((ids < p.n_bool).sum())
+        atoms = ids[ids >= p.n_bool] - p.n_bool
+        n_atom += len(atoms)
+        nnz_used += int(nnz[atoms].sum())
+    return dict(total_nodes=int(stats["total_nodes"]), bool_slots=n_bool, atom_slots=n_atom,
+                atom_nnz=nnz_used, table_bytes=int(stats["table_bytes"]))
 
 
-def flops_per_step(cost, R):
-    # forward 4 flops/node (two multiply-adds), reverse 6 flops/node (p*bh + q*bl: 3,
-    # (bh - bl) and the multiply-add into the slot sensitivity: 3);
-    # Boolean slot: p, 1-p, gradient (-1/2 w G): 6; atom slot: z (2 per nnz + 1), u (1),
-    # erfc (25, rational approximation), exp (10), dp/dz (2), p and 1-p (2),
-    # gradient (2 + 2 per nnz)
+def flops_per_pass(cost, R):
+    """FP32-equivalent operations of one forward + reverse sweep over all constraints.
+
+    forward 4/node (two multiply-adds), reverse 6/node; Boolean slot 6 (p, 1-p, gradient);
+    atom slot: z 2/nnz + 1, u 1, erfc 25, exp 10, dp/dz 2, p and 1-p 2, gradient 2 + 2/nnz.
+    """
     per = (10 * cost["total_nodes"] + 6 * cost["bool_slots"]
-           + (1 + 1 + 25 + 10 + 2 + 2 + 2) * cost["atom_slots"] + 4 * cost["atom_nnz"])
+           + 43 * cost["atom_slots"] + 4 * cost["atom_nnz"])
     return float(per) * R
 
 
-def bytes_per_step(cost, p, R):
-    # compiled tables streamed once per launch + per restart state: read a, b; gradient
-    # read-modify-write and the projected step (read a, b, grads; write a, b, zero grads)
-    S = 4 * (p.n_bool + p.n_real)
-    return float(cost["table_bytes"]) + R * S * 6
+def bytes_per_pass(cost, p, R):
+    """Compiled tables read once per pass, plus per restart: a, b read, gradient written and
+    read, projected state written, and one weight per constraint read."""
+    return float(cost["table_bytes"]) + R * (4 * (p.n_bool + p.n_real) * 5 + 4 * p.n_cons)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+                                   "(restarts and instances shard across GPUs without exchange)"}))
         sys.exit(2)
     import torch
 
     import paper_2603_22877_amd as fsmt
+    from paper_2603_22877_amd import solver as S
     import workloads as W
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     p = W.make_config(2)
     R = W.RESTARTS[2]
-    a0, b0 = W.initial_points(p, R, 2, 0)
+    ell = p.meta["mean_duration"]
+    t0 = time.perf_counter()
     h = fsmt.xbdd_compile(p)
+    compile_s = time.perf_counter() - t0
     stats = fsmt.xbdd_info(h)
     cost = algorithmic_cost(p, stats)
     st = torch.cuda.Stream(device=dev)
-    # variable-major state [n][R] viewed as [R][n]: lanes = restarts read consecutive words
-    a = torch.as_tensor(a0.T.copy(), device=dev).t()
-    b = torch.as_tensor(b0.T.copy(), device=dev).t()
-    ga = torch.zeros(p.n_bool, R, device=dev).t()
-    gb = torch.zeros(p.n_real, R, device=dev).t()
-    w = torch.ones(p.n_cons, device=dev)
-    obj = torch.zeros(R, device=dev)
-    gsq = torch.zeros(R, device=dev)
-    nw = (p.n_cons + 31) // 32
-    x = torch.zeros(R, p.n_bool, dtype=torch.int8, device=dev)
-    bits = torch.zeros(R, nw, dtype=torch.int32, device=dev)
-    nu = torch.zeros(R, dtype=torch.int32, device=dev)
-    ver = torch.zeros(R, dtype=torch.int32, device=dev)
-    eta_a, eta_b = 0.05, 1.0
-    kap = args.kappa
+    a0, b0 = W.initial_points(p, R, 2, 0)
+    kappas = S.kappa_schedule(ell, max(LEVELS, args.steps, args.warmup, 2))
 
-    def step(ev=None):
-        obj.zero_()
-        if ev is not None:
-            ev[0].record(st)
-        fsmt.cop_backward(h, a, b, kap, w, obj, ga, gb, flags=fsmt.FSMT_ACCUMULATE, stream=st)
-        if ev is not None:
-            ev[1].record(st)
-        fsmt.pgd_step(h, a, b, ga, gb, eta_a, eta_b, gsq, stream=st)
-        fsmt.round_and_check(h, a, b, x, bits, nu, ver, stream=st)
+    def fixed_cfg(n_levels):
+        return S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=STEPS_PER_LEVEL, eta_a=ETA_A,
+                             eta_b=ETA_B, eps=0.0, stop_on_sat=0)
 
     if args.pmc_mode:
         src = torch.empty(64 * 1024 * 1024, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written
-        for _ in range(5):
-            step()
+        state = S.BatchState(h, a0, b0)
+        S.solve_batched([h], [state], fixed_cfg(2), stream=st)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4}))
         return
 
-    with torch.cuda.stream(st):
-        for _ in range(args.warmup):
-            step()
+    levels = max(1, min(args.steps, 128))
+    warm = S.BatchState(h, a0, b0)
+    S.solve_batched([h], [warm], fixed_cfg(max(1, min(args.warmup, 128))), stream=st)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    state = S.BatchState(h, a0, b0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with torch.cuda.stream(st):
-        for k in range(args.steps):
-            step(evs[k])
+    e0.record(st)
+    S.solve_batched([h], [state], fixed_cfg(levels), stream=st)
+    e1.record(st)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    kern_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-    evals = p.n_cons * R * args.steps
+    dt = time.perf_counter() - t0
+    kern_s = e0.elapsed_time(e1) * 1e-3
+    pgd_steps = int(state.steps_done.cpu().numpy().min())
+    assert pgd_steps == levels * STEPS_PER_LEVEL
+    evals = p.n_cons * R * pgd_steps
     value = evals / dt
 
-    fl = flops_per_step(cost, R)
-    by = bytes_per_step(cost, p, R)
-    achieved_tf = fl / (kern_ms * 1e-3) / 1e12
-    achieved_gbs = by / (kern_ms * 1e-3) / 1e9
+    fl = flops_per_pass(cost, R) * pgd_steps
+    by = bytes_per_pass(cost, p, R) * pgd_steps
+    ach_tf = fl / kern_s / 1e12
+    ach_gbs = by / kern_s / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_sched200.json")
+    tfile = os.path.join(ROOT, "profiles", "traffic_solver_sched200.json")
     if os.path.exists(tfile):
         try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
+            tj = json.load(open(tfile))
+            traffic = tj["bytes_per_pgd_step"] * pgd_steps
         except Exception:
             traffic = None
 
     out = {
         "metric": "constraint-evals/s (fwd+bwd) and time-to-SAT, batched fused vs plain, 1 GPU",
-        "value": value, "unit": "constraint-evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "value": value, "unit": "constraint-evals/s", "n_gpus": 1, "steps": levels,
+        "warmup": args.warmup, "ms_per_step": dt / levels * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "scheduling 200 jobs / 10 machines, 64 restarts",
+        "config": {"workload": "job-shop scheduling, 200 jobs on 10 machines, 64 restarts "
+                               "(fused batched solver; step = one annealing level of 100 PGD "
+                               "iterations + check + ERWA)",
                    "n_cons": p.n_cons, "n_bool": p.n_bool, "n_real": p.n_real, "restarts": R,
-                   "kappa": kap, "path": "per-call kernels (cop_backward, pgd_step, round_and_check)"},
-        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_FP32_TFLOPS,
-                     "traffic": traffic, "kernel": "cop_kernel<true>", "kernel_ms": kern_ms,
-                     "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS},
+                   "pgd_steps_timed": pgd_steps, "compile_s": compile_s,
+                   "table_bytes": stats["table_bytes"]},
+        "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach_tf / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "kernel": "solve_wg_kernel", "kernel_ms": kern_s * 1e3,
+                     "hbm_achieved_gbs": ach_gbs, "hbm_frac": ach_gbs / PEAK_HBM_GBS},
     }
+    if not args.no_tts:
+        out["time_to_sat"] = time_to_sat(args, fsmt, S, W, st)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, a0, b0, kap)
+        out["cpu_baseline"] = cpu_baseline(p, a0, b0, kappas[0])
     print(json.dumps(out))
+
+
+def time_to_sat(args, fsmt, S, W, st):
+    """Batched fused vs plain per-call time-to-SAT on scheduling 200x10 instance seeds."""
+    import torch
+    res = {"batched_s": [], "plain_s": [], "plain_restarts": [], "batched_level": []}
+    cap = args.tts_cap
+    for seed in range(args.tts_seeds):
+        p = W.make_config(2, seed)
+        h = fsmt.xbdd_compile(p)
+        kap = S.kappa_schedule(p.meta["mean_duration"], LEVELS)
+        cfg = S.SolveConfig(kappas=kap, steps_per_level=STEPS_PER_LEVEL, eta_a=ETA_A, eta_b=ETA_B,
+                            eps=EPS, stop_on_sat=2)
+        # batched: 64 restarts per launch; relaunch with fresh seeds until SAT or cap
+        t0 = time.perf_counter()
+        tb, batch_round = None, 0
+        while time.perf_counter() - t0 < cap:
+            a0, b0 = W.initial_points(p, 64, 2, seed, 100 + batch_round)
+            state = S.BatchState(h, a0, b0)
+            S.solve_batched([h], [state], cfg, stream=st)
+            torch.cuda.synchronize()
+            ver = state.verdict.cpu().numpy()
+            if ver.max() == 1:
+                tb = time.perf_counter() - t0
+                res["batched_level"].append(int(state.level_done.cpu().numpy()[ver == 1].min()))
+                break
+            batch_round += 1
+        res["batched_s"].append(tb)
+        # plain: one restart at a time with new seeds
+        plain = S.PlainSolver(h, R=1)
+        t0 = time.perf_counter()
+        tp, r = None, 0
+        while time.perf_counter() - t0 < cap:
+            a0, b0 = W.initial_points(p, 1, 2, seed, 100 + r)
+            out = plain.run(a0, b0, cfg, stream=st)
+            torch.cuda.synchronize()
+            if out["verdict"] == 1:
+                tp = time.perf_counter() - t0
+                break
+            r += 1
+        res["plain_s"].append(tp)
+        res["plain_restarts"].append(r + 1)
+
+    def par2(ts):
+        return float(np.mean([t if t is not None else 2 * cap for t in ts]))
+
+    def med(ts):
+        return float(statistics.median([t if t is not None else 2 * cap for t in ts]))
+
+    return {"instances": args.tts_seeds, "cap_s": cap,
+            "batched_median_s": med(res["batched_s"]), "plain_median_s": med(res["plain_s"]),
+            "batched_par2_s": par2(res["batched_s"]), "plain_par2_s": par2(res["plain_s"]),
+            "speedup_median": med(res["plain_s"]) / med(res["batched_s"]),
+            "batched_solved": sum(t is not None for t in res["batched_s"]),
+            "plain_solved": sum(t is not None for t in res["plain_s"]),
+            "per_instance": res,
+            "hyperparameters": {"levels": LEVELS, "kappa": "4 t / (40 mean duration)",
+                                "steps_per_level": STEPS_PER_LEVEL, "eta_a": ETA_A, "eta_b": ETA_B,
+                                "eps": EPS, "rho": 0.5, "gamma": 2.0, "tau": 1}}
 
 
 def cpu_baseline(p, a0, b0, kap):
