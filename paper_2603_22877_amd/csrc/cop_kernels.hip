@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     const int NN = A.lds_nodes + 2, SS = A.lds_slots;
     const WaveScratch W = WaveScratch::at(lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS);
     const GlobalState st{A.a, A.b};
-    const GlobalScatter sc{A.ga, A.gb};
+    const GlobalScatter sc{A.ga, A.gb, A.R_pad < 64 ? A.R_pad : 64};
+    float oacc = 0.0f;   // objective partial of this lane's restart (R_pad <= 64: fixed per lane)
 
     for (int64_t task = wave0; task < A.n_tasks; task += n_waves) {
         int pos, r;
@@ -67,17 +68,19 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
         const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W, lane);
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
-        // objective: reduce lanes holding the same restart, then one atomic per restart
         if (A.obj) {
-            float contrib = wc * unsat;
-            if (A.R_pad < 64) {
-                for (int off = 32; off >= A.R_pad; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
-                if (lane < A.R_pad && r < A.R) atomic_add_f32(A.obj + r, contrib);
+            if (A.R_pad <= 64) {
+                oacc += wc * unsat;
             } else if (r < A.R) {
-                atomic_add_f32(A.obj + r, contrib);
+                atomic_add_f32(A.obj + r, wc * unsat);
             }
         }
         if (kGrad) task_backward(A.T, t, wc, sc, W, lane);
+    }
+    // objective: reduce lanes holding the same restart, one atomic per restart and wave
+    if (A.obj && A.R_pad <= 64) {
+        for (int off = 32; off >= A.R_pad; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
+        if (lane < A.R_pad && lane < A.R && oacc != 0.0f) atomic_add_f32(A.obj + lane, oacc);
     }
 }
 

@@ -16,6 +16,8 @@ struct TabView {
     const Node *nodes;
     const BucketInfo *bucket;
     const int32_t *bucket_start;
+    const int32_t *task_bucket;
+    const AtomRec *arec;
     const int32_t *pos_con;
     const int32_t *sup;
     const int32_t *con_bucket;
@@ -36,6 +38,8 @@ struct TabView {
         t.nodes = h->d.nodes;
         t.bucket = h->d.bucket;
         t.bucket_start = h->d.bucket_start;
+        t.task_bucket = h->d.task_bucket;
+        t.arec = h->d.arec;
         t.pos_con = h->d.pos_con;
         t.sup = h->d.sup;
         t.con_bucket = h->d.con_bucket;
@@ -71,15 +75,45 @@ struct LdsState {
 };
 
 // ---- gradient accumulation policies
+// Every lane calls add_a / add_b at the same points (uniform control flow); a lane with
+// nothing to add passes var < 0.
+//
+// Global memory: device-scope float atomics are performed past the per-XCD L2, so equal
+// (variable, restart) targets held by different constraint groups of the wave (lanes
+// rpad apart) are first merged by a shuffle butterfly; one atomic per remaining target.
 struct GlobalScatter {
     View ga, gb;
-    __device__ __forceinline__ void add_a(int r, int i, float g) const { atomic_add_f32(&ga.at(r, i), g); }
-    __device__ __forceinline__ void add_b(int r, int j, float g) const { atomic_add_f32(&gb.at(r, j), g); }
+    int rpad;   // lanes per constraint group (64: one group, nothing to merge)
+    __device__ __forceinline__ void merge(int &var, float &val, int lane) const {
+        for (int off = rpad; off < 64; off <<= 1) {
+            const int pv = __shfl_xor(var, off, 64);
+            const float pval = __shfl_xor(val, off, 64);
+            if (pv == var && var >= 0) {
+                if ((lane & off) == 0) val += pval; else val = 0.0f;
+            }
+        }
+    }
+    __device__ __forceinline__ void add_a(int r, int i, float g, int lane) const {
+        merge(i, g, lane);
+        if (i >= 0 && g != 0.0f) atomic_add_f32(&ga.at(r, i), g);
+    }
+    __device__ __forceinline__ void add_b(int r, int j, float g, int lane) const {
+        merge(j, g, lane);
+        if (j >= 0 && g != 0.0f) atomic_add_f32(&gb.at(r, j), g);
+    }
+    // for divergent call sites (no merging)
+    __device__ __forceinline__ void add_b_direct(int r, int j, float g) const { atomic_add_f32(&gb.at(r, j), g); }
 };
+// LDS: the fused solver's gradient lives in LDS and its atomics stay on the CU.
 struct LdsScatter {
     float *ga, *gb;
-    __device__ __forceinline__ void add_a(int, int i, float g) const { atomicAdd(ga + i, g); }
-    __device__ __forceinline__ void add_b(int, int j, float g) const { atomicAdd(gb + j, g); }
+    __device__ __forceinline__ void add_a(int, int i, float g, int) const {
+        if (i >= 0 && g != 0.0f) atomicAdd(ga + i, g);
+    }
+    __device__ __forceinline__ void add_b(int, int j, float g, int) const {
+        if (j >= 0 && g != 0.0f) atomicAdd(gb + j, g);
+    }
+    __device__ __forceinline__ void add_b_direct(int, int j, float g) const { atomicAdd(gb + j, g); }
 };
 
 // z = q.b - q0 of atom k for restart r (exact order, see atom_z_exact).
@@ -93,6 +127,35 @@ __device__ __forceinline__ double atom_z_state(const TabView &T, int k, const St
         acc = acc + prod;
     }
     return acc - T.atom_rhs[k];
+}
+
+// z of an inline atom record: the same multiply-then-add sequence as the CSR form.
+template <class St>
+__device__ __forceinline__ double rec_z(const AtomRec &a, const St &st, int r) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    const double p0 = (double)a.c0 * (double)st.bv(r, a.v0);
+    acc = acc + p0;
+    if (a.flags & 2u) {
+        const double p1 = (double)a.c1 * (double)st.bv(r, a.v1);
+        acc = acc + p1;
+    }
+    return acc - (double)a.rhs;
+}
+
+__device__ __forceinline__ AtomRec load_rec(const AtomRec *p) {
+    const int4 x = reinterpret_cast<const int4 *>(p)[0];
+    const int4 z = reinterpret_cast<const int4 *>(p)[1];
+    AtomRec a;
+    a.v0 = x.x;
+    a.v1 = x.y;
+    a.c0 = __int_as_float(x.z);
+    a.c1 = __int_as_float(x.w);
+    a.rhs = __int_as_float(z.x);
+    a.scale = __int_as_float(z.y);
+    a.atom = z.z;
+    a.flags = (uint32_t)z.w;
+    return a;
 }
 
 // Find the bucket containing position pos (uniform across the wave).
@@ -122,9 +185,9 @@ struct WaveScratch {
 };
 
 struct TaskCtx {
-    BucketInfo B;
-    TplInfo Tp;
+    BucketInfo B;         // bucket record with the template fields
     const int32_t *sup;   // this lane's support column
+    const AtomRec *rec;   // this lane's first inline atom record (or null)
     int c;                // original constraint id (or -1)
     int r;
     bool valid;
@@ -134,10 +197,11 @@ struct TaskCtx {
 __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bool r_ok) {
     TaskCtx t;
     const int pos0 = __builtin_amdgcn_readfirstlane(pos);
-    const int bk = find_bucket(T.bucket_start, T.n_buckets, pos0);
+    const int bk = __builtin_amdgcn_readfirstlane(T.task_bucket[pos0 >> 6]);
     t.B = T.bucket[bk];
-    t.Tp = T.tpl[t.B.tpl];
-    t.sup = T.sup + t.B.sup_base + (pos - t.B.pos_begin);
+    const int local = pos - t.B.pos_begin;
+    t.sup = T.sup + t.B.sup_base + local;
+    t.rec = t.B.arec_base >= 0 ? T.arec + t.B.arec_base + local : nullptr;
     t.c = T.pos_con[pos];
     t.r = r;
     t.valid = (t.c >= 0) && r_ok;
@@ -148,7 +212,7 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
 template <class St>
 __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t, const St &st, double kappa,
                                               bool hard, const WaveScratch &W, int lane) {
-    const int N = t.Tp.n_nodes, S = t.Tp.n_slots, NB = t.Tp.n_bslots;
+    const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
     for (int s = 0; s < NB; ++s) {
         const float av = t.valid ? st.av(t.r, t.sup[(int64_t)s * np]) : 0.0f;
@@ -158,14 +222,25 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
     for (int s = NB; s < S; ++s) {
         float p = 0.5f, q = 0.5f, d = 0.0f;
         if (t.valid) {
-            const int k = t.sup[(int64_t)s * np] - T.n_bool;
-            const double z = atom_z_state(T, k, st, t.r);
+            double z, scale;
+            bool strict;
+            if (t.rec) {
+                const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
+                z = rec_z(a, st, t.r);
+                scale = (double)a.scale;
+                strict = (a.flags & 1u) != 0;
+            } else {
+                const int k = t.sup[(int64_t)s * np] - T.n_bool;
+                z = atom_z_state(T, k, st, t.r);
+                scale = T.atom_scale[k];
+                strict = T.atom_strict[k] != 0;
+            }
             if (hard) {
-                const bool tr = T.atom_strict[k] ? (z < 0.0) : (z <= 0.0);
+                const bool tr = strict ? (z < 0.0) : (z <= 0.0);
                 p = tr ? 1.0f : 0.0f;
                 q = tr ? 0.0f : 1.0f;
             } else {
-                const double ks = kappa * T.atom_scale[k];
+                const double ks = kappa * scale;
                 const float u = (float)(z * ks);
                 const float e = 0.5f * erfcf(fabsf(u));          // the smaller of p, 1-p
                 p = (u >= 0.0f) ? e : 1.0f - e;
@@ -179,8 +254,8 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
         W.D[s * 64 + lane] = d;
     }
     for (int v = 0; v < N + 2; ++v) W.M[v * 64 + lane] = 0.0f;
-    W.M[t.Tp.root * 64 + lane] = 1.0f;
-    const Node *nd = T.nodes + t.Tp.node_off;
+    W.M[t.B.root * 64 + lane] = 1.0f;
+    const Node *nd = T.nodes + t.B.node_off;
     for (int v = 0; v < N; ++v) {
         const Node x = load_node(nd + v);
         const float mv = W.M[v * 64 + lane];
@@ -194,28 +269,57 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
 template <class Sc>
 __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t, float wc, const Sc &sc,
                                               const WaveScratch &W, int lane) {
-    const int N = t.Tp.n_nodes, S = t.Tp.n_slots, NB = t.Tp.n_bslots;
+    const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
     for (int s = 0; s < S; ++s) W.G[s * 64 + lane] = 0.0f;
     W.Bm[N * 64 + lane] = 0.0f;
     W.Bm[(N + 1) * 64 + lane] = 1.0f;
-    const Node *nd = T.nodes + t.Tp.node_off;
+    const Node *nd = T.nodes + t.B.node_off;
     for (int v = N - 1; v >= 0; --v) {
         const Node x = load_node(nd + v);
         const float bh = W.Bm[x.hi * 64 + lane], bl = W.Bm[x.lo * 64 + lane];
         W.Bm[v * 64 + lane] = W.P[x.slot * 64 + lane] * bh + W.Q[x.slot * 64 + lane] * bl;
         W.G[x.slot * 64 + lane] += W.M[v * 64 + lane] * (bh - bl);
     }
-    if (!t.valid) return;
+    // Boolean slots: distinct variables within a constraint
     for (int s = 0; s < NB; ++s) {
-        const float g = wc * W.G[s * 64 + lane] * -0.5f;     // dp/da = -1/2
-        if (g != 0.0f) sc.add_a(t.r, t.sup[(int64_t)s * np], g);
+        const float g = t.valid ? wc * W.G[s * 64 + lane] * -0.5f : 0.0f;     // dp/da = -1/2
+        sc.add_a(t.r, t.valid ? t.sup[(int64_t)s * np] : -1, g, lane);
     }
-    for (int s = NB; s < S; ++s) {
-        const float gz = wc * W.G[s * 64 + lane] * W.D[s * 64 + lane];
-        if (gz == 0.0f) continue;
-        const int k = t.sup[(int64_t)s * np] - T.n_bool;
-        for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e) sc.add_b(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+    if (t.rec) {
+        // inline atoms: consecutive atoms on the same variable are summed in registers; a
+        // running target is flushed (uniformly across the wave) when the next atom's differs
+        int v0 = -1, v1 = -1;
+        float g0 = 0.0f, g1 = 0.0f;
+        for (int s = NB; s < S; ++s) {
+            AtomRec a;
+            float gz = 0.0f;
+            if (t.valid) {
+                a = load_rec(t.rec + (int64_t)(s - NB) * np);
+                gz = wc * W.G[s * 64 + lane] * W.D[s * 64 + lane];
+            } else {
+                a.v0 = a.v1 = -1;
+                a.c0 = a.c1 = 0.0f;
+                a.flags = 0;
+            }
+            const bool n0 = a.v0 != v0, n1 = a.v1 != v1;
+            sc.add_b(t.r, n0 ? v0 : -1, n0 ? g0 : 0.0f, lane);
+            sc.add_b(t.r, n1 ? v1 : -1, n1 ? g1 : 0.0f, lane);
+            if (n0) { v0 = a.v0; g0 = 0.0f; }
+            if (n1) { v1 = a.v1; g1 = 0.0f; }
+            g0 += gz * a.c0;
+            if (a.flags & 2u) g1 += gz * a.c1;
+        }
+        sc.add_b(t.r, v0, g0, lane);
+        sc.add_b(t.r, v1, g1, lane);
+    } else if (t.valid) {
+        for (int s = NB; s < S; ++s) {
+            const float gz = wc * W.G[s * 64 + lane] * W.D[s * 64 + lane];
+            if (gz == 0.0f) continue;
+            const int k = t.sup[(int64_t)s * np] - T.n_bool;
+            for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
+                sc.add_b_direct(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+        }
     }
 }
 
@@ -223,18 +327,21 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
 template <class St>
 __device__ __forceinline__ bool walk_state(const TabView &T, const St &st, int c, int r) {
     const BucketInfo B = T.bucket[T.con_bucket[c]];
-    const TplInfo Tp = T.tpl[B.tpl];
-    const int32_t *s = T.sup + B.sup_base + T.con_local[c];
-    const int N = Tp.n_nodes;
-    int v = Tp.root;
+    const int local = T.con_local[c];
+    const int32_t *s = T.sup + B.sup_base + local;
+    const int N = B.n_nodes;
+    int v = B.root;
     while (v < N) {
-        const Node x = T.nodes[Tp.node_off + v];
-        const int id = s[(int64_t)x.slot * B.n_pos];
+        const Node x = T.nodes[B.node_off + v];
         bool tr;
-        if (x.slot < Tp.n_bslots) {
-            tr = st.av(r, id) < 0.0f;
+        if (x.slot < B.n_bslots) {
+            tr = st.av(r, s[(int64_t)x.slot * B.n_pos]) < 0.0f;
+        } else if (B.arec_base >= 0) {
+            const AtomRec a = load_rec(T.arec + B.arec_base + (int64_t)(x.slot - B.n_bslots) * B.n_pos + local);
+            const double z = rec_z(a, st, r);
+            tr = (a.flags & 1u) ? (z < 0.0) : (z <= 0.0);
         } else {
-            const int k = id - T.n_bool;
+            const int k = s[(int64_t)x.slot * B.n_pos] - T.n_bool;
             const double z = atom_z_state(T, k, st, r);
             tr = T.atom_strict[k] ? (z < 0.0) : (z <= 0.0);
         }

@@ -36,7 +36,24 @@ struct BucketInfo {
     int32_t n_pos;      // positions, a multiple of 64 (>= constraints in the bucket)
     int32_t n_con;      // real constraints in the bucket
     int64_t sup_base;   // offset of the bucket's support block (n_slots * n_pos ids)
-    int64_t pad;
+    int64_t arec_base;  // offset of the bucket's inline atom records, or -1
+    // copy of the template record (one scalar load serves the whole wave)
+    int32_t node_off, n_nodes, n_slots, n_bslots, root;
+    int32_t pad[3];
+};
+
+// Inline atom record (atoms with at most two variables whose "<=" coefficients and
+// right-hand side are exact in float32): one coalesced 32-byte load per (position, atom
+// slot) replaces the CSR indirection. Records are stored per bucket, atom-slot-major:
+// arec[arec_base + (slot - n_bslots) * n_pos + local]. Promoting the float32 values to
+// FP64 gives exactly the stored atom, so the exact test is unchanged.
+struct AtomRec {
+    int32_t v0, v1;     // real variables (v1 unused when nnz == 1)
+    float c0, c1;       // coefficients in "<=" form
+    float rhs;          // right-hand side in "<=" form
+    float scale;        // 1/(sqrt(2)|q|)
+    int32_t atom;       // atom id
+    uint32_t flags;     // bit 0 strict, bit 1 two variables
 };
 
 struct Node {
@@ -48,6 +65,8 @@ struct DeviceTables {
     Node *nodes = nullptr;
     BucketInfo *bucket = nullptr;
     int32_t *bucket_start = nullptr;  // [n_buckets+1] position prefix
+    int32_t *task_bucket = nullptr;   // [n_pos/64] bucket of each 64-position group
+    AtomRec *arec = nullptr;          // inline atom records
     int32_t *pos_con = nullptr;       // [n_pos] original constraint id or -1 (padding)
     int32_t *sup = nullptr;           // support ids, slot-major per bucket
     int32_t *con_bucket = nullptr;    // [C]

@@ -51,12 +51,28 @@ struct HalfSpaces {
     int32_t n, nnz;
 };
 
-// Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces, by
-// Dykstra's alternating projections (half-spaces in order, then the box, per sweep; the
-// increments pb[m], ph[nnz] live in LDS). All threads of the block must call it. Stops when a
-// sweep moves no coordinate by more than 4e-7 (1 + |y|), or after 256 sweeps.
+// Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces.
+// If the clamped point already satisfies every half-space it is the projection; otherwise
+// Dykstra's alternating projections run from y (half-spaces in order, then the box, per
+// sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no coordinate by more than
+// 4e-7 (1 + |y|), or 256 sweeps. All threads of the block must call it.
 __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, const float *lo, const float *hi,
                                                 int m, const HalfSpaces &hs) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
+    __syncthreads();
+    int violated = 0;
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < hs.n && !violated; ++t) {
+            float v = -hs.rhs[t];
+            for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) v += hs.coef[e] * pb[hs.var[e]];
+            violated = v > 0.0f;
+        }
+    }
+    if (!__syncthreads_or(violated)) {
+        for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = pb[j];
+        __syncthreads();
+        return;
+    }
     for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = 0.0f;
     for (int e = threadIdx.x; e < hs.nnz; e += blockDim.x) ph[e] = 0.0f;
     __syncthreads();
@@ -87,6 +103,25 @@ __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, 
         }
         if (!__syncthreads_or(moved)) break;
     }
+}
+
+// Sums of two values over the block (results valid in every thread).
+__device__ __forceinline__ float2 block_sum2(float a, float b) {
+    __shared__ float2 part2[16];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part2[w] = make_float2(a, b);
+    __syncthreads();
+    float2 t = make_float2(0.0f, 0.0f);
+    for (int i = 0; i < nw; ++i) {
+        t.x += part2[i].x;
+        t.y += part2[i].y;
+    }
+    return t;
 }
 
 fsmt_status fill_view(const fsmt_view &v, float value, hipStream_t st);

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "eval_task.hpp"
+#include "solve_grid.hpp"
 
 namespace fsmt {
 
@@ -68,8 +69,14 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
     float *wrow = I.w + (int64_t)r * C, *hrow = I.hist + (int64_t)r * C;
     uint32_t *brow = I.sat_bits + (int64_t)r * nw;
 
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sa[i] = I.a[(int64_t)r * I.a_sr + i];
-    for (int j = threadIdx.x; j < m; j += blockDim.x) sb[j] = I.b[(int64_t)r * I.b_sr + j];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        sa[i] = I.a[(int64_t)r * I.a_sr + i];
+        ga[i] = 0.0f;
+    }
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        sb[j] = I.b[(int64_t)r * I.b_sr + j];
+        gb[j] = 0.0f;
+    }
     int level = I.level_done[r];
     int steps_done = I.steps_done[r];
     int verdict = I.verdict[r];
@@ -84,9 +91,7 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
         const double kappa = P.kappas[level];
         const bool hard = isinf(kappa);
         for (int k = 0; k < P.steps; ++k) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) ga[i] = 0.0f;
-            for (int j = threadIdx.x; j < m; j += blockDim.x) gb[j] = 0.0f;
-            __syncthreads();
+            // gradients are zero here: zeroed at entry and by the previous step's update
             float oacc = 0.0f;
             for (int task = wave; task < n_tasks; task += P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
@@ -96,13 +101,13 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
                 task_backward(T, t, wc, sc, W, lane);
             }
             __syncthreads();
-            obj = block_sum(oacc);
             // projected step (Eq. pg1/pg2) and the gradient map norm (Eq. grad_map)
             float acc = 0.0f;
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const float x = sa[i], y = x - P.eta_a * ga[i];
                 const float p = y < -1.0f ? -1.0f : (y > 1.0f ? 1.0f : y);
                 sa[i] = p;
+                ga[i] = 0.0f;
                 const float g = (x - p) / P.eta_a;
                 acc += g * g;
             }
@@ -111,6 +116,7 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
                     const float x = sb[j], y = x - P.eta_b * gb[j];
                     const float p = y < T.real_lo[j] ? T.real_lo[j] : (y > T.real_hi[j] ? T.real_hi[j] : y);
                     sb[j] = p;
+                    gb[j] = 0.0f;
                     const float g = (x - p) / P.eta_b;
                     acc += g * g;
                 }
@@ -120,13 +126,15 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
                 for (int j = threadIdx.x; j < m; j += blockDim.x) {
                     const float x = sb[j], p = gb[j];
                     sb[j] = p;
+                    gb[j] = 0.0f;
                     const float g = (x - p) / P.eta_b;
                     acc += g * g;
                 }
             }
-            const float gsq = block_sum(acc);
+            const float2 red = block_sum2(oacc, acc);   // also orders the updates before the next sweep
+            obj = red.x;
             ++steps_done;
-            if (gsq <= P.eps2) break;
+            if (red.y <= P.eps2) break;
         }
         // rounding, exact check and ERWA (Alg. "CLS with Annealing")
         const bool update = ((level + 1) % P.tau) == 0;
@@ -212,6 +220,20 @@ static size_t state_floats_of(const fsmt_xbdd *h) {
 
 using namespace fsmt;
 
+// Schedule choice per instance (cost model in units of one wave task): the persistent
+// schedule needs the restart's state in LDS and costs ceil(tasks / waves) sequential tasks
+// per step on one CU; the grid schedule spreads tasks x restarts over all CUs (about 8 waves
+// each) and pays two launches per step (about 20 task-times).
+static bool prefer_grid(const fsmt_xbdd *h, int R, int waves_a, int n_cu) {
+    const double tasks_a = (double)h->n_pos / 64.0;                  // per restart, lane = constraint
+    const double t_a = std::ceil(tasks_a / std::max(1, waves_a));
+    int rp = 1;
+    while (rp < R && rp < 64) rp <<= 1;
+    const double lanes = (double)h->n_pos * (R <= 64 ? rp : std::ceil(R / 64.0) * 64.0);
+    const double t_b = std::ceil(lanes / 64.0 / (8.0 * n_cu)) + 20.0;
+    return t_b < t_a;
+}
+
 extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
                                           const fsmt_solve_state *states, void *stream) {
     clear_error();
@@ -223,28 +245,12 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     if (!(O.eta_a > 0.0f) || !(O.eta_b > 0.0f)) return set_error(FSMT_EINVAL, "step sizes must be positive");
     if (O.tau < 1) return set_error(FSMT_EINVAL, "tau must be >= 1");
     if (!(O.gamma > 0.0f) || !(O.rho >= 0.0f)) return set_error(FSMT_EINVAL, "bad ERWA parameters");
-    if (O.schedule != 0 && O.schedule != 1) return set_error(FSMT_EUNSUPPORTED, "schedule %d not available", O.schedule);
+    if (O.schedule < 0 || O.schedule > 2) return set_error(FSMT_EINVAL, "schedule %d unknown", O.schedule);
+    if (O.stop_on_sat < 0 || O.stop_on_sat > 2) return set_error(FSMT_EINVAL, "stop_on_sat must be 0, 1 or 2");
     for (int t = 0; t < O.n_levels; ++t)
         if (!(O.kappas[t] >= 0.0)) return set_error(FSMT_EINVAL, "kappa[%d] must be in [0, +inf]", t);
 
-    SolveParams P{};
-    P.n_inst = n_inst;
-    P.n_levels = O.n_levels;
-    P.steps = O.steps_per_level;
-    P.tau = O.tau;
-    P.normalize = O.normalize ? 1 : 0;
-    P.stop_mode = O.stop_on_sat;
-    P.eta_a = O.eta_a;
-    P.eta_b = O.eta_b;
-    P.eps2 = O.eps > 0.0f ? O.eps * O.eps : -1.0f;
-    P.rho = O.rho;
-    P.gamma = O.gamma;
-    for (int t = 0; t < O.n_levels; ++t) P.kappas[t] = O.kappas[t];
-
-    std::vector<InstDesc> desc(n_inst);
-    int64_t wg = 0;
-    size_t state_f = 0;
-    int maxn = 0, maxs = 1;
+    // ---- validate states, collect shapes
     int device = -1;
     fsmt_status rc;
     for (int i = 0; i < n_inst; ++i) {
@@ -262,64 +268,240 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             (R > 1 && ((h->n_bool > 0 && S.a.stride_r < h->n_bool) || (h->n_real > 0 && S.b.stride_r < h->n_real))))
             return set_error(FSMT_EINVAL, "instance %d: a and b must be row-major [R][n] with unit column stride", i);
         const void *ptrs[] = {h->n_bool ? S.a.data : nullptr, h->n_real ? S.b.data : nullptr, S.w, S.hist,
-                              S.sat_bits, S.n_unsat, S.verdict, S.level_done, S.steps_done, S.obj};
-        for (int q = 0; q < 10; ++q) {
-            if (!ptrs[q] && q >= 2) return set_error(FSMT_EINVAL, "instance %d: state pointer %d is NULL", i, q);
+                              S.sat_bits, S.n_unsat, S.verdict, S.level_done, S.steps_done, S.obj, S.grad_a, S.grad_b};
+        for (int q = 0; q < 12; ++q) {
+            if (!ptrs[q] && q >= 2 && q < 10) return set_error(FSMT_EINVAL, "instance %d: state pointer %d is NULL", i, q);
             if ((rc = check_device_ptr(ptrs[q], h->device, "state"))) return rc;
         }
-        InstDesc &d = desc[i];
-        d.T = TabView::of(h);
-        d.hs = halfspaces_of(h);
-        d.a = S.a.data;
-        d.b = S.b.data;
-        d.a_sr = S.a.stride_r;
-        d.b_sr = S.b.stride_r;
-        d.w = S.w;
-        d.hist = S.hist;
-        d.sat_bits = S.sat_bits;
-        d.n_unsat = S.n_unsat;
-        d.verdict = S.verdict;
-        d.level_done = S.level_done;
-        d.steps_done = S.steps_done;
-        d.obj = S.obj;
-        d.R = R;
-        d.wg_base = (int32_t)wg;
-        wg += R;
-        state_f = std::max(state_f, state_floats_of(h));
-        maxn = std::max(maxn, h->max_nodes);
-        maxs = std::max(maxs, h->max_slots);
     }
-    if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
-    const int NN = maxn + 2;
-    const size_t wave_bytes = WaveScratch::bytes(NN, maxs);
+
+    // ---- persistent-schedule geometry (max over its instances) and schedule choice
     const size_t budget = (size_t)lds_budget_bytes();
-    const size_t state_bytes = state_f * sizeof(float);
-    if (state_bytes + wave_bytes > budget)
-        return set_error(FSMT_EUNSUPPORTED, "restart state (%zu B) does not fit the persistent schedule's LDS (%zu B)",
-                         state_bytes, budget);
-    const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
-    P.lds_nodes = maxn;
-    P.lds_slots = maxs;
-    P.state_floats = (int32_t)state_f;
-    P.waves = waves;
-    const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+    int n_cu = 256;
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    std::vector<char> use_grid(n_inst, 0);
+    for (int i = 0; i < n_inst; ++i) {
+        const fsmt_xbdd *h = insts[i];
+        const size_t wb = WaveScratch::bytes(h->max_nodes + 2, std::max(h->max_slots, 1));
+        const size_t sb = state_floats_of(h) * sizeof(float);
+        const bool fits = sb + wb <= budget;
+        const int waves = fits ? (int)std::min<size_t>(16, (budget - sb) / wb) : 0;
+        if (O.schedule == 1 && !fits)
+            return set_error(FSMT_EUNSUPPORTED, "instance %d: restart state (%zu B) does not fit the persistent "
+                             "schedule's LDS (%zu B)", i, sb, budget);
+        use_grid[i] = O.schedule == 2 || !fits || (O.schedule == 0 && prefer_grid(h, states[i].a.rows, waves, n_cu));
+    }
 
     hipStream_t st = (hipStream_t)stream;
-    void *dbuf = nullptr;
-    const size_t desc_bytes = sizeof(InstDesc) * (size_t)n_inst;
-    const size_t flag_off = (desc_bytes + 255) / 256 * 256;
-    if (hipMallocAsync(&dbuf, flag_off + sizeof(int32_t) * (size_t)n_inst, st) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_error(FSMT_ENOMEM, "descriptor allocation failed");
+    std::vector<int> ia, ib;
+    for (int i = 0; i < n_inst; ++i) (use_grid[i] ? ib : ia).push_back(i);
+
+    // the grid part runs on a forked stream, concurrently with the persistent launch
+    hipStream_t gst = st;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (!ia.empty() && !ib.empty()) {
+        if (hipStreamCreateWithFlags(&gst, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+            return set_error(FSMT_EHIP, "stream / event creation failed");
+        (void)hipEventRecord(fork, st);
+        (void)hipStreamWaitEvent(gst, fork, 0);
     }
-    int32_t *flags = (int32_t *)((char *)dbuf + flag_off);
-    if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-        fill_i32(flags, n_inst, 0, st) != FSMT_OK) {
-        (void)hipFreeAsync(dbuf, st);
-        return set_error(FSMT_EHIP, "descriptor upload failed");
+
+    rc = FSMT_OK;
+    // ---- persistent schedule
+    if (!ia.empty()) {
+        SolveParams P{};
+        P.n_inst = (int)ia.size();
+        P.n_levels = O.n_levels;
+        P.steps = O.steps_per_level;
+        P.tau = O.tau;
+        P.normalize = O.normalize ? 1 : 0;
+        P.stop_mode = O.stop_on_sat;
+        P.eta_a = O.eta_a;
+        P.eta_b = O.eta_b;
+        P.eps2 = O.eps > 0.0f ? O.eps * O.eps : -1.0f;
+        P.rho = O.rho;
+        P.gamma = O.gamma;
+        for (int t = 0; t < O.n_levels; ++t) P.kappas[t] = O.kappas[t];
+        std::vector<InstDesc> desc(ia.size());
+        int64_t wg = 0;
+        size_t state_f = 0;
+        int maxn = 0, maxs = 1;
+        for (size_t q = 0; q < ia.size(); ++q) {
+            const fsmt_xbdd *h = insts[ia[q]];
+            const fsmt_solve_state &S = states[ia[q]];
+            InstDesc &d = desc[q];
+            d.T = TabView::of(h);
+            d.hs = halfspaces_of(h);
+            d.a = S.a.data;
+            d.b = S.b.data;
+            d.a_sr = S.a.stride_r;
+            d.b_sr = S.b.stride_r;
+            d.w = S.w;
+            d.hist = S.hist;
+            d.sat_bits = S.sat_bits;
+            d.n_unsat = S.n_unsat;
+            d.verdict = S.verdict;
+            d.level_done = S.level_done;
+            d.steps_done = S.steps_done;
+            d.obj = S.obj;
+            d.R = S.a.rows;
+            d.wg_base = (int32_t)wg;
+            wg += d.R;
+            state_f = std::max(state_f, state_floats_of(h));
+            maxn = std::max(maxn, h->max_nodes);
+            maxs = std::max(maxs, h->max_slots);
+        }
+        if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
+        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
+        const size_t state_bytes = state_f * sizeof(float);
+        const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
+        P.lds_nodes = maxn;
+        P.lds_slots = maxs;
+        P.state_floats = (int32_t)state_f;
+        P.waves = waves;
+        const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+        void *dbuf = nullptr;
+        const size_t desc_bytes = sizeof(InstDesc) * desc.size();
+        const size_t flag_off = (desc_bytes + 255) / 256 * 256;
+        if (hipMallocAsync(&dbuf, flag_off + sizeof(int32_t) * desc.size(), st) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(FSMT_ENOMEM, "descriptor allocation failed");
+        } else {
+            int32_t *flags = (int32_t *)((char *)dbuf + flag_off);
+            if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+                fill_i32(flags, (int64_t)desc.size(), 0, st) != FSMT_OK) {
+                rc = set_error(FSMT_EHIP, "descriptor upload failed");
+            } else {
+                hipLaunchKernelGGL(solve_wg_kernel, dim3((unsigned)wg), dim3(64 * waves), lds, st, (const InstDesc *)dbuf,
+                                   P, flags);
+                rc = launch_status("solver kernel");
+            }
+            (void)hipFreeAsync(dbuf, st);
+        }
     }
-    hipLaunchKernelGGL(solve_wg_kernel, dim3((unsigned)wg), dim3(64 * waves), lds, st, (const InstDesc *)dbuf, P, flags);
-    rc = launch_status("solver kernel");
-    (void)hipFreeAsync(dbuf, st);
+
+    // ---- grid schedule
+    if (!ib.empty() && !rc) {
+        std::vector<GridInst> gi(ib.size());
+        int total_r = 0;
+        int64_t tasks = 0, checks = 0, scratch_floats = 0;
+        int maxn = 0, maxs = 1;
+        size_t step_lds = 0;
+        for (size_t q = 0; q < ib.size(); ++q) {
+            const fsmt_xbdd *h = insts[ib[q]];
+            const fsmt_solve_state &S = states[ib[q]];
+            GridInst &d = gi[q];
+            d.T = TabView::of(h);
+            d.hs = halfspaces_of(h);
+            d.a = S.a.data;
+            d.b = S.b.data;
+            d.a_sr = S.a.stride_r;
+            d.b_sr = S.b.stride_r;
+            d.ga = S.grad_a;
+            d.gb = S.grad_b;
+            d.ga_sr = h->n_bool;
+            d.gb_sr = h->n_real;
+            d.w = S.w;
+            d.hist = S.hist;
+            d.sat_bits = S.sat_bits;
+            d.n_unsat = S.n_unsat;
+            d.verdict = S.verdict;
+            d.level_done = S.level_done;
+            d.steps_done = S.steps_done;
+            d.obj = S.obj;
+            d.R = S.a.rows;
+            int rp = 1, lg = 0;
+            while (rp < d.R && rp < 64) { rp <<= 1; ++lg; }
+            d.R_pad = d.R <= 64 ? rp : (d.R + 63) / 64 * 64;
+            d.log2_rpad = d.R <= 64 ? lg : 0;
+            d.rbase = total_r;
+            d.task_base = tasks;
+            d.check_base = checks;
+            total_r += d.R;
+            tasks += d.R <= 64 ? (int64_t)h->n_pos * d.R_pad / 64 : (int64_t)h->n_pos * (d.R_pad / 64);
+            checks += (int64_t)d.R * ((h->n_cons + 255) / 256);
+            if (!S.grad_a || !S.grad_b) scratch_floats += (int64_t)d.R * (h->n_bool + h->n_real);
+            maxn = std::max(maxn, h->max_nodes);
+            maxs = std::max(maxs, h->max_slots);
+            if (h->n_hs) step_lds = std::max(step_lds, (size_t)(2 * h->n_real + h->hs_nnz) * sizeof(float));
+        }
+        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
+        if (wave_bytes > 65536) rc = set_error(FSMT_ELIMIT, "diagram too large for the grid schedule");
+        if (step_lds > 65536) rc = set_error(FSMT_ELIMIT, "projection work arrays exceed LDS");
+        // device scratch: descriptors, kappas, per-restart flags and accumulators, gradients
+        const size_t off_k = (sizeof(GridInst) * gi.size() + 255) / 256 * 256;
+        const size_t off_act = off_k + (sizeof(double) * std::max(1, O.n_levels) + 255) / 256 * 256;
+        const size_t off_stp = off_act + (sizeof(int32_t) * total_r + 255) / 256 * 256;
+        const size_t off_obj = off_stp + (sizeof(int32_t) * total_r + 255) / 256 * 256;
+        const size_t off_flg = off_obj + (sizeof(float) * total_r + 255) / 256 * 256;
+        const size_t off_grd = off_flg + (sizeof(int32_t) * gi.size() + 255) / 256 * 256;
+        const size_t total = off_grd + sizeof(float) * (size_t)scratch_floats + 256;
+        void *buf = nullptr;
+        if (!rc && hipMallocAsync(&buf, total, gst) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(FSMT_ENOMEM, "grid schedule scratch allocation failed");
+        }
+        if (!rc) {
+            char *base = (char *)buf;
+            float *grd = (float *)(base + off_grd);
+            for (GridInst &d : gi) {
+                if (!d.ga || !d.gb) {
+                    d.ga = grd;
+                    d.gb = grd + (int64_t)d.R * d.T.n_bool;
+                    grd += (int64_t)d.R * (d.T.n_bool + d.T.n_real);
+                }
+            }
+            GridShared S{};
+            S.kappas = (const double *)(base + off_k);
+            S.active = (int32_t *)(base + off_act);
+            S.stepping = (int32_t *)(base + off_stp);
+            S.obj_acc = (float *)(base + off_obj);
+            S.stop_flags = (int32_t *)(base + off_flg);
+            S.total_r = total_r;
+            S.n_levels = O.n_levels;
+            S.stop_mode = O.stop_on_sat;
+            S.tau = O.tau;
+            S.normalize = O.normalize ? 1 : 0;
+            S.lds_nodes = maxn;
+            S.lds_slots = maxs;
+            S.eta_a = O.eta_a;
+            S.eta_b = O.eta_b;
+            S.eps2 = O.eps > 0.0f ? O.eps * O.eps : -1.0f;
+            S.rho = O.rho;
+            S.gamma = O.gamma;
+            S.total_tasks = tasks;
+            std::vector<double> kap(O.kappas, O.kappas + O.n_levels);
+            if (hipMemcpyAsync(base, gi.data(), sizeof(GridInst) * gi.size(), hipMemcpyHostToDevice, gst) != hipSuccess ||
+                (O.n_levels > 0 && hipMemcpyAsync(base + off_k, kap.data(), sizeof(double) * kap.size(),
+                                                  hipMemcpyHostToDevice, gst) != hipSuccess) ||
+                fill_i32(S.stop_flags, (int64_t)gi.size(), 0, gst) != FSMT_OK ||
+                fill_f32((float *)(base + off_grd), scratch_floats, 0.0f, gst) != FSMT_OK) {
+                rc = set_error(FSMT_EHIP, "grid schedule upload failed");
+            } else {
+                GridPlan plan{};
+                plan.steps = O.steps_per_level;
+                plan.sweep_wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes));
+                plan.sweep_lds = wave_bytes * plan.sweep_wpb;
+                plan.sweep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tasks + plan.sweep_wpb - 1) / plan.sweep_wpb,
+                                                                               (int64_t)n_cu * 8));
+                plan.step_lds = step_lds;
+                plan.check_blocks = checks;
+                plan.use_graph = true;
+                rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, O.n_levels, gst);
+            }
+            (void)hipFreeAsync(buf, gst);
+        }
+    }
+
+    if (join) {
+        (void)hipEventRecord(join, gst);
+        (void)hipStreamWaitEvent(st, join, 0);
+        (void)hipStreamSynchronize(gst);
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
+        (void)hipStreamDestroy(gst);
+    }
     return rc;
 }

@@ -1,0 +1,289 @@
+// Grid schedule of the batched solver, for instances whose restart state does not fit in
+// LDS (or whose restarts are too few to fill the device from one workgroup each).
+//
+// One annealing level is a fixed sequence of grid-wide kernels over all such instances:
+//   begin  : per restart, decide whether it runs this level; zero its counters
+//   K x  { sweep : forward + reverse sweep of every (constraint, restart) lane of every
+//                  instance (waves as in the per-call kernel, lanes of inactive restarts
+//                  skip their work), gradient scatter into the instance's gradient arrays
+//          step  : per restart (one block), projected step on the box / unit atoms,
+//                  gradient map norm, early end of the level once ||g||^2 <= eps^2 }
+//   check  : exact check of every (constraint, restart)
+//   end    : per restart, ERWA update of its weights, level counter, verdict, stop flag
+// Every kernel reads the level of its restart from device memory, so the sequence is
+// captured once into a hipGraph and replayed once per level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "eval_task.hpp"
+#include "solve_grid.hpp"
+
+namespace fsmt {
+
+__device__ __forceinline__ int find_base32(const GridInst *I, int n, int64_t key, int which) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t b = which == 0 ? I[mid].task_base : which == 1 ? (int64_t)I[mid].rbase : I[mid].check_base;
+        if (b <= key) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per restart: does it run this level?
+__global__ void grid_begin_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= S.total_r) return;
+    const int ii = find_base32(insts, n_inst, g, 1);
+    const GridInst &I = insts[ii];
+    const int r = g - I.rbase;
+    const bool done = I.verdict[r] == 1 && S.stop_mode != 0;
+    const bool stopped = S.stop_mode == 2 && S.stop_flags[ii] != 0;
+    const int act = (!done && !stopped && I.level_done[r] < S.n_levels) ? 1 : 0;
+    S.active[g] = act;
+    S.stepping[g] = act;
+    S.obj_acc[g] = 0.0f;
+    if (act) I.n_unsat[r] = 0;
+}
+
+// Forward + reverse sweep over every instance's (constraint, restart) lanes.
+__global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int NN = S.lds_nodes + 2, SS = S.lds_slots;
+    const WaveScratch W = WaveScratch::at(lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS);
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    // objective partials are carried across this wave's tasks while they stay in one
+    // instance (R <= 64: a lane's restart is fixed there) and flushed on a change
+    int cur = -1, cur_rpad = 64, cur_rbase = 0, cur_R = 0;
+    float oacc = 0.0f;
+    auto flush = [&]() {
+        if (cur < 0) return;
+        for (int off = 32; off >= cur_rpad; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
+        if (lane < cur_rpad && lane < cur_R && oacc != 0.0f) atomic_add_f32(S.obj_acc + cur_rbase + lane, oacc);
+        oacc = 0.0f;
+    };
+    for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < S.total_tasks; task += n_waves) {
+        const int ii = find_base32(insts, n_inst, task, 0);
+        const GridInst &I = insts[ii];
+        const int64_t lt = task - I.task_base;
+        int pos, r;
+        if (I.R_pad <= 64) {
+            pos = (int)(lt * (64 >> I.log2_rpad)) + (lane >> I.log2_rpad);
+            r = lane & (I.R_pad - 1);
+        } else {
+            const int wpc = I.R_pad >> 6;
+            pos = (int)(lt / wpc);
+            r = (int)(lt % wpc) * 64 + lane;
+        }
+        if (ii != cur) {
+            flush();
+            cur = ii;
+            cur_rpad = I.R_pad <= 64 ? I.R_pad : 64;
+            cur_rbase = I.rbase;
+            cur_R = I.R <= 64 ? I.R : 0;
+        }
+        const bool r_ok = r < I.R && S.stepping[I.rbase + r] != 0;
+        const GlobalState st{View{I.a, I.R, I.T.n_bool, I.a_sr, 1}, View{I.b, I.R, I.T.n_real, I.b_sr, 1}};
+        const GlobalScatter sc{View{I.ga, I.R, I.T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, I.T.n_real, I.gb_sr, 1},
+                               I.R_pad < 64 ? I.R_pad : 64};
+        const TaskCtx t = task_ctx(I.T, pos, r, r_ok);
+        const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
+        const bool hard = isinf(kappa);
+        const float unsat = task_forward(I.T, t, st, kappa, hard, W, lane);
+        const float wc = t.valid ? I.w[(int64_t)r * I.T.n_cons + t.c] : 0.0f;
+        if (I.R_pad <= 64) {
+            oacc += wc * unsat;
+        } else if (r < I.R && wc * unsat != 0.0f) {
+            atomic_add_f32(S.obj_acc + I.rbase + r, wc * unsat);
+        }
+        task_backward(I.T, t, wc, sc, W, lane);
+    }
+    flush();
+}
+
+// Projected step, one block per restart.
+__global__ void __launch_bounds__(256) grid_step_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    extern __shared__ float sm[];
+    const int g = blockIdx.x;
+    const int ii = find_base32(insts, n_inst, g, 1);
+    const GridInst &I = insts[ii];
+    const int r = g - I.rbase;
+    if (!S.stepping[g]) return;
+    const int n = I.T.n_bool, m = I.T.n_real;
+    float *arow = I.a + (int64_t)r * I.a_sr, *brow = I.b + (int64_t)r * I.b_sr;
+    float *garow = I.ga + (int64_t)r * I.ga_sr, *gbrow = I.gb + (int64_t)r * I.gb_sr;
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float x = arow[i], y = x - S.eta_a * garow[i];
+        const float p = y < -1.0f ? -1.0f : (y > 1.0f ? 1.0f : y);
+        arow[i] = p;
+        garow[i] = 0.0f;
+        const float q = (x - p) / S.eta_a;
+        acc += q * q;
+    }
+    if (I.hs.n == 0) {
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const float x = brow[j], y = x - S.eta_b * gbrow[j];
+            const float p = y < I.T.real_lo[j] ? I.T.real_lo[j] : (y > I.T.real_hi[j] ? I.T.real_hi[j] : y);
+            brow[j] = p;
+            gbrow[j] = 0.0f;
+            const float q = (x - p) / S.eta_b;
+            acc += q * q;
+        }
+    } else {
+        float *y = sm, *pb = sm + m, *ph = sm + 2 * m;
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            y[j] = brow[j] - S.eta_b * gbrow[j];
+            gbrow[j] = 0.0f;
+        }
+        project_dykstra(y, pb, ph, I.T.real_lo, I.T.real_hi, m, I.hs);
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const float x = brow[j], p = y[j];
+            brow[j] = p;
+            const float q = (x - p) / S.eta_b;
+            acc += q * q;
+        }
+    }
+    const float gsq = block_sum(acc);
+    if (threadIdx.x == 0) {
+        I.obj[r] = S.obj_acc[g];
+        S.obj_acc[g] = 0.0f;
+        I.steps_done[r] += 1;
+        if (gsq <= S.eps2) S.stepping[g] = 0;
+    }
+}
+
+// Exact check: one 256-thread block per (instance, restart, 256-constraint group).
+__global__ void __launch_bounds__(256) grid_check_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = blockIdx.x;
+    const int ii = find_base32(insts, n_inst, blk, 2);
+    const GridInst &I = insts[ii];
+    const int64_t lb = blk - I.check_base;
+    const int groups = (I.T.n_cons + 255) / 256;
+    const int r = (int)(lb / groups);
+    const int c64 = (int)(lb % groups) * 256 + (threadIdx.x & ~63);
+    if (!S.active[I.rbase + r]) return;
+    const int c = c64 + lane;
+    const int C = I.T.n_cons, nw = (C + 31) >> 5;
+    const GlobalState st{View{I.a, I.R, I.T.n_bool, I.a_sr, 1}, View{I.b, I.R, I.T.n_real, I.b_sr, 1}};
+    const bool sat = c < C ? walk_state(I.T, st, c, r) : false;
+    const uint64_t mask = __ballot(sat);
+    const uint64_t valid = __ballot(c < C);
+    if (lane == 0 && valid) {
+        uint32_t *row = I.sat_bits + (int64_t)r * nw;
+        row[c64 >> 5] = (uint32_t)mask;
+        if ((c64 >> 5) + 1 < nw) row[(c64 >> 5) + 1] = (uint32_t)(mask >> 32);
+        atomicAdd(I.n_unsat + r, (int)__popcll(valid & ~mask));
+    }
+}
+
+// ERWA, level counter and verdict, one block per restart.
+__global__ void __launch_bounds__(1024) grid_end_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    const int g = blockIdx.x;
+    const int ii = find_base32(insts, n_inst, g, 1);
+    const GridInst &I = insts[ii];
+    const int r = g - I.rbase;
+    if (!S.active[g]) return;
+    const int C = I.T.n_cons, nw = (C + 31) >> 5;
+    const int level = I.level_done[r];
+    const bool update = ((level + 1) % S.tau) == 0;
+    float *wr = I.w + (int64_t)r * C, *hr = I.hist + (int64_t)r * C;
+    const uint32_t *br = I.sat_bits + (int64_t)r * nw;
+    float ws = 0.0f;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const float viol = ((br[c >> 5] >> (c & 31)) & 1u) ? 0.0f : 1.0f;
+        float h = S.rho * hr[c] + viol, wv = wr[c];
+        if (update) {
+            wv *= powf(S.gamma, h);
+            h = 1.0f;
+            wr[c] = wv;
+        }
+        hr[c] = h;
+        ws += wv;
+    }
+    ws = block_sum(ws);
+    if (update && S.normalize) {
+        const float scale = (float)C / ws;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) wr[c] *= scale;
+    }
+    if (threadIdx.x == 0) {
+        I.level_done[r] = level + 1;
+        if (I.n_unsat[r] == 0) {
+            I.verdict[r] = 1;
+            if (S.stop_mode == 2) atomicExch(S.stop_flags + ii, 1);
+        }
+    }
+}
+
+static fsmt_status launch_status(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(FSMT_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return FSMT_OK;
+}
+
+// Enqueue one level's kernel sequence on st.
+static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
+                                 hipStream_t st) {
+    fsmt_status rc;
+    hipLaunchKernelGGL(grid_begin_kernel, dim3((S.total_r + 255) / 256), dim3(256), 0, st, d_insts, n_inst, S);
+    if ((rc = launch_status("grid begin"))) return rc;
+    for (int k = 0; k < P.steps; ++k) {
+        hipLaunchKernelGGL(grid_sweep_kernel, dim3(P.sweep_blocks), dim3(64 * P.sweep_wpb), P.sweep_lds, st, d_insts,
+                           n_inst, S);
+        if ((rc = launch_status("grid sweep"))) return rc;
+        hipLaunchKernelGGL(grid_step_kernel, dim3(S.total_r), dim3(256), P.step_lds, st, d_insts, n_inst, S);
+        if ((rc = launch_status("grid step"))) return rc;
+    }
+    if (P.check_blocks > 0) {
+        hipLaunchKernelGGL(grid_check_kernel, dim3((unsigned)P.check_blocks), dim3(256), 0, st, d_insts, n_inst, S);
+        if ((rc = launch_status("grid check"))) return rc;
+    }
+    hipLaunchKernelGGL(grid_end_kernel, dim3(S.total_r), dim3(1024), 0, st, d_insts, n_inst, S);
+    return launch_status("grid end");
+}
+
+fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
+                              int n_levels, hipStream_t st) {
+    if (n_levels <= 0 || n_inst == 0) return FSMT_OK;
+    // capture one level into a graph on a private stream, replay it once per level
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = cap != nullptr && P.use_graph;
+    if (use_graph && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) use_graph = false;
+    if (use_graph) {
+        fsmt_status rc = enqueue_level(d_insts, n_inst, S, P, cap);
+        hipError_t e = hipStreamEndCapture(cap, &graph);
+        if (rc || e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            use_graph = false;
+        }
+    }
+    fsmt_status rc = FSMT_OK;
+    for (int t = 0; t < n_levels && !rc; ++t) {
+        if (use_graph) {
+            if (hipGraphLaunch(exec, st) != hipSuccess) rc = set_error(FSMT_EHIP, "hipGraphLaunch failed");
+        } else {
+            rc = enqueue_level(d_insts, n_inst, S, P, st);
+        }
+    }
+    if (exec) {
+        // the executable may be destroyed only after its launches finished
+        (void)hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(exec);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    return rc;
+}
+
+}  // namespace fsmt

@@ -1,0 +1,43 @@
+// Descriptors of the grid schedule of the batched solver (see solve_grid.hip).
+#pragma once
+#include "eval_task.hpp"
+
+namespace fsmt {
+
+struct GridInst {
+    TabView T;
+    HalfSpaces hs;
+    float *a, *b, *ga, *gb;         // row-major [R][n] rows with unit column stride
+    int64_t a_sr, b_sr, ga_sr, gb_sr;
+    float *w, *hist;                // [R][C]
+    uint32_t *sat_bits;
+    int32_t *n_unsat, *verdict, *level_done, *steps_done;
+    float *obj;
+    int32_t R, R_pad, log2_rpad, rbase;   // rbase: first global restart index
+    int64_t task_base;                    // first sweep task (wave) of this instance
+    int64_t check_base;                   // first check block of this instance
+};
+
+struct GridShared {
+    const double *kappas;           // device [n_levels]
+    int32_t *active, *stepping;     // [total_r]
+    float *obj_acc;                 // [total_r]
+    int32_t *stop_flags;            // [n_inst]
+    int32_t total_r, n_levels, stop_mode, tau, normalize;
+    int32_t lds_nodes, lds_slots;
+    float eta_a, eta_b, eps2, rho, gamma;
+    int64_t total_tasks;
+};
+
+struct GridPlan {
+    int steps;
+    int sweep_blocks, sweep_wpb;
+    size_t sweep_lds, step_lds;
+    int64_t check_blocks;
+    bool use_graph;
+};
+
+fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
+                              int n_levels, hipStream_t st);
+
+}  // namespace fsmt

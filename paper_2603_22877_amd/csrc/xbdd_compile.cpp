@@ -430,7 +430,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         const int nc = (int)members[t].size();
         const int npos = (nc + 63) / 64 * 64;
         const int ns = tpls[t].n_slots;
-        BucketInfo bi{t, bstart.back(), npos, nc, (int64_t)sup.size(), 0};
+        const TplInfo &ti = tinfo[t];
+        BucketInfo bi{t, bstart.back(), npos, nc, (int64_t)sup.size(), -1, ti.node_off, ti.n_nodes, ti.n_slots,
+                      ti.n_bslots, ti.root, {0, 0, 0}};
         const int b_id = (int)buckets.size();
         sup.resize(sup.size() + (size_t)ns * npos, 0);
         for (int i = 0; i < npos; ++i) {
@@ -446,6 +448,44 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         bstart.push_back(bstart.back() + npos);
         buckets.push_back(bi);
     }
+    // inline atom records for buckets whose atoms all qualify
+    std::vector<AtomRec> arec;
+    bool all_inline = true;
+    for (BucketInfo &bi : buckets) {
+        const int na = bi.n_slots - bi.n_bslots;
+        if (na == 0) continue;
+        bool ok = true;
+        for (int i = 0; i < bi.n_con && ok; ++i)
+            for (int s = bi.n_bslots; s < bi.n_slots && ok; ++s) {
+                const int k = sup[bi.sup_base + (int64_t)s * bi.n_pos + i] - n;
+                const int e0 = a_ptr[k], e1 = a_ptr[k + 1];
+                ok = (e1 - e0) <= 2 && (double)(float)a_rhs[k] == a_rhs[k] && std::isfinite((float)a_scale[k]);
+                for (int e = e0; e < e1 && ok; ++e) ok = (double)(float)a_coef[e] == a_coef[e];
+            }
+        if (!ok) {
+            all_inline = false;
+            continue;
+        }
+        bi.arec_base = (int64_t)arec.size();
+        arec.resize(arec.size() + (size_t)na * bi.n_pos, AtomRec{0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u});
+        for (int i = 0; i < bi.n_con; ++i)
+            for (int s = bi.n_bslots; s < bi.n_slots; ++s) {
+                const int k = sup[bi.sup_base + (int64_t)s * bi.n_pos + i] - n;
+                const int e0 = a_ptr[k], e1 = a_ptr[k + 1];
+                AtomRec &rr = arec[bi.arec_base + (int64_t)(s - bi.n_bslots) * bi.n_pos + i];
+                rr.v0 = a_var[e0];
+                rr.c0 = (float)a_coef[e0];
+                rr.v1 = (e1 - e0 == 2) ? a_var[e0 + 1] : a_var[e0];
+                rr.c1 = (e1 - e0 == 2) ? (float)a_coef[e0 + 1] : 0.0f;
+                rr.rhs = (float)a_rhs[k];
+                rr.scale = (float)a_scale[k];
+                rr.atom = k;
+                rr.flags = (a_strict[k] ? 1u : 0u) | ((e1 - e0 == 2) ? 2u : 0u);
+            }
+    }
+    std::vector<int32_t> task_bucket((size_t)bstart.back() / 64);
+    for (size_t b = 0; b < buckets.size(); ++b)
+        for (int q = bstart[b] / 64; q < bstart[b + 1] / 64; ++q) task_bucket[q] = (int32_t)b;
     h->n_buckets = (int)buckets.size();
     h->n_pos = bstart.back();
     h->h_tpl = tinfo;
@@ -531,10 +571,20 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.nodes, nodes, "nodes");
     if (!rc) rc = U.put(&h->d.bucket, buckets, "buckets");
     if (!rc) rc = U.put(&h->d.bucket_start, bstart, "bucket starts");
+    if (!rc) rc = U.put(&h->d.task_bucket, task_bucket, "task buckets");
+    if (!rc) rc = U.put(&h->d.arec, arec, "inline atom records");
     if (!rc) rc = U.put(&h->d.pos_con, pos_con, "positions");
     if (!rc) rc = U.put(&h->d.sup, sup, "supports");
     if (!rc) rc = U.put(&h->d.con_bucket, con_bucket, "constraint buckets");
     if (!rc) rc = U.put(&h->d.con_local, con_local, "constraint positions");
+    if (all_inline) {   // every atom is reached through its inline record
+        a_ptr.assign(1, 0);
+        a_var.clear();
+        a_coef.clear();
+        a_rhs.clear();
+        a_scale.clear();
+        a_strict.clear();
+    }
     if (!rc) rc = U.put(&h->d.atom_ptr, a_ptr, "atom offsets");
     if (!rc) rc = U.put(&h->d.atom_var, a_var, "atom variables");
     if (!rc) rc = U.put(&h->d.atom_coef, a_coef, "atom coefficients");

@@ -40,6 +40,7 @@ class SolveConfig:
     tau: int = 1
     normalize: bool = True
     stop_on_sat: int = 2
+    schedule: int = 0        # 0 automatic, 1 persistent, 2 grid
 
     def abi(self):
         kap = (ct.c_double * max(1, len(self.kappas)))(*self.kappas)
@@ -51,7 +52,7 @@ class SolveConfig:
         o.rho, o.gamma, o.tau = float(self.rho), float(self.gamma), int(self.tau)
         o.normalize = int(bool(self.normalize))
         o.stop_on_sat = int(self.stop_on_sat)
-        o.schedule = 0
+        o.schedule = int(self.schedule)
         return o, kap
 
 

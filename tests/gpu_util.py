@@ -9,7 +9,9 @@ torch = pytest.importorskip("torch")
 # Tolerances (floating point parity, FP32 library vs FP64 oracle on identical inputs):
 #  objective U:       |U - U_ref| <= 1e-5 U_ref + 1e-6 sum(w)       (relative, floor near SAT)
 #  per-constraint:    |u - u_ref| <= 1e-5 u_ref + 1e-7
-#  gradient (vector): ||g - g_ref||_2 <= 1e-5 ||g_ref||_2 (+ tiny absolute floor)
+#  gradient (vector): ||g - g_ref||_2 <= 1e-5 ||g_ref||_2 + 1e-6 ||S||_2, S_i = sum_c |dU_c/dv_i|
+#                     (an FP32 sum of mixed-sign terms is accurate relative to the sum of
+#                     magnitudes; the floor is ~8 ulps of it and matters only under cancellation)
 #  gradient (coord):  |g_i - g_ref_i| <= 1e-5 * sum_c |dU_c/dv_i| + 4e-7 * max_i sum_c |dU_c/dv_i|
 REL = 1e-5
 
@@ -40,8 +42,9 @@ def assert_gradient(g, g_ref, absg, name="grad"):
     g = np.asarray(g, np.float64)
     for r in range(g.shape[0]):
         nrm = np.linalg.norm(g_ref[r])
+        floor = 1e-6 * np.linalg.norm(absg[r]) if absg is not None else 0.0
         e = np.linalg.norm(g[r] - g_ref[r])
-        assert e <= REL * nrm + 1e-12, f"{name}[{r}]: ||err|| {e:.3e} vs ||ref|| {nrm:.3e}"
+        assert e <= REL * nrm + floor + 1e-12, f"{name}[{r}]: ||err|| {e:.3e} vs ||ref|| {nrm:.3e}, floor {floor:.3e}"
         if absg is not None and absg.shape[1] > 0:
             tol = REL * absg[r] + 4e-7 * absg[r].max() + 1e-30
             err = np.abs(g[r] - g_ref[r])

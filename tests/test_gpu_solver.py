@@ -22,11 +22,12 @@ def _bits_of(st):
     return st.sat_bits.cpu().numpy().view(np.uint32)
 
 
-def _one_step(p, R, kap, eta_a, eta_b, seed):
+def _one_step(p, R, kap, eta_a, eta_b, seed, schedule=0):
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 50, seed)
     st = S.BatchState(h, a0, b0)
-    cfg = S.SolveConfig(kappas=[kap], steps_per_level=1, eta_a=eta_a, eta_b=eta_b, eps=0.0, stop_on_sat=0)
+    cfg = S.SolveConfig(kappas=[kap], steps_per_level=1, eta_a=eta_a, eta_b=eta_b, eps=0.0, stop_on_sat=0,
+                        schedule=schedule)
     S.solve_batched([h], [st], cfg)
     torch.cuda.synchronize()
     return h, a0, b0, st
@@ -55,11 +56,12 @@ def _assert_step(p, a0, b0, st, kap, eta_a, eta_b):
     assert np.all(st.level_done.cpu().numpy() == 1) and np.all(st.steps_done.cpu().numpy() == 1)
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
 @pytest.mark.parametrize("cfg,R,kap,eta_b", [(1, 4, 0.05, 5.0), (2, 8, 0.1, 5.0), (3, 4, 0.2, 8.0)])
-def test_fused_step_matches_oracle(cfg, R, kap, eta_b):
-    print(f"fused step config {cfg} R={R}", flush=True)
+def test_fused_step_matches_oracle(cfg, R, kap, eta_b, schedule):
+    print(f"fused step config {cfg} R={R} schedule {schedule}", flush=True)
     p = W.make_config(cfg)
-    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg)
+    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg, schedule)
     _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
 
 
@@ -181,3 +183,69 @@ def test_solver_rejects_bad_options():
     with pytest.raises(fsmt.FsmtError):
         S.solve_batched([h], [st], S.SolveConfig(kappas=[-1.0]))
     assert int(st.level_done.max()) == 0
+
+
+def _run(h, a, b, cfg):
+    st = S.BatchState(h, a, b)
+    S.solve_batched([h], [st], cfg)
+    torch.cuda.synchronize()
+    return st
+
+
+@pytest.mark.parametrize("cfg_id,R", [(1, 8), (2, 16), (3, 4)])
+def test_grid_and_persistent_schedules_agree(cfg_id, R):
+    """Both schedules run the same algorithm: over 3 levels x 4 steps (no early exit) the
+    states agree to FP32 accumulation-order noise and the bookkeeping is identical."""
+    p = W.make_config(cfg_id)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 70, cfg_id)
+    kap = S.kappa_schedule(p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)), 3)
+    res = []
+    for sched in (1, 2):
+        cfg = S.SolveConfig(kappas=kap, steps_per_level=4, eta_a=0.5, eta_b=2.0, eps=0.0, stop_on_sat=0,
+                            schedule=sched)
+        res.append(_run(h, a0, b0, cfg))
+    A, B = res
+    np.testing.assert_allclose(A.a.cpu().numpy(), B.a.cpu().numpy(), rtol=0, atol=2e-4)
+    np.testing.assert_allclose(A.b.cpu().numpy(), B.b.cpu().numpy(), rtol=2e-4, atol=2e-4)
+    for k in ("level_done", "steps_done"):
+        np.testing.assert_array_equal(getattr(A, k).cpu().numpy(), getattr(B, k).cpu().numpy())
+    assert np.all(A.steps_done.cpu().numpy() == 12)
+
+
+def test_grid_schedule_early_exit_and_stop_flags():
+    p = W.make_config(2)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, 16, 2, 11)
+    cfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100, eta_a=0.5,
+                        eta_b=5.0, eps=1e-2, stop_on_sat=2, schedule=2)
+    st = _run(h, a0, b0, cfg)
+    ver = st.verdict.cpu().numpy()
+    assert ver.max() == 1
+    steps = st.steps_done.cpu().numpy()
+    assert steps.max() < 100 * int(st.level_done.cpu().numpy().max())     # eps ended levels early
+    r = int(np.argmax(ver))
+    assert oracle.check(p, st.a.cpu().numpy()[r:r + 1], st.b.cpu().numpy()[r:r + 1])["verdict"][0] == 1
+
+
+def test_uneven_batch_mixes_schedules():
+    """Config 4 (48 instances, 16 restarts each): large scheduling instances go to the grid
+    schedule, small ones to the persistent one, in one call; per-instance bookkeeping and
+    check bits are verified against the oracle on a sample of instances."""
+    print("config 4 uneven batch", flush=True)
+    probs = W.make_batch_config4()
+    R = 16
+    hs = [fsmt.xbdd_compile(p) for p in probs]
+    states = [S.BatchState(h, *W.initial_points(p, R, 4, i)) for i, (h, p) in enumerate(zip(hs, probs))]
+    cfg = S.SolveConfig(kappas=[0.05, 0.1], steps_per_level=3, eta_a=0.5, eta_b=2.0, eps=0.0, stop_on_sat=0)
+    S.solve_batched(hs, states, cfg)
+    torch.cuda.synchronize()
+    for st in states:
+        assert np.all(st.level_done.cpu().numpy() == 2) and np.all(st.steps_done.cpu().numpy() == 6)
+    rng = np.random.default_rng(0)
+    big = int(np.argmax([p.n_cons for p in probs]))
+    for i in sorted(set(rng.choice(len(probs), 4, replace=False).tolist() + [big])):
+        p, st = probs[i], states[i]
+        ch = oracle.check(p, st.a.cpu().numpy(), st.b.cpu().numpy())
+        np.testing.assert_array_equal(_bits_of(st), ch["sat_bits"])
+        np.testing.assert_array_equal(st.n_unsat.cpu().numpy(), ch["n_unsat"])
