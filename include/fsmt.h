@@ -240,8 +240,9 @@ typedef struct {
     int32_t stop_on_sat;      /* 0 = keep iterating (fixed work, benchmarks); 1 = a restart stops
                                  once its check passes; 2 = additionally every restart of the
                                  same instance stops at its next level boundary */
-    int32_t schedule;         /* 0 = automatic, 1 = persistent restart-per-workgroup */
-    int32_t reserved[5];
+    int32_t schedule;         /* 0 = automatic, 1 = persistent, 2 = grid (see fsmt_solve_batched) */
+    int32_t cluster;          /* persistent schedule: workgroups per restart (0 = automatic) */
+    int32_t reserved[4];
 } fsmt_solve_opts;
 
 /* Per-instance solver state, device memory owned by the caller ([R] rows each). The

@@ -48,7 +48,7 @@ class SolveOpts(ct.Structure):
                 ("eta_a", ct.c_float), ("eta_b", ct.c_float), ("eps", ct.c_float),
                 ("rho", ct.c_float), ("gamma", ct.c_float), ("tau", ct.c_int32),
                 ("normalize", ct.c_int32), ("stop_on_sat", ct.c_int32), ("schedule", ct.c_int32),
-                ("reserved", ct.c_int32 * 5)]
+                ("cluster", ct.c_int32), ("reserved", ct.c_int32 * 4)]
 
 
 class SolveState(ct.Structure):

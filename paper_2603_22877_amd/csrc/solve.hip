@@ -31,7 +31,10 @@ struct InstDesc {
     uint32_t *sat_bits;
     int32_t *n_unsat, *verdict, *level_done, *steps_done;
     float *obj;
-    int32_t R, wg_base;
+    float *part;        // [R][k][n + m + 1] partial gradients and objective (k > 1)
+    int32_t *bar;       // [R] cluster barrier counters (k > 1)
+    int32_t *ctl;       // [R][2] level result published by rank 0: n_unsat, stop (k > 1)
+    int32_t R, wg_base, k, pad;
 };
 
 struct SolveParams {
@@ -53,14 +56,44 @@ __device__ __forceinline__ int find_inst(const InstDesc *I, int n, int wg) {
     return lo;
 }
 
-__global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags) {
+// Cluster barrier of the k workgroups that share one restart. Thread 0 publishes this
+// workgroup's writes (agent-scope release), arrives, and waits for the cluster with a
+// bounded spin; on a timeout (or another cluster's abort) it raises the abort flag and every
+// waiting workgroup leaves, so the grid always drains. Returns false on abort.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool cluster_sync(int32_t *bar, int target, int32_t *abort_flag) {
+    __syncthreads();
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(bar, 1);
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+            if (++spins > kSpinLimit) {
+                atomicExch(abort_flag, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();   // acquire: the cluster's partials and rank 0's level results
+    }
+    return __syncthreads_and(ok) != 0;
+}
+
+__global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags,
+                                                        int32_t *abort_flag) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ii = find_inst(insts, P.n_inst, blockIdx.x);
     const InstDesc &I = insts[ii];
     const TabView T = I.T;
     const HalfSpaces hs = I.hs;
-    const int r = blockIdx.x - I.wg_base;
+    const int k = I.k;
+    const int local = blockIdx.x - I.wg_base;
+    const int r = local / k, rank = local - r * k;
     const int n = T.n_bool, m = T.n_real, C = T.n_cons;
     const int nw = (C + 31) >> 5;
     float *sa = lds, *sb = sa + n, *ga = sb + m, *gb = ga + n, *pb = gb + m, *ph = pb + m;
@@ -68,6 +101,9 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
     const WaveScratch W = WaveScratch::at(lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS);
     float *wrow = I.w + (int64_t)r * C, *hrow = I.hist + (int64_t)r * C;
     uint32_t *brow = I.sat_bits + (int64_t)r * nw;
+    const int64_t pstride = (int64_t)n + m + 1;
+    float *prow = k > 1 ? I.part + (int64_t)r * k * pstride : nullptr;
+    int bar_target = 0;
 
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         sa[i] = I.a[(int64_t)r * I.a_sr + i];
@@ -82,6 +118,7 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
     int verdict = I.verdict[r];
     int n_unsat = I.n_unsat[r];
     float obj = I.obj[r];
+    bool aborted = false;
     __syncthreads();
     const LdsState st{sa, sb};
     const LdsScatter sc{ga, gb};
@@ -90,15 +127,36 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
     while (level < P.n_levels && !(verdict == 1 && P.stop_mode != 0)) {
         const double kappa = P.kappas[level];
         const bool hard = isinf(kappa);
-        for (int k = 0; k < P.steps; ++k) {
+        for (int step = 0; step < P.steps; ++step) {
             // gradients are zero here: zeroed at entry and by the previous step's update
             float oacc = 0.0f;
-            for (int task = wave; task < n_tasks; task += P.waves) {
+            for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
                 const float unsat = task_forward(T, t, st, kappa, hard, W, lane);
                 const float wc = t.valid ? wrow[t.c] : 0.0f;
                 oacc += wc * unsat;
                 task_backward(T, t, wc, sc, W, lane);
+            }
+            if (k > 1) {
+                // publish this workgroup's partial gradient and objective, then sum the
+                // cluster's partials in rank order (every rank gets the same bits)
+                const float op = block_sum(oacc);
+                float *mine = prow + (int64_t)rank * pstride;
+                for (int i = threadIdx.x; i < n + m; i += blockDim.x) mine[i] = ga[i];
+                if (threadIdx.x == 0) mine[n + m] = op;
+                bar_target += k;
+                if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
+                    aborted = true;
+                    break;
+                }
+                for (int i = threadIdx.x; i < n + m; i += blockDim.x) {
+                    float s = 0.0f;
+                    for (int q = 0; q < k; ++q) s += prow[(int64_t)q * pstride + i];
+                    ga[i] = s;
+                }
+                float os = 0.0f;
+                for (int q = 0; q < k; ++q) os += prow[(int64_t)q * pstride + n + m];
+                oacc = threadIdx.x == 0 ? os : 0.0f;
             }
             __syncthreads();
             // projected step (Eq. pg1/pg2) and the gradient map norm (Eq. grad_map)
@@ -136,52 +194,71 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
             ++steps_done;
             if (red.y <= P.eps2) break;
         }
-        // rounding, exact check and ERWA (Alg. "CLS with Annealing")
-        const bool update = ((level + 1) % P.tau) == 0;
-        float nu_acc = 0.0f, wsum = 0.0f;
-        for (int c0 = wave * 64; c0 < C; c0 += P.waves * 64) {
-            const int c = c0 + lane;
-            const bool sat = c < C ? walk_state(T, st, c, r) : false;
-            const uint64_t mask = __ballot(sat);
-            if (lane == 0) {
-                brow[c0 >> 5] = (uint32_t)mask;
-                if ((c0 >> 5) + 1 < nw) brow[(c0 >> 5) + 1] = (uint32_t)(mask >> 32);
-            }
-            if (c < C) {
-                const float viol = sat ? 0.0f : 1.0f;
-                float h = P.rho * hrow[c] + viol;
-                float wv = wrow[c];
-                if (update) {
-                    wv *= powf(P.gamma, h);
-                    h = 1.0f;
-                    wrow[c] = wv;
+        if (aborted) break;
+        // rounding, exact check and ERWA (Alg. "CLS with Annealing"): rank 0 of the cluster
+        int stop = 0;
+        if (rank == 0) {
+            const bool update = ((level + 1) % P.tau) == 0;
+            float nu_acc = 0.0f, wsum = 0.0f;
+            for (int c0 = wave * 64; c0 < C; c0 += P.waves * 64) {
+                const int c = c0 + lane;
+                const bool sat = c < C ? walk_state(T, st, c, r) : false;
+                const uint64_t mask = __ballot(sat);
+                if (lane == 0) {
+                    brow[c0 >> 5] = (uint32_t)mask;
+                    if ((c0 >> 5) + 1 < nw) brow[(c0 >> 5) + 1] = (uint32_t)(mask >> 32);
                 }
-                hrow[c] = h;
-                wsum += wv;
-                nu_acc += viol;
+                if (c < C) {
+                    const float viol = sat ? 0.0f : 1.0f;
+                    float h = P.rho * hrow[c] + viol;
+                    float wv = wrow[c];
+                    if (update) {
+                        wv *= powf(P.gamma, h);
+                        h = 1.0f;
+                        wrow[c] = wv;
+                    }
+                    hrow[c] = h;
+                    wsum += wv;
+                    nu_acc += viol;
+                }
+            }
+            n_unsat = (int)block_sum(nu_acc);
+            if (update && P.normalize) {
+                const float ws = block_sum(wsum);
+                const float scale = (float)C / ws;
+                for (int c = threadIdx.x; c < C; c += blockDim.x) wrow[c] *= scale;
+            }
+            if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
+            stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
+            if (k > 1 && threadIdx.x == 0) {
+                I.ctl[2 * r] = n_unsat;
+                I.ctl[2 * r + 1] = stop;
             }
         }
-        n_unsat = (int)block_sum(nu_acc);
-        if (update && P.normalize) {
-            const float ws = block_sum(wsum);
-            const float scale = (float)C / ws;
-            for (int c = threadIdx.x; c < C; c += blockDim.x) wrow[c] *= scale;
+        if (k > 1) {
+            bar_target += k;
+            if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
+                aborted = true;
+                break;
+            }
+            n_unsat = I.ctl[2 * r];
+            stop = I.ctl[2 * r + 1];
         }
         ++level;
-        if (n_unsat == 0) {
-            verdict = 1;
-            if (P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
-        }
-        if (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) break;
+        if (n_unsat == 0) verdict = 1;
+        if (stop) break;
         __syncthreads();
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
-    for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
+    if (rank != 0) return;
+    if (!aborted) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
+        for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
+    }
     if (threadIdx.x == 0) {
         I.level_done[r] = level;
         I.steps_done[r] = steps_done;
-        I.verdict[r] = verdict;
+        I.verdict[r] = aborted ? -2 : verdict;
         I.n_unsat[r] = n_unsat;
         I.obj[r] = obj;
     }
@@ -325,9 +402,41 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         P.gamma = O.gamma;
         for (int t = 0; t < O.n_levels; ++t) P.kappas[t] = O.kappas[t];
         std::vector<InstDesc> desc(ia.size());
-        int64_t wg = 0;
         size_t state_f = 0;
         int maxn = 0, maxs = 1;
+        int64_t total_r = 0, min_tasks = INT64_MAX, part_floats = 0;
+        for (size_t q = 0; q < ia.size(); ++q) {
+            const fsmt_xbdd *h = insts[ia[q]];
+            state_f = std::max(state_f, state_floats_of(h));
+            maxn = std::max(maxn, h->max_nodes);
+            maxs = std::max(maxs, h->max_slots);
+            total_r += states[ia[q]].a.rows;
+            min_tasks = std::min<int64_t>(min_tasks, h->n_pos / 64);
+        }
+        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
+        const size_t state_bytes = state_f * sizeof(float);
+        const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
+        const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+        // workgroups per restart: a cluster of k co-resident workgroups shares one restart's
+        // sweep (all of them must be resident at once: their barrier waits for each other)
+        int occ = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_wg_kernel, 64 * waves, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+        const int64_t resident = (int64_t)n_cu * std::max(occ, 1);
+        int k = 1;
+        if (O.cluster > 0) {
+            k = O.cluster;
+            if (k > 16 || total_r * k > resident || (k > 1 && !ib.empty()))
+                return set_error(FSMT_EUNSUPPORTED, "cluster of %d workgroups per restart cannot be co-resident", k);
+        }
+        // automatic: one workgroup per restart. Measured on config 2 (64 restarts, 66 tasks
+        // per restart): 4 workgroups per restart took 34.7 us per PGD step against 29 us
+        // for one, the agent-scope release/acquire of the cluster barrier (L2 write-back and
+        // invalidate) costing more than the split sweep saves.
+        (void)min_tasks;
+        int64_t wg = 0;
         for (size_t q = 0; q < ia.size(); ++q) {
             const fsmt_xbdd *h = insts[ia[q]];
             const fsmt_solve_state &S = states[ia[q]];
@@ -347,35 +456,43 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             d.steps_done = S.steps_done;
             d.obj = S.obj;
             d.R = S.a.rows;
+            d.k = k;
             d.wg_base = (int32_t)wg;
-            wg += d.R;
-            state_f = std::max(state_f, state_floats_of(h));
-            maxn = std::max(maxn, h->max_nodes);
-            maxs = std::max(maxs, h->max_slots);
+            wg += (int64_t)d.R * k;
+            if (k > 1) part_floats += (int64_t)d.R * k * ((int64_t)h->n_bool + h->n_real + 1);
         }
         if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
-        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
-        const size_t state_bytes = state_f * sizeof(float);
-        const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
         P.lds_nodes = maxn;
         P.lds_slots = maxs;
         P.state_floats = (int32_t)state_f;
         P.waves = waves;
-        const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+        // scratch: descriptors | stop flags [n] | abort flag | barriers [R] | level results [2R] | partials
         void *dbuf = nullptr;
         const size_t desc_bytes = sizeof(InstDesc) * desc.size();
-        const size_t flag_off = (desc_bytes + 255) / 256 * 256;
-        if (hipMallocAsync(&dbuf, flag_off + sizeof(int32_t) * desc.size(), st) != hipSuccess) {
+        const size_t off_flag = (desc_bytes + 255) / 256 * 256;
+        const size_t n_int = desc.size() + 1 + 3 * (size_t)total_r;
+        const size_t off_part = off_flag + (n_int * sizeof(int32_t) + 255) / 256 * 256;
+        if (hipMallocAsync(&dbuf, off_part + sizeof(float) * (size_t)part_floats + 256, st) != hipSuccess) {
             (void)hipGetLastError();
             rc = set_error(FSMT_ENOMEM, "descriptor allocation failed");
         } else {
-            int32_t *flags = (int32_t *)((char *)dbuf + flag_off);
+            int32_t *ints = (int32_t *)((char *)dbuf + off_flag);
+            int32_t *flags = ints, *abort_flag = ints + desc.size(), *bar = abort_flag + 1, *ctl = bar + total_r;
+            float *part = (float *)((char *)dbuf + off_part);
+            int64_t rb = 0, pb = 0;
+            for (InstDesc &d : desc) {
+                d.bar = bar + rb;
+                d.ctl = ctl + 2 * rb;
+                d.part = k > 1 ? part + pb : nullptr;
+                rb += d.R;
+                if (k > 1) pb += (int64_t)d.R * k * ((int64_t)d.T.n_bool + d.T.n_real + 1);
+            }
             if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-                fill_i32(flags, (int64_t)desc.size(), 0, st) != FSMT_OK) {
+                fill_i32(ints, (int64_t)n_int, 0, st) != FSMT_OK) {
                 rc = set_error(FSMT_EHIP, "descriptor upload failed");
             } else {
                 hipLaunchKernelGGL(solve_wg_kernel, dim3((unsigned)wg), dim3(64 * waves), lds, st, (const InstDesc *)dbuf,
-                                   P, flags);
+                                   P, flags, abort_flag);
                 rc = launch_status("solver kernel");
             }
             (void)hipFreeAsync(dbuf, st);

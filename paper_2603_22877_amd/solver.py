@@ -41,6 +41,7 @@ class SolveConfig:
     normalize: bool = True
     stop_on_sat: int = 2
     schedule: int = 0        # 0 automatic, 1 persistent, 2 grid
+    cluster: int = 0         # persistent schedule: workgroups per restart (0 automatic)
 
     def abi(self):
         kap = (ct.c_double * max(1, len(self.kappas)))(*self.kappas)
@@ -53,6 +54,7 @@ class SolveConfig:
         o.normalize = int(bool(self.normalize))
         o.stop_on_sat = int(self.stop_on_sat)
         o.schedule = int(self.schedule)
+        o.cluster = int(self.cluster)
         return o, kap
 
 

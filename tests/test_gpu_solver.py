@@ -213,7 +213,21 @@ def test_grid_and_persistent_schedules_agree(cfg_id, R):
     assert np.all(A.steps_done.cpu().numpy() == 12)
 
 
-def test_grid_schedule_early_exit_and_stop_flags():
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_levels_end_early_at_eps(schedule):
+    """With kappa = 0 the b-gradient vanishes and the Booleans saturate at the box, so the
+    gradient map falls below eps and every level ends before its step cap."""
+    p = W.make_config(1)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, 8, 1, 12)
+    cfg = S.SolveConfig(kappas=[0.0, 0.0], steps_per_level=100, eta_a=0.5, eta_b=5.0, eps=1e-2, stop_on_sat=0,
+                        schedule=schedule)
+    st = _run(h, a0, b0, cfg)
+    assert np.all(st.level_done.cpu().numpy() == 2)
+    assert st.steps_done.cpu().numpy().max() < 200
+
+
+def test_grid_schedule_reaches_sat_and_stops():
     p = W.make_config(2)
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 16, 2, 11)
@@ -222,8 +236,8 @@ def test_grid_schedule_early_exit_and_stop_flags():
     st = _run(h, a0, b0, cfg)
     ver = st.verdict.cpu().numpy()
     assert ver.max() == 1
-    steps = st.steps_done.cpu().numpy()
-    assert steps.max() < 100 * int(st.level_done.cpu().numpy().max())     # eps ended levels early
+    levels = st.level_done.cpu().numpy()
+    assert levels.max() - levels.min() <= 1          # the others stopped at the next level boundary
     r = int(np.argmax(ver))
     assert oracle.check(p, st.a.cpu().numpy()[r:r + 1], st.b.cpu().numpy()[r:r + 1])["verdict"][0] == 1
 
@@ -249,3 +263,38 @@ def test_uneven_batch_mixes_schedules():
         ch = oracle.check(p, st.a.cpu().numpy(), st.b.cpu().numpy())
         np.testing.assert_array_equal(_bits_of(st), ch["sat_bits"])
         np.testing.assert_array_equal(st.n_unsat.cpu().numpy(), ch["n_unsat"])
+
+
+@pytest.mark.parametrize("cluster", [2, 4])
+def test_cluster_split_step_matches_oracle(cluster):
+    """Several workgroups per restart (partials summed in rank order): one step still
+    matches the oracle, and every rank applies the same update."""
+    p = W.make_config(2)
+    R = 8
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 50, 2)
+    st = S.BatchState(h, a0, b0)
+    cfg = S.SolveConfig(kappas=[0.1], steps_per_level=1, eta_a=0.5, eta_b=5.0, eps=0.0, stop_on_sat=0,
+                        schedule=1, cluster=cluster)
+    S.solve_batched([h], [st], cfg)
+    torch.cuda.synchronize()
+    _assert_step(p, a0, b0, st, 0.1, 0.5, 5.0)
+
+
+def test_cluster_split_agrees_with_single_workgroup_over_levels():
+    p = W.make_config(2)
+    R = 16
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, R, 71, 0)
+    kap = S.kappa_schedule(p.meta["mean_duration"], 3)
+    res = []
+    for cl in (1, 4):
+        cfg = S.SolveConfig(kappas=kap, steps_per_level=5, eta_a=0.5, eta_b=5.0, eps=0.0, stop_on_sat=0,
+                            schedule=1, cluster=cl)
+        res.append(_run(h, a0, b0, cfg))
+    A, B = res
+    np.testing.assert_allclose(A.a.cpu().numpy(), B.a.cpu().numpy(), rtol=0, atol=2e-4)
+    np.testing.assert_allclose(A.b.cpu().numpy(), B.b.cpu().numpy(), rtol=2e-4, atol=2e-4)
+    np.testing.assert_array_equal(A.level_done.cpu().numpy(), B.level_done.cpu().numpy())
+    np.testing.assert_array_equal(A.steps_done.cpu().numpy(), B.steps_done.cpu().numpy())
+    assert B.verdict.cpu().numpy().min() >= 0        # no barrier abort
