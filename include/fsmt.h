@@ -90,13 +90,21 @@ enum {
     FSMT_PROJ_BOX = 1     /* the box [-1,1]^n x [real_lo, real_hi] only */
 };
 
+/* Where the diagram passes keep a lane's node messages (Eq. "dp" forward masses and
+ * reverse probabilities). Both give the same results; the choice is performance only. */
+enum {
+    FSMT_MSG_AUTO = 0,    /* registers when the largest diagram fits a compiled bound, else LDS */
+    FSMT_MSG_LDS = 1      /* always the wave's LDS columns (any diagram size) */
+};
+
 typedef struct {
     int32_t device;            /* HIP device that holds the tables (-1 = current device,
                                   FSMT_HOST_ONLY = no upload: only xbdd_info and
                                   xbdd_export_diagram accept such a handle) */
     int32_t max_nodes;         /* reject diagrams with more decision nodes (0 = 1024) */
     int32_t projection;        /* FSMT_PROJ_UNIT or FSMT_PROJ_BOX */
-    int32_t reserved[5];
+    int32_t messages;          /* FSMT_MSG_AUTO or FSMT_MSG_LDS */
+    int32_t reserved[4];
 } fsmt_compile_opts;
 
 typedef struct {

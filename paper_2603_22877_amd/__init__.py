@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import FSMT_ACCUMULATE, FSMT_HOST_ONLY, FSMT_PROJ_BOX, FSMT_PROJ_UNIT, FsmtError  # noqa: F401
+from ._abi import (FSMT_ACCUMULATE, FSMT_HOST_ONLY, FSMT_MSG_AUTO, FSMT_MSG_LDS, FSMT_PROJ_BOX,  # noqa: F401
+                   FSMT_PROJ_UNIT, FsmtError)
 
 __all__ = ["XBDD", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram", "cop_forward",
            "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "FsmtError",
@@ -60,11 +61,13 @@ class XBDD:
 
 
 def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0,
-                 projection: int = 0) -> XBDD:
+                 projection: int = 0, messages: int = 0) -> XBDD:
     """Compile a problem (object with the ``workloads.format.Problem`` arrays).
 
     ``device``: HIP device index, None for the current one, or FSMT_HOST_ONLY.
     ``projection``: FSMT_PROJ_UNIT (box + unit atoms, default) or FSMT_PROJ_BOX.
+    ``messages``: FSMT_MSG_AUTO (registers when the diagrams are small, default) or
+    FSMT_MSG_LDS.
     """
     keep = {}
     s = _abi.Problem()
@@ -80,6 +83,7 @@ def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0,
     o.device = -1 if device is None else int(device)
     o.max_nodes = int(max_nodes)
     o.projection = int(projection)
+    o.messages = int(messages)
     out = ct.c_void_p()
     _abi.check(lib().xbdd_compile(ct.byref(s), ct.byref(o), ct.byref(out)))
     return XBDD(out.value, problem)

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libfsmt.so")
 FSMT_OK, FSMT_EINVAL, FSMT_ENOMEM, FSMT_EUNSUPPORTED, FSMT_ELIMIT, FSMT_EHIP = 0, -1, -2, -3, -4, -5
 FSMT_HOST_ONLY = -2
 FSMT_PROJ_UNIT, FSMT_PROJ_BOX = 0, 1
+FSMT_MSG_AUTO, FSMT_MSG_LDS = 0, 1
 FSMT_ACCUMULATE = 1
 
 EXPORTED = ["fsmt_last_error", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram",
@@ -27,7 +28,7 @@ class Problem(ct.Structure):
 
 class CompileOpts(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("max_nodes", ct.c_int32), ("projection", ct.c_int32),
-                ("reserved", ct.c_int32 * 5)]
+                ("messages", ct.c_int32), ("reserved", ct.c_int32 * 4)]
 
 
 class Stats(ct.Structure):

@@ -18,6 +18,9 @@ ARCH = os.environ.get("FSMT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off (they are not used by hand anywhere either)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # let the register-resident diagram messages (about 100 floats a lane) be promoted
+         # to VGPRs as a whole; the default budget leaves one array in scratch memory
+         "-mllvm", "-amdgpu-promote-alloca-to-vector-limit=8192",
          "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 
 

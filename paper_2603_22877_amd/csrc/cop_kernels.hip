@@ -40,8 +40,9 @@ struct CopArgs {
     int32_t lds_nodes, lds_slots;  // per-wave LDS geometry (max over templates)
 };
 
-template <bool kGrad>
+template <bool kGrad, int V>
 __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
+    using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -49,7 +50,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     const int64_t wave0 = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
     const int NN = A.lds_nodes + 2, SS = A.lds_slots;
-    const WaveScratch W = WaveScratch::at(lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS);
+    FSMT_MSG_STORE(Ms, W, lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS, lane);
     const GlobalState st{A.a, A.b};
     const GlobalScatter sc{A.ga, A.gb, A.R_pad < 64 ? A.R_pad : 64};
     float oacc = 0.0f;   // objective partial of this lane's restart (R_pad <= 64: fixed per lane)
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
             r = (int)(task % wpc) * 64 + lane;
         }
         const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
-        const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W, lane);
+        const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W);
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         if (A.obj) {
@@ -299,10 +300,11 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         if ((rc = check_device_ptr(ptrs[i], h->device, names[i]))) return rc;
 
     const int NN = h->max_nodes + 2, SS = std::max(h->max_slots, 1);
-    const size_t wave_bytes = (size_t)(2 * NN + 4 * SS) * 64 * sizeof(float);
+    const int msg = msg_variant(h->max_nodes, h->max_slots, h->lds_messages);
+    const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(NN, SS) : 0;
     if (wave_bytes > 65536)
         return set_error(FSMT_ELIMIT, "diagram too large for the LDS-resident pass (%d nodes, %d slots)", h->max_nodes, h->max_slots);
-    int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes));
+    const int wpb = wave_bytes ? (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes)) : 4;
 
     if (!(flags & FSMT_ACCUMULATE)) {
         if (obj && (rc = fill_f32(obj, R, 0.0f, st))) return rc;
@@ -339,10 +341,16 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const int64_t waves = std::min<int64_t>(A.n_tasks, max_waves);
     const int blocks = (int)((waves + wpb - 1) / wpb);
     const size_t lds = wave_bytes * wpb;
-    if (grad)
-        hipLaunchKernelGGL(cop_kernel<true>, dim3(blocks), dim3(64 * wpb), lds, st, A);
-    else
-        hipLaunchKernelGGL(cop_kernel<false>, dim3(blocks), dim3(64 * wpb), lds, st, A);
+    const dim3 g(blocks), bl(64 * wpb);
+    if (grad) {
+        if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<true, kMsgSmall>), g, bl, 0, st, A);
+        else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<true, kMsgMedium>), g, bl, 0, st, A);
+        else hipLaunchKernelGGL((cop_kernel<true, kMsgLds>), g, bl, lds, st, A);
+    } else {
+        if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<false, kMsgSmall>), g, bl, 0, st, A);
+        else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<false, kMsgMedium>), g, bl, 0, st, A);
+        else hipLaunchKernelGGL((cop_kernel<false, kMsgLds>), g, bl, lds, st, A);
+    }
     return launch_status("cop kernel");
 }
 

@@ -208,95 +208,162 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
     return t;
 }
 
+// ---- message stores
+// A store holds one lane's forward masses M and reverse probabilities Bm per node (plus the
+// two terminals) and P = P[literal True], Q = 1 - P, D = dp/dz, G = dP[False]/dp per slot.
+//
+// RegMsgs keeps them in VGPRs: the diagram size is bounded at compile time, so every loop
+// over nodes or slots unrolls (guarded by the bucket's actual sizes), static indices become
+// plain registers, and the wave-uniform child and slot indices read from a node record
+// address the arrays through gfx950's GPR indexing. The node chain then runs at register
+// latency and no LDS is needed. LdsMsgs keeps them in the wave's LDS columns ([row][lane])
+// for diagrams of any size.
+template <int NM, int SM>
+struct RegMsgs {
+    static constexpr int kNodes = NM, kSlots = SM;
+    static constexpr int kArrNodes = NM + 2, kArrSlots = SM;
+    // the arrays are separate locals of the kernel (see bind_msgs): a single aggregate
+    // indexed dynamically would not be split into registers
+    float *m_, *b_, *p_, *q_, *d_, *g_;
+    __device__ __forceinline__ float &M(int v) { return m_[v]; }
+    __device__ __forceinline__ float &Bm(int v) { return b_[v]; }
+    __device__ __forceinline__ float &P(int s) { return p_[s]; }
+    __device__ __forceinline__ float &Q(int s) { return q_[s]; }
+    __device__ __forceinline__ float &D(int s) { return d_[s]; }
+    __device__ __forceinline__ float &G(int s) { return g_[s]; }
+};
+
+struct LdsMsgs {
+    static constexpr int kNodes = 0, kSlots = 0;   // unbounded
+    static constexpr int kArrNodes = 1, kArrSlots = 1;
+    WaveScratch W;
+    int lane;
+    __device__ __forceinline__ float &M(int v) { return W.M[v * 64 + lane]; }
+    __device__ __forceinline__ float &Bm(int v) { return W.Bm[v * 64 + lane]; }
+    __device__ __forceinline__ float &P(int s) { return W.P[s * 64 + lane]; }
+    __device__ __forceinline__ float &Q(int s) { return W.Q[s * 64 + lane]; }
+    __device__ __forceinline__ float &D(int s) { return W.D[s * 64 + lane]; }
+    __device__ __forceinline__ float &G(int s) { return W.G[s * 64 + lane]; }
+};
+
+// for (i = lo; i < n; ++i) f(i), fully unrolled over [lo, K) when the bound K is static
+template <int K, class F>
+__device__ __forceinline__ void for_up(int lo, int n, F &&f) {
+    if constexpr (K > 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i >= lo && i < n) f(i);
+    } else {
+        for (int i = lo; i < n; ++i) f(i);
+    }
+}
+// for (i = n - 1; i >= 0; --i) f(i)
+template <int K, class F>
+__device__ __forceinline__ void for_down(int n, F &&f) {
+    if constexpr (K > 0) {
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i)
+            if (i < n) f(i);
+    } else {
+        for (int i = n - 1; i >= 0; --i) f(i);
+    }
+}
+
+// Literal probability of one atom slot under Gaussian smoothing (Eq. "sampling"):
+// p = erfc(u) / 2 with u = kappa * scale * z, z = q.b - q0 and scale = 1 / (sqrt 2 |q|)
+// fixed at compile time, and its derivative dp/dz. Hard mode (kappa = inf) is the
+// indicator of the atom at b.
+__device__ __forceinline__ void atom_literal(double z, double scale, bool strict, double kappa, bool hard,
+                                             float &p, float &q, float &d) {
+    if (hard) {
+        const bool tr = strict ? (z < 0.0) : (z <= 0.0);
+        p = tr ? 1.0f : 0.0f;
+        q = tr ? 0.0f : 1.0f;
+        d = 0.0f;
+    } else {
+        const double ks = kappa * scale;
+        const float u = (float)(z * ks);
+        const float e = 0.5f * erfcf(fabsf(u));          // the smaller of p, 1-p
+        p = (u >= 0.0f) ? e : 1.0f - e;
+        q = (u >= 0.0f) ? 1.0f - e : e;
+        if (u != u) { p = u; q = u; }                    // NaN in, NaN out
+        d = -(float)(ks * 0.56418958354775628695) * expf(-u * u);   // dp/dz = -k s/sqrt(pi) e^-u^2
+    }
+}
+
 // Literal probabilities and the forward pass; returns P[c False] (0 for invalid lanes).
-template <class St>
+template <class St, class Ms>
 __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t, const St &st, double kappa,
-                                              bool hard, const WaveScratch &W, int lane) {
+                                              bool hard, Ms &W) {
+    constexpr int KN = Ms::kNodes, KS = Ms::kSlots;
     const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
-    for (int s = 0; s < NB; ++s) {
+    for_up<KS>(0, NB, [&](int s) {
         const float av = t.valid ? st.av(t.r, t.sup[(int64_t)s * np]) : 0.0f;
-        W.P[s * 64 + lane] = (1.0f - av) * 0.5f;
-        W.Q[s * 64 + lane] = (1.0f + av) * 0.5f;
-    }
-    for (int s = NB; s < S; ++s) {
+        W.P(s) = (1.0f - av) * 0.5f;
+        W.Q(s) = (1.0f + av) * 0.5f;
+    });
+    for_up<KS>(NB, S, [&](int s) {
         float p = 0.5f, q = 0.5f, d = 0.0f;
         if (t.valid) {
-            double z, scale;
-            bool strict;
             if (t.rec) {
                 const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
-                z = rec_z(a, st, t.r);
-                scale = (double)a.scale;
-                strict = (a.flags & 1u) != 0;
+                atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p, q, d);
             } else {
                 const int k = t.sup[(int64_t)s * np] - T.n_bool;
-                z = atom_z_state(T, k, st, t.r);
-                scale = T.atom_scale[k];
-                strict = T.atom_strict[k] != 0;
-            }
-            if (hard) {
-                const bool tr = strict ? (z < 0.0) : (z <= 0.0);
-                p = tr ? 1.0f : 0.0f;
-                q = tr ? 0.0f : 1.0f;
-            } else {
-                const double ks = kappa * scale;
-                const float u = (float)(z * ks);
-                const float e = 0.5f * erfcf(fabsf(u));          // the smaller of p, 1-p
-                p = (u >= 0.0f) ? e : 1.0f - e;
-                q = (u >= 0.0f) ? 1.0f - e : e;
-                if (u != u) { p = u; q = u; }                    // NaN in, NaN out
-                d = -(float)(ks * 0.56418958354775628695) * expf(-u * u);   // dp/dz = -k s/sqrt(pi) e^-u^2
+                atom_literal(atom_z_state(T, k, st, t.r), T.atom_scale[k], T.atom_strict[k] != 0, kappa, hard, p, q,
+                             d);
             }
         }
-        W.P[s * 64 + lane] = p;
-        W.Q[s * 64 + lane] = q;
-        W.D[s * 64 + lane] = d;
-    }
-    for (int v = 0; v < N + 2; ++v) W.M[v * 64 + lane] = 0.0f;
-    W.M[t.B.root * 64 + lane] = 1.0f;
+        W.P(s) = p;
+        W.Q(s) = q;
+        W.D(s) = d;
+    });
+    for_up<(KN > 0 ? KN + 2 : 0)>(0, N + 2, [&](int v) { W.M(v) = 0.0f; });
+    W.M(t.B.root) = 1.0f;
     const Node *nd = T.nodes + t.B.node_off;
-    for (int v = 0; v < N; ++v) {
+    for_up<KN>(0, N, [&](int v) {
         const Node x = load_node(nd + v);
-        const float mv = W.M[v * 64 + lane];
-        W.M[x.hi * 64 + lane] += W.P[x.slot * 64 + lane] * mv;
-        W.M[x.lo * 64 + lane] += W.Q[x.slot * 64 + lane] * mv;
-    }
-    return t.valid ? W.M[(N + 1) * 64 + lane] : 0.0f;
+        const float mv = W.M(v);
+        W.M(x.hi) += W.P(x.slot) * mv;
+        W.M(x.lo) += W.Q(x.slot) * mv;
+    });
+    return t.valid ? W.M(N + 1) : 0.0f;
 }
 
 // Reverse pass and chain rule; scatters w * dP[c False]/d(state) through the policy.
-template <class Sc>
-__device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t, float wc, const Sc &sc,
-                                              const WaveScratch &W, int lane) {
+template <class Sc, class Ms>
+__device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t, float wc, const Sc &sc, Ms &W,
+                                              int lane) {
+    constexpr int KN = Ms::kNodes, KS = Ms::kSlots;
     const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
-    for (int s = 0; s < S; ++s) W.G[s * 64 + lane] = 0.0f;
-    W.Bm[N * 64 + lane] = 0.0f;
-    W.Bm[(N + 1) * 64 + lane] = 1.0f;
+    for_up<KS>(0, S, [&](int s) { W.G(s) = 0.0f; });
+    W.Bm(N) = 0.0f;
+    W.Bm(N + 1) = 1.0f;
     const Node *nd = T.nodes + t.B.node_off;
-    for (int v = N - 1; v >= 0; --v) {
+    for_down<KN>(N, [&](int v) {
         const Node x = load_node(nd + v);
-        const float bh = W.Bm[x.hi * 64 + lane], bl = W.Bm[x.lo * 64 + lane];
-        W.Bm[v * 64 + lane] = W.P[x.slot * 64 + lane] * bh + W.Q[x.slot * 64 + lane] * bl;
-        W.G[x.slot * 64 + lane] += W.M[v * 64 + lane] * (bh - bl);
-    }
+        const float bh = W.Bm(x.hi), bl = W.Bm(x.lo);
+        W.Bm(v) = W.P(x.slot) * bh + W.Q(x.slot) * bl;
+        W.G(x.slot) += W.M(v) * (bh - bl);
+    });
     // Boolean slots: distinct variables within a constraint
-    for (int s = 0; s < NB; ++s) {
-        const float g = t.valid ? wc * W.G[s * 64 + lane] * -0.5f : 0.0f;     // dp/da = -1/2
+    for_up<KS>(0, NB, [&](int s) {
+        const float g = t.valid ? wc * W.G(s) * -0.5f : 0.0f;     // dp/da = -1/2
         sc.add_a(t.r, t.valid ? t.sup[(int64_t)s * np] : -1, g, lane);
-    }
+    });
     if (t.rec) {
         // inline atoms: consecutive atoms on the same variable are summed in registers; a
         // running target is flushed (uniformly across the wave) when the next atom's differs
         int v0 = -1, v1 = -1;
         float g0 = 0.0f, g1 = 0.0f;
-        for (int s = NB; s < S; ++s) {
+        for_up<KS>(NB, S, [&](int s) {
             AtomRec a;
             float gz = 0.0f;
             if (t.valid) {
                 a = load_rec(t.rec + (int64_t)(s - NB) * np);
-                gz = wc * W.G[s * 64 + lane] * W.D[s * 64 + lane];
+                gz = wc * W.G(s) * W.D(s);
             } else {
                 a.v0 = a.v1 = -1;
                 a.c0 = a.c1 = 0.0f;
@@ -309,18 +376,58 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
             if (n1) { v1 = a.v1; g1 = 0.0f; }
             g0 += gz * a.c0;
             if (a.flags & 2u) g1 += gz * a.c1;
-        }
+        });
         sc.add_b(t.r, v0, g0, lane);
         sc.add_b(t.r, v1, g1, lane);
     } else if (t.valid) {
-        for (int s = NB; s < S; ++s) {
-            const float gz = wc * W.G[s * 64 + lane] * W.D[s * 64 + lane];
-            if (gz == 0.0f) continue;
-            const int k = t.sup[(int64_t)s * np] - T.n_bool;
-            for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
-                sc.add_b_direct(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
-        }
+        for_up<KS>(NB, S, [&](int s) {
+            const float gz = wc * W.G(s) * W.D(s);
+            if (gz != 0.0f) {
+                const int k = t.sup[(int64_t)s * np] - T.n_bool;
+                for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
+                    sc.add_b_direct(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+            }
+        });
     }
+}
+
+// Message-store variants: a kernel is instantiated per variant and the host picks the
+// smallest whose bounds hold for every diagram of the launch.
+enum MsgVariant { kMsgLds = 0, kMsgSmall = 1, kMsgMedium = 2 };
+template <int V> struct MsgOf;
+template <> struct MsgOf<kMsgSmall> { using type = RegMsgs<4, 4>; };
+template <> struct MsgOf<kMsgMedium> { using type = RegMsgs<20, 12>; };
+template <> struct MsgOf<kMsgLds> { using type = LdsMsgs; };
+
+// Bind a store: an LDS store to the wave's columns (base: this wave's LDS scratch), a
+// register store to the kernel's local arrays.
+template <class Ms>
+__device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, int lane, float *m, float *b, float *p,
+                                          float *q, float *d, float *g) {
+    if constexpr (Ms::kNodes == 0) {
+        W.W = WaveScratch::at(base, NN, SS);
+        W.lane = lane;
+    } else {
+        W.m_ = m;
+        W.b_ = b;
+        W.p_ = p;
+        W.q_ = q;
+        W.d_ = d;
+        W.g_ = g;
+    }
+}
+// Declares the store W of type Ms with its register arrays (unused for LDS stores).
+#define FSMT_MSG_STORE(Ms, W, base, NN, SS, lane)                                                              \
+    float W##_m[Ms::kArrNodes], W##_b[Ms::kArrNodes], W##_p[Ms::kArrSlots], W##_q[Ms::kArrSlots],               \
+        W##_d[Ms::kArrSlots], W##_g[Ms::kArrSlots];                                                             \
+    Ms W;                                                                                                       \
+    bind_msgs(W, base, NN, SS, lane, W##_m, W##_b, W##_p, W##_q, W##_d, W##_g)
+
+inline int msg_variant(int max_nodes, int max_slots, bool lds_only) {
+    if (lds_only) return kMsgLds;
+    if (max_nodes <= 4 && max_slots <= 4) return kMsgSmall;
+    if (max_nodes <= 20 && max_slots <= 12) return kMsgMedium;
+    return kMsgLds;
 }
 
 // Deterministic walk of constraint c at the rounded point (exact check).

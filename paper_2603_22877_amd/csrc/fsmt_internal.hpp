@@ -95,6 +95,7 @@ struct fsmt_xbdd {
     int max_nodes = 0, max_slots = 0;
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
     int n_box_units = 0, n_hs = 0, hs_nnz = 0;
+    bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     std::vector<fsmt::TplInfo> h_tpl;
     std::vector<fsmt::BucketInfo> h_bucket;
     std::vector<int32_t> h_bucket_start;

@@ -83,8 +83,15 @@ __device__ __forceinline__ bool cluster_sync(int32_t *bar, int target, int32_t *
     return __syncthreads_and(ok) != 0;
 }
 
-__global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags,
-                                                        int32_t *abort_flag) {
+// Waves per workgroup of the solver kernel for each message variant: register-resident
+// messages of the larger bound need up to 256 VGPRs, so those workgroups hold 8 waves.
+template <int V> struct SolveWaves { static constexpr int value = 16; };
+template <> struct SolveWaves<kMsgMedium> { static constexpr int value = 8; };
+
+template <int V>
+__global__ void __launch_bounds__(64 * SolveWaves<V>::value)
+    solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags, int32_t *abort_flag) {
+    using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ii = find_inst(insts, P.n_inst, blockIdx.x);
@@ -98,7 +105,7 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
     const int nw = (C + 31) >> 5;
     float *sa = lds, *sb = sa + n, *ga = sb + m, *gb = ga + n, *pb = gb + m, *ph = pb + m;
     const int NN = P.lds_nodes + 2, SS = P.lds_slots;
-    const WaveScratch W = WaveScratch::at(lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS);
+    FSMT_MSG_STORE(Ms, W, lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS, lane);
     float *wrow = I.w + (int64_t)r * C, *hrow = I.hist + (int64_t)r * C;
     uint32_t *brow = I.sat_bits + (int64_t)r * nw;
     const int64_t pstride = (int64_t)n + m + 1;
@@ -132,7 +139,7 @@ __global__ void __launch_bounds__(1024) solve_wg_kernel(const InstDesc *insts, S
             float oacc = 0.0f;
             for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
-                const float unsat = task_forward(T, t, st, kappa, hard, W, lane);
+                const float unsat = task_forward(T, t, st, kappa, hard, W);
                 const float wc = t.valid ? wrow[t.c] : 0.0f;
                 oacc += wc * unsat;
                 task_backward(T, t, wc, sc, W, lane);
@@ -278,13 +285,20 @@ static int lds_budget_bytes() {
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > budget)
             budget = v;
-        if (budget > 65536 &&
-            hipFuncSetAttribute((const void *)solve_wg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
-            (void)hipGetLastError();
-            budget = 65536;
+        const void *fns[] = {(const void *)solve_wg_kernel<kMsgLds>, (const void *)solve_wg_kernel<kMsgSmall>,
+                             (const void *)solve_wg_kernel<kMsgMedium>};
+        for (const void *f : fns) {
+            if (budget > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
+                (void)hipGetLastError();
+                budget = 65536;
+            }
         }
     }
     return budget;
+}
+
+static int solve_waves(int msg) {
+    return msg == kMsgMedium ? SolveWaves<kMsgMedium>::value : SolveWaves<kMsgSmall>::value;
 }
 
 static size_t state_floats_of(const fsmt_xbdd *h) {
@@ -359,10 +373,11 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     std::vector<char> use_grid(n_inst, 0);
     for (int i = 0; i < n_inst; ++i) {
         const fsmt_xbdd *h = insts[i];
-        const size_t wb = WaveScratch::bytes(h->max_nodes + 2, std::max(h->max_slots, 1));
+        const int mv = msg_variant(h->max_nodes, h->max_slots, h->lds_messages);
+        const size_t wb = mv == kMsgLds ? WaveScratch::bytes(h->max_nodes + 2, std::max(h->max_slots, 1)) : 0;
         const size_t sb = state_floats_of(h) * sizeof(float);
         const bool fits = sb + wb <= budget;
-        const int waves = fits ? (int)std::min<size_t>(16, (budget - sb) / wb) : 0;
+        const int waves = !fits ? 0 : wb ? (int)std::min<size_t>(16, (budget - sb) / wb) : solve_waves(mv);
         if (O.schedule == 1 && !fits)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: restart state (%zu B) does not fit the persistent "
                              "schedule's LDS (%zu B)", i, sb, budget);
@@ -413,14 +428,20 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             total_r += states[ia[q]].a.rows;
             min_tasks = std::min<int64_t>(min_tasks, h->n_pos / 64);
         }
-        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
+        bool lds_only = false;
+        for (size_t q = 0; q < ia.size(); ++q) lds_only = lds_only || insts[ia[q]]->lds_messages;
+        const int msg = msg_variant(maxn, maxs, lds_only);
+        const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
         const size_t state_bytes = state_f * sizeof(float);
-        const int waves = (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes);
+        const int waves = wave_bytes ? (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes) : solve_waves(msg);
         const size_t lds = state_bytes + (size_t)waves * wave_bytes;
+        const void *kern = msg == kMsgSmall    ? (const void *)solve_wg_kernel<kMsgSmall>
+                           : msg == kMsgMedium ? (const void *)solve_wg_kernel<kMsgMedium>
+                                               : (const void *)solve_wg_kernel<kMsgLds>;
         // workgroups per restart: a cluster of k co-resident workgroups shares one restart's
         // sweep (all of them must be resident at once: their barrier waits for each other)
         int occ = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_wg_kernel, 64 * waves, lds) != hipSuccess) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * waves, lds) != hipSuccess) {
             (void)hipGetLastError();
             occ = 1;
         }
@@ -491,8 +512,14 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                 fill_i32(ints, (int64_t)n_int, 0, st) != FSMT_OK) {
                 rc = set_error(FSMT_EHIP, "descriptor upload failed");
             } else {
-                hipLaunchKernelGGL(solve_wg_kernel, dim3((unsigned)wg), dim3(64 * waves), lds, st, (const InstDesc *)dbuf,
-                                   P, flags, abort_flag);
+                const dim3 g((unsigned)wg), b(64 * waves);
+                const InstDesc *d = (const InstDesc *)dbuf;
+                if (msg == kMsgSmall)
+                    hipLaunchKernelGGL(solve_wg_kernel<kMsgSmall>, g, b, lds, st, d, P, flags, abort_flag);
+                else if (msg == kMsgMedium)
+                    hipLaunchKernelGGL(solve_wg_kernel<kMsgMedium>, g, b, lds, st, d, P, flags, abort_flag);
+                else
+                    hipLaunchKernelGGL(solve_wg_kernel<kMsgLds>, g, b, lds, st, d, P, flags, abort_flag);
                 rc = launch_status("solver kernel");
             }
             (void)hipFreeAsync(dbuf, st);
@@ -544,7 +571,10 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             maxs = std::max(maxs, h->max_slots);
             if (h->n_hs) step_lds = std::max(step_lds, (size_t)(2 * h->n_real + h->hs_nnz) * sizeof(float));
         }
-        const size_t wave_bytes = WaveScratch::bytes(maxn + 2, maxs);
+        bool lds_only = false;
+        for (size_t q = 0; q < ib.size(); ++q) lds_only = lds_only || insts[ib[q]]->lds_messages;
+        const int msg = msg_variant(maxn, maxs, lds_only);
+        const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
         if (wave_bytes > 65536) rc = set_error(FSMT_ELIMIT, "diagram too large for the grid schedule");
         if (step_lds > 65536) rc = set_error(FSMT_ELIMIT, "projection work arrays exceed LDS");
         // device scratch: descriptors, kappas, per-restart flags and accumulators, gradients
@@ -599,7 +629,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             } else {
                 GridPlan plan{};
                 plan.steps = O.steps_per_level;
-                plan.sweep_wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes));
+                plan.msg = msg;
+                plan.sweep_wpb = wave_bytes ? (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes)) : 4;
                 plan.sweep_lds = wave_bytes * plan.sweep_wpb;
                 plan.sweep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tasks + plan.sweep_wpb - 1) / plan.sweep_wpb,
                                                                                (int64_t)n_cu * 8));

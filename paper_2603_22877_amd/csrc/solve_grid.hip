@@ -50,11 +50,13 @@ __global__ void grid_begin_kernel(const GridInst *insts, int n_inst, GridShared 
 }
 
 // Forward + reverse sweep over every instance's (constraint, restart) lanes.
+template <int V>
 __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     const int NN = S.lds_nodes + 2, SS = S.lds_slots;
-    const WaveScratch W = WaveScratch::at(lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS);
+    FSMT_MSG_STORE(Ms, W, lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS, lane);
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
     // objective partials are carried across this wave's tasks while they stay in one
     // instance (R <= 64: a lane's restart is fixed there) and flushed on a change
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         const TaskCtx t = task_ctx(I.T, pos, r, r_ok);
         const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
         const bool hard = isinf(kappa);
-        const float unsat = task_forward(I.T, t, st, kappa, hard, W, lane);
+        const float unsat = task_forward(I.T, t, st, kappa, hard, W);
         const float wc = t.valid ? I.w[(int64_t)r * I.T.n_cons + t.c] : 0.0f;
         if (I.R_pad <= 64) {
             oacc += wc * unsat;
@@ -233,8 +235,13 @@ static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const Grid
     hipLaunchKernelGGL(grid_begin_kernel, dim3((S.total_r + 255) / 256), dim3(256), 0, st, d_insts, n_inst, S);
     if ((rc = launch_status("grid begin"))) return rc;
     for (int k = 0; k < P.steps; ++k) {
-        hipLaunchKernelGGL(grid_sweep_kernel, dim3(P.sweep_blocks), dim3(64 * P.sweep_wpb), P.sweep_lds, st, d_insts,
-                           n_inst, S);
+        const dim3 g(P.sweep_blocks), b(64 * P.sweep_wpb);
+        if (P.msg == kMsgSmall)
+            hipLaunchKernelGGL(grid_sweep_kernel<kMsgSmall>, g, b, 0, st, d_insts, n_inst, S);
+        else if (P.msg == kMsgMedium)
+            hipLaunchKernelGGL(grid_sweep_kernel<kMsgMedium>, g, b, 0, st, d_insts, n_inst, S);
+        else
+            hipLaunchKernelGGL(grid_sweep_kernel<kMsgLds>, g, b, P.sweep_lds, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid sweep"))) return rc;
         hipLaunchKernelGGL(grid_step_kernel, dim3(S.total_r), dim3(256), P.step_lds, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid step"))) return rc;

@@ -32,6 +32,7 @@ struct GridShared {
 struct GridPlan {
     int steps;
     int sweep_blocks, sweep_wpb;
+    int msg;                        // message-store variant of the sweep (MsgVariant)
     size_t sweep_lds, step_lds;
     int64_t check_blocks;
     bool use_graph;

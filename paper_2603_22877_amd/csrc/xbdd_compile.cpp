@@ -290,6 +290,10 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         return set_error(FSMT_EINVAL, "null array in problem");
     const int max_nodes = (opts && opts->max_nodes > 0) ? std::min(opts->max_nodes, 65000) : 1024;
     const bool host_only = opts && opts->device == FSMT_HOST_ONLY;
+    if (opts && opts->messages != FSMT_MSG_AUTO && opts->messages != FSMT_MSG_LDS)
+        return set_error(FSMT_EINVAL, "messages must be FSMT_MSG_AUTO or FSMT_MSG_LDS");
+    if (opts && opts->projection != FSMT_PROJ_UNIT && opts->projection != FSMT_PROJ_BOX)
+        return set_error(FSMT_EINVAL, "projection must be FSMT_PROJ_UNIT or FSMT_PROJ_BOX");
     int h_box_units = 0;
     int device = (opts && opts->device >= 0) ? opts->device : -1;
     if (!host_only && device < 0 && hipGetDevice(&device) != hipSuccess)
@@ -496,6 +500,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     h->h_con_bucket = con_bucket;
     h->h_con_local = con_local;
     h->host_only = host_only;
+    h->lds_messages = opts && opts->messages == FSMT_MSG_LDS;
 
     // ---- feasible set of the projection (Def. "Projection", Prop. "qp"): the box, plus
     // unit atomic constraints (one atom literal, no Boolean) when requested.

@@ -198,6 +198,8 @@ def test_errors_are_reported_not_thrown():
     p.real_lo = p.real_lo.copy()
     p.real_lo[0] = p.real_hi[0] + 1
     assert _err(p) == _abi.FSMT_EINVAL
+    assert _err(W.make_config(1), messages=2) == _abi.FSMT_EINVAL
+    assert _err(W.make_config(1), projection=5) == _abi.FSMT_EINVAL
 
 
 def test_runtime_calls_reject_host_only_handles():

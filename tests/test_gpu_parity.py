@@ -42,8 +42,11 @@ def _run_cop(p, h, a, b, kap, w=None, layout="rows", grad=True):
     return out
 
 
-def _compare(p, a, b, kap, w=None, layout="rows"):
-    h = fsmt.xbdd_compile(p)
+MSG = {"auto": 0, "lds": 1}
+
+
+def _compare(p, a, b, kap, w=None, layout="rows", messages="auto"):
+    h = fsmt.xbdd_compile(p, messages=MSG[messages])
     g = _run_cop(p, h, a, b, kap, w, layout)
     o = oracle.objective(p, a, b, kap, w=w)
     wsum = (np.ones(p.n_cons) if w is None else np.broadcast_to(w, (a.shape[0], p.n_cons))).sum(-1)
@@ -56,15 +59,27 @@ def _compare(p, a, b, kap, w=None, layout="rows"):
     return g, o
 
 
+@pytest.mark.parametrize("messages", ["auto", "lds"])
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("R", [1, 3, 16, 64, 100])
 @pytest.mark.parametrize("kap", [0.0, 0.4, 2.5, INF])
-def test_random_formulas_all_kinds(seed, R, kap):
-    print(f"random formulas seed={seed} R={R} kappa={kap}", flush=True)
+def test_random_formulas_all_kinds(seed, R, kap, messages):
+    print(f"random formulas seed={seed} R={R} kappa={kap} messages={messages}", flush=True)
     p = W.make_random_formula(1000 + seed, n_bool=8, n_real=4, n_atoms=8, n_cons=150, max_len=6)
     a, b = W.initial_points(p, R, 99, seed)
     a[0, :2] = [0.0, -1.0]
-    _compare(p, a, b, kap, w=np.random.default_rng(seed).uniform(0.5, 2, (R, p.n_cons)))
+    _compare(p, a, b, kap, w=np.random.default_rng(seed).uniform(0.5, 2, (R, p.n_cons)), messages=messages)
+
+
+@pytest.mark.parametrize("max_len,seed", [(2, 0), (2, 1), (3, 0), (12, 0), (12, 1)])
+def test_message_store_bounds(max_len, seed):
+    """Diagrams within the 4-node and 20-node register bounds and beyond them (LDS store)."""
+    p = W.make_random_formula(3000 + seed, n_bool=10, n_real=4, n_atoms=10, n_cons=120, max_len=max_len)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"max_len={max_len} seed={seed} nodes={info['max_nodes']} slots={info['max_slots']}", flush=True)
+    a, b = W.initial_points(p, 24, 98, seed)
+    for kap in (0.3, 3.0):
+        _compare(p, a, b, kap)
 
 
 def test_fig2_toy_values():
@@ -77,11 +92,12 @@ def test_fig2_toy_values():
 
 @pytest.mark.parametrize("cfg,R,kap", [(1, 1, 0.3), (1, 1, INF), (2, 64, 0.05), (2, 64, 0.5),
                                        (3, 16, 0.1), (3, 16, 1.0)])
-def test_workload_configs(cfg, R, kap):
-    print(f"config {cfg} R={R} kappa={kap}", flush=True)
+@pytest.mark.parametrize("messages", ["auto", "lds"])
+def test_workload_configs(cfg, R, kap, messages):
+    print(f"config {cfg} R={R} kappa={kap} messages={messages}", flush=True)
     p = W.make_config(cfg)
     a, b = W.initial_points(p, R, cfg, 0)
-    _compare(p, a, b, kap)
+    _compare(p, a, b, kap, messages=messages)
 
 
 @pytest.mark.parametrize("cfg,R", [(1, 5), (2, 64), (3, 16)])
