@@ -118,6 +118,8 @@ typedef struct {
     int64_t atom_nnz;
     int32_t n_box_units;       /* single-variable unit atoms folded into the box */
     int32_t n_halfspaces;      /* multi-variable unit atoms kept as half-spaces of D */
+    int32_t n_big;             /* constraints with big diagrams (evaluated level by level,
+                                  one wavefront per constraint and restart) */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

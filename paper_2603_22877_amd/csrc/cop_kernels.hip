@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
+    const int wib = wave_id();
     const int wpb = blockDim.x >> 6;
     const int64_t wave0 = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
             r = (int)(task % wpc) * 64 + lane;
         }
         const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
+        if (t.B.big) continue;   // evaluated by cop_level_kernel
         const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W);
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
@@ -82,6 +83,181 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     if (A.obj && A.R_pad <= 64) {
         for (int off = 32; off >= A.R_pad; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
         if (lane < A.R_pad && lane < A.R && oacc != 0.0f) atomic_add_f32(A.obj + lane, oacc);
+    }
+}
+
+// ------------------------------------------------------------------ big diagrams
+// Level-synchronous passes for diagrams too large for per-lane message columns (long
+// cardinality, not-all-equal and parity constraints): one wavefront per (constraint,
+// chunk of restarts). Nodes are stored level by level (sorted by slot), so a level is a
+// contiguous range; its nodes go to the lanes. The wave stages the constraint's node table
+// in its LDS rows once and reuses it for every restart of the chunk; messages live in LDS
+// rows too: M and Bm per node, P, Q, D, G per slot.
+//   literal probabilities: lane = slot (as in task_forward)
+//   forward : per level, each node adds p M[v] to M[hi] and (1-p) M[v] to M[lo] (LDS
+//             atomics: nodes of one level may share children, which lie on deeper levels)
+//   reverse : per level from the bottom, Bm[v] = p Bm[hi] + (1-p) Bm[lo] (children final),
+//             and the level's sensitivity G[s] = sum_v M[v] (Bm[hi] - Bm[lo]) is a wave sum
+//   scatter : lane = slot, as in task_backward
+constexpr int kLevelChunk = 8;   // restarts per wavefront task
+
+struct LevelArgs {
+    TabView T;
+    cptr<int32_t> lev, big_pos;
+    int32_t n_big, R;
+    View a, b, w, unsat, ga, gb;
+    float *obj;
+    double kappa;
+    int32_t hard;
+    int32_t lds_nodes, lds_slots;   // per-wave LDS rows (max over big templates)
+};
+
+// floats of one wave's LDS rows: node table (2 words a node), M, Bm, P, Q, D, G
+__host__ __device__ inline size_t level_wave_floats(int max_nodes, int max_slots) {
+    return (size_t)2 * max_nodes + 2 * ((size_t)max_nodes + 2) + 4 * (size_t)max_slots;
+}
+
+// Orders this wave's LDS accesses: the next level reads what this level added.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ Node unpack_node(uint2 raw) {
+    Node n;
+    n.slot = (uint16_t)(raw.x & 0xFFFFu);
+    n.hi = (uint16_t)(raw.x >> 16);
+    n.lo = (uint16_t)(raw.y & 0xFFFFu);
+    n.pad = 0;
+    return n;
+}
+
+template <bool kGrad>
+__global__ void __launch_bounds__(256) cop_level_kernel(LevelArgs A) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    const int wib = wave_id();
+    const int wpb = blockDim.x >> 6;
+    const int NMAX = A.lds_nodes, SS = A.lds_slots;
+    float *base = lds + (size_t)wib * level_wave_floats(NMAX, SS);
+    uint2 *NL = reinterpret_cast<uint2 *>(base);
+    float *M = base + 2 * NMAX, *Bm = M + NMAX + 2, *P = Bm + NMAX + 2, *Q = P + SS, *D = Q + SS, *G = D + SS;
+    const TabView &T = A.T;
+    const GlobalState st{A.a, A.b};
+    const GlobalScatter sc{A.ga, A.gb, 64};
+    const int chunks = (A.R + kLevelChunk - 1) / kLevelChunk;
+    const int64_t n_tasks = (int64_t)A.n_big * chunks;
+    for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < n_tasks; task += (int64_t)gridDim.x * wpb) {
+        const int q = (int)(task / chunks), r0 = (int)(task - (int64_t)q * chunks) * kLevelChunk;
+        const int r1 = r0 + kLevelChunk < A.R ? r0 + kLevelChunk : A.R;
+        const int pos = __builtin_amdgcn_readfirstlane(A.big_pos[q]);
+        const BucketInfo B = load_bucket(T.bucket + __builtin_amdgcn_readfirstlane(T.task_bucket[pos >> 6]));
+        const int c = __builtin_amdgcn_readfirstlane(T.pos_con[pos]);
+        const int local = pos - B.pos_begin;
+        const int N = B.n_nodes, S = B.n_slots, NB = B.n_bslots;
+        const int64_t np = B.n_pos;
+        const cptr<int32_t> sup = T.sup + B.sup_base + local;
+        const cptr<AtomRec> rec = B.arec_base >= 0 ? T.arec + B.arec_base + local : nullptr;
+        const cptr<int32_t> lev = A.lev + B.lev_off;
+        const cptr<u32x2> nd = (cptr<u32x2>)(T.nodes + B.node_off);
+        for (int v = lane; v < N; v += 64) {
+            const u32x2 raw = nd[v];
+            NL[v] = make_uint2(raw.x, raw.y);
+        }
+        wave_lds_sync();
+
+        for (int r = r0; r < r1; ++r) {
+            for (int s = lane; s < S; s += 64) {
+                float p, qq, d = 0.0f;
+                if (s < NB) {
+                    const float av = st.av(r, sup[(int64_t)s * np]);
+                    p = (1.0f - av) * 0.5f;
+                    qq = (1.0f + av) * 0.5f;
+                } else if (rec) {
+                    const AtomRec at = load_rec(rec + (int64_t)(s - NB) * np);
+                    atom_literal(rec_z(at, st, r), (double)at.scale, (at.flags & 1u) != 0, A.kappa, A.hard != 0, p, qq,
+                                 d);
+                } else {
+                    const int k = sup[(int64_t)s * np] - T.n_bool;
+                    atom_literal(atom_z_state(T, k, st, r), T.atom_scale[k], T.atom_strict[k] != 0, A.kappa, A.hard != 0,
+                                 p, qq, d);
+                }
+                P[s] = p;
+                Q[s] = qq;
+                D[s] = d;
+            }
+            for (int v = lane; v < N + 2; v += 64) M[v] = 0.0f;
+            wave_lds_sync();
+            if (lane == 0) M[B.root] = 1.0f;
+            wave_lds_sync();
+            for (int s = 0; s < S; ++s) {
+                const int v0 = lev[s], v1 = lev[s + 1];
+                if (v0 == v1) continue;
+                const float p = P[s], qq = Q[s];
+                for (int v = v0 + lane; v < v1; v += 64) {
+                    const Node x = unpack_node(NL[v]);
+                    const float mv = M[v];
+                    atomicAdd(M + x.hi, p * mv);
+                    atomicAdd(M + x.lo, qq * mv);
+                }
+                wave_lds_sync();
+            }
+            const float unsat = M[N + 1];
+            const float wc = A.w.at(r, c);
+            if (lane == 0) {
+                if (A.unsat.data) A.unsat.at(r, c) = unsat;
+                if (A.obj) atomic_add_f32(A.obj + r, wc * unsat);
+            }
+            if (kGrad) {
+                if (lane == 0) {
+                    Bm[N] = 0.0f;
+                    Bm[N + 1] = 1.0f;
+                }
+                wave_lds_sync();
+                for (int s = S - 1; s >= 0; --s) {
+                    const int v0 = lev[s], v1 = lev[s + 1];
+                    float g = 0.0f;
+                    if (v0 < v1) {
+                        const float p = P[s], qq = Q[s];
+                        for (int v = v0 + lane; v < v1; v += 64) {
+                            const Node x = unpack_node(NL[v]);
+                            const float bh = Bm[x.hi], bl = Bm[x.lo];
+                            Bm[v] = p * bh + qq * bl;
+                            g += M[v] * (bh - bl);
+                        }
+                        g = wave_sum(g);
+                    }
+                    if (lane == 0) G[s] = g;
+                    wave_lds_sync();
+                }
+                for (int s = lane; s < S; s += 64) {
+                    const float g = wc * G[s];
+                    if (s < NB) {
+                        sc.add_b_direct_a(r, sup[(int64_t)s * np], g * -0.5f);      // dp/da = -1/2
+                    } else if (rec) {
+                        const AtomRec at = load_rec(rec + (int64_t)(s - NB) * np);
+                        const float gz = g * D[s];
+                        if (gz != 0.0f) {
+                            sc.add_b_direct(r, at.v0, gz * at.c0);
+                            if (at.flags & 2u) sc.add_b_direct(r, at.v1, gz * at.c1);
+                        }
+                    } else {
+                        const float gz = g * D[s];
+                        if (gz != 0.0f) {
+                            const int k = sup[(int64_t)s * np] - T.n_bool;
+                            for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
+                                sc.add_b_direct(r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();   // the next restart overwrites this wave's message rows
+        }
     }
 }
 
@@ -103,8 +279,8 @@ __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t value) {
 }
 
 // One block per restart: clamp / project step, gradient-map norm, zero the gradient.
-__global__ void __launch_bounds__(256) pgd_kernel(View a, View b, View ga, View gb, const float *lo,
-                                                  const float *hi, float eta_a, float eta_b, float *gsq,
+__global__ void __launch_bounds__(256) pgd_kernel(View a, View b, View ga, View gb, cptr<float> lo,
+                                                  cptr<float> hi, float eta_a, float eta_b, float *gsq,
                                                   HalfSpaces hs) {
     extern __shared__ float sm[];
     const int r = blockIdx.x;
@@ -241,7 +417,8 @@ fsmt_status select_device(const fsmt_xbdd *h) {
 }
 
 HalfSpaces halfspaces_of(const fsmt_xbdd *h) {
-    return HalfSpaces{h->d.hs_ptr, h->d.hs_var, h->d.hs_coef, h->d.hs_rhs, h->d.hs_inv, h->n_hs, h->hs_nnz};
+    return HalfSpaces{as_cptr(h->d.hs_ptr), as_cptr(h->d.hs_var), as_cptr(h->d.hs_coef), as_cptr(h->d.hs_rhs),
+                      as_cptr(h->d.hs_inv), h->n_hs, h->hs_nnz};
 }
 
 static fsmt_status launch_status(const char *what) {
@@ -299,12 +476,16 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     for (int i = 0; i < 7; ++i)
         if ((rc = check_device_ptr(ptrs[i], h->device, names[i]))) return rc;
 
-    const int NN = h->max_nodes + 2, SS = std::max(h->max_slots, 1);
-    const int msg = msg_variant(h->max_nodes, h->max_slots, h->lds_messages);
+    // one lane per constraint for the small diagrams, one wavefront per (constraint,
+    // restart) for the big ones
+    const int NN = h->small_max_nodes + 2, SS = std::max(h->small_max_slots, 1);
+    const int msg = msg_variant(h->small_max_nodes, h->small_max_slots, h->lds_messages, h->all_inline);
     const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(NN, SS) : 0;
-    if (wave_bytes > 65536)
-        return set_error(FSMT_ELIMIT, "diagram too large for the LDS-resident pass (%d nodes, %d slots)", h->max_nodes, h->max_slots);
     const int wpb = wave_bytes ? (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes)) : 4;
+    const size_t level_wave_bytes = level_wave_floats(h->big_max_nodes, std::max(h->big_max_slots, 1)) * sizeof(float);
+    if (h->n_big > 0 && level_wave_bytes > 65536)
+        return set_error(FSMT_ELIMIT, "diagram too large for the level-synchronous pass (%d nodes, %d slots)",
+                         h->big_max_nodes, h->big_max_slots);
 
     if (!(flags & FSMT_ACCUMULATE)) {
         if (obj && (rc = fill_f32(obj, R, 0.0f, st))) return rc;
@@ -335,23 +516,53 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     A.obj = obj;
     A.kappa = kappa;
     A.hard = std::isinf(kappa) ? 1 : 0;
-    A.lds_nodes = h->max_nodes;
+    A.lds_nodes = h->small_max_nodes;
     A.lds_slots = SS;
     const int64_t max_waves = 256 * 32;
     const int64_t waves = std::min<int64_t>(A.n_tasks, max_waves);
     const int blocks = (int)((waves + wpb - 1) / wpb);
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
-    if (grad) {
-        if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<true, kMsgSmall>), g, bl, 0, st, A);
-        else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<true, kMsgMedium>), g, bl, 0, st, A);
-        else hipLaunchKernelGGL((cop_kernel<true, kMsgLds>), g, bl, lds, st, A);
-    } else {
-        if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<false, kMsgSmall>), g, bl, 0, st, A);
-        else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<false, kMsgMedium>), g, bl, 0, st, A);
-        else hipLaunchKernelGGL((cop_kernel<false, kMsgLds>), g, bl, lds, st, A);
+    if (h->n_big < h->n_cons) {
+        if (grad) {
+            if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<true, kMsgSmall>), g, bl, 0, st, A);
+            else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<true, kMsgMedium>), g, bl, 0, st, A);
+            else hipLaunchKernelGGL((cop_kernel<true, kMsgLds>), g, bl, lds, st, A);
+        } else {
+            if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<false, kMsgSmall>), g, bl, 0, st, A);
+            else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<false, kMsgMedium>), g, bl, 0, st, A);
+            else hipLaunchKernelGGL((cop_kernel<false, kMsgLds>), g, bl, lds, st, A);
+        }
+        if ((rc = launch_status("cop kernel"))) return rc;
     }
-    return launch_status("cop kernel");
+    if (h->n_big > 0) {
+        LevelArgs L{};
+        L.T = A.T;
+        L.lev = as_cptr(h->d.lev);
+        L.big_pos = as_cptr(h->d.big_pos);
+        L.n_big = h->n_big;
+        L.R = R;
+        L.a = A.a;
+        L.b = A.b;
+        L.w = A.w;
+        L.unsat = A.unsat;
+        L.ga = A.ga;
+        L.gb = A.gb;
+        L.obj = obj;
+        L.kappa = kappa;
+        L.hard = A.hard;
+        L.lds_nodes = h->big_max_nodes;
+        L.lds_slots = std::max(h->big_max_slots, 1);
+        const int lwpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / level_wave_bytes));
+        const int64_t ltasks = (int64_t)h->n_big * ((R + kLevelChunk - 1) / kLevelChunk);
+        const int lblocks = (int)std::min<int64_t>((ltasks + lwpb - 1) / lwpb, (int64_t)256 * 16);
+        if (grad)
+            hipLaunchKernelGGL(cop_level_kernel<true>, dim3(lblocks), dim3(64 * lwpb), level_wave_bytes * lwpb, st, L);
+        else
+            hipLaunchKernelGGL(cop_level_kernel<false>, dim3(lblocks), dim3(64 * lwpb), level_wave_bytes * lwpb, st, L);
+        if ((rc = launch_status("cop level kernel"))) return rc;
+    }
+    return FSMT_OK;
 }
 
 }  // namespace fsmt
@@ -394,7 +605,8 @@ fsmt_status pgd_step(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, fsmt_view gra
     const size_t lds = hs.n ? (size_t)(2 * h->n_real + hs.nnz) * sizeof(float) : 0;
     if (lds > 65536) return set_error(FSMT_ELIMIT, "projection onto %d half-spaces over %d reals exceeds LDS", hs.n, h->n_real);
     hipLaunchKernelGGL(pgd_kernel, dim3(R), dim3(256), lds, (hipStream_t)stream, View::of(a), View::of(b),
-                       View::of(grad_a), View::of(grad_b), h->d.real_lo, h->d.real_hi, eta_a, eta_b, gmap_sq, hs);
+                       View::of(grad_a), View::of(grad_b), as_cptr(h->d.real_lo), as_cptr(h->d.real_hi), eta_a, eta_b,
+                       gmap_sq, hs);
     return launch_status("pgd kernel");
 }
 

@@ -12,46 +12,46 @@ namespace fsmt {
 
 // Device pointers of one compiled instance.
 struct TabView {
-    const TplInfo *tpl;
-    const Node *nodes;
-    const BucketInfo *bucket;
-    const int32_t *bucket_start;
-    const int32_t *task_bucket;
-    const AtomRec *arec;
-    const int32_t *pos_con;
-    const int32_t *sup;
-    const int32_t *con_bucket;
-    const int32_t *con_local;
-    const int32_t *atom_ptr;
-    const int32_t *atom_var;
-    const double *atom_coef;
-    const double *atom_rhs;
-    const double *atom_scale;
-    const uint8_t *atom_strict;
-    const float *real_lo;
-    const float *real_hi;
+    cptr<TplInfo> tpl;
+    cptr<Node> nodes;
+    cptr<BucketInfo> bucket;
+    cptr<int32_t> bucket_start;
+    cptr<int32_t> task_bucket;
+    cptr<AtomRec> arec;
+    cptr<int32_t> pos_con;
+    cptr<int32_t> sup;
+    cptr<int32_t> con_bucket;
+    cptr<int32_t> con_local;
+    cptr<int32_t> atom_ptr;
+    cptr<int32_t> atom_var;
+    cptr<double> atom_coef;
+    cptr<double> atom_rhs;
+    cptr<double> atom_scale;
+    cptr<uint8_t> atom_strict;
+    cptr<float> real_lo;
+    cptr<float> real_hi;
     int32_t n_bool, n_real, n_cons, n_pos, n_buckets, pad;
 
     static TabView of(const fsmt_xbdd *h) {
         TabView t;
-        t.tpl = h->d.tpl;
-        t.nodes = h->d.nodes;
-        t.bucket = h->d.bucket;
-        t.bucket_start = h->d.bucket_start;
-        t.task_bucket = h->d.task_bucket;
-        t.arec = h->d.arec;
-        t.pos_con = h->d.pos_con;
-        t.sup = h->d.sup;
-        t.con_bucket = h->d.con_bucket;
-        t.con_local = h->d.con_local;
-        t.atom_ptr = h->d.atom_ptr;
-        t.atom_var = h->d.atom_var;
-        t.atom_coef = h->d.atom_coef;
-        t.atom_rhs = h->d.atom_rhs;
-        t.atom_scale = h->d.atom_scale;
-        t.atom_strict = h->d.atom_strict;
-        t.real_lo = h->d.real_lo;
-        t.real_hi = h->d.real_hi;
+        t.tpl = as_cptr(h->d.tpl);
+        t.nodes = as_cptr(h->d.nodes);
+        t.bucket = as_cptr(h->d.bucket);
+        t.bucket_start = as_cptr(h->d.bucket_start);
+        t.task_bucket = as_cptr(h->d.task_bucket);
+        t.arec = as_cptr(h->d.arec);
+        t.pos_con = as_cptr(h->d.pos_con);
+        t.sup = as_cptr(h->d.sup);
+        t.con_bucket = as_cptr(h->d.con_bucket);
+        t.con_local = as_cptr(h->d.con_local);
+        t.atom_ptr = as_cptr(h->d.atom_ptr);
+        t.atom_var = as_cptr(h->d.atom_var);
+        t.atom_coef = as_cptr(h->d.atom_coef);
+        t.atom_rhs = as_cptr(h->d.atom_rhs);
+        t.atom_scale = as_cptr(h->d.atom_scale);
+        t.atom_strict = as_cptr(h->d.atom_strict);
+        t.real_lo = as_cptr(h->d.real_lo);
+        t.real_hi = as_cptr(h->d.real_hi);
         t.n_bool = h->n_bool;
         t.n_real = h->n_real;
         t.n_cons = h->n_cons;
@@ -103,6 +103,7 @@ struct GlobalScatter {
     }
     // for divergent call sites (no merging)
     __device__ __forceinline__ void add_b_direct(int r, int j, float g) const { atomic_add_f32(&gb.at(r, j), g); }
+    __device__ __forceinline__ void add_b_direct_a(int r, int i, float g) const { atomic_add_f32(&ga.at(r, i), g); }
 };
 // LDS: the fused solver's gradient lives in LDS and its atomics stay on the CU.
 struct LdsScatter {
@@ -143,9 +144,9 @@ __device__ __forceinline__ double rec_z(const AtomRec &a, const St &st, int r) {
     return acc - (double)a.rhs;
 }
 
-__device__ __forceinline__ AtomRec load_rec(const AtomRec *p) {
-    const int4 x = reinterpret_cast<const int4 *>(p)[0];
-    const int4 z = reinterpret_cast<const int4 *>(p)[1];
+__device__ __forceinline__ AtomRec load_rec(cptr<AtomRec> p) {
+    const i32x4 x = ((cptr<i32x4>)p)[0];
+    const i32x4 z = ((cptr<i32x4>)p)[1];
     AtomRec a;
     a.v0 = x.x;
     a.v1 = x.y;
@@ -159,7 +160,7 @@ __device__ __forceinline__ AtomRec load_rec(const AtomRec *p) {
 }
 
 // Find the bucket containing position pos (uniform across the wave).
-__device__ __forceinline__ int find_bucket(const int32_t *start, int nb, int pos) {
+__device__ __forceinline__ int find_bucket(cptr<int32_t> start, int nb, int pos) {
     int lo = 0, hi = nb - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -186,8 +187,8 @@ struct WaveScratch {
 
 struct TaskCtx {
     BucketInfo B;         // bucket record with the template fields
-    const int32_t *sup;   // this lane's support column
-    const AtomRec *rec;   // this lane's first inline atom record (or null)
+    cptr<int32_t> sup;    // this lane's support column
+    cptr<AtomRec> rec;    // this lane's first inline atom record (or null)
     int c;                // original constraint id (or -1)
     int r;
     bool valid;
@@ -198,7 +199,7 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
     TaskCtx t;
     const int pos0 = __builtin_amdgcn_readfirstlane(pos);
     const int bk = __builtin_amdgcn_readfirstlane(T.task_bucket[pos0 >> 6]);
-    t.B = T.bucket[bk];
+    t.B = load_bucket(T.bucket + bk);
     const int local = pos - t.B.pos_begin;
     t.sup = T.sup + t.B.sup_base + local;
     t.rec = t.B.arec_base >= 0 ? T.arec + t.B.arec_base + local : nullptr;
@@ -221,7 +222,11 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
 template <int NM, int SM>
 struct RegMsgs {
     static constexpr int kNodes = NM, kSlots = SM;
-    static constexpr int kArrNodes = NM + 2, kArrSlots = SM;
+    // At least 9 elements per array: the compiler lowers a uniform dynamic index into a
+    // shorter register array as a compare/select per element, into a longer one as a
+    // single indexed move (GPR indexing).
+    static constexpr int kArrNodes = NM + 2 < 9 ? 9 : NM + 2, kArrSlots = SM < 9 ? 9 : SM;
+    static constexpr bool kInlineOnly = true;   // every atom slot has an inline record
     // the arrays are separate locals of the kernel (see bind_msgs): a single aggregate
     // indexed dynamically would not be split into registers
     float *m_, *b_, *p_, *q_, *d_, *g_;
@@ -236,6 +241,7 @@ struct RegMsgs {
 struct LdsMsgs {
     static constexpr int kNodes = 0, kSlots = 0;   // unbounded
     static constexpr int kArrNodes = 1, kArrSlots = 1;
+    static constexpr bool kInlineOnly = false;      // inline records or the CSR atom table
     WaveScratch W;
     int lane;
     __device__ __forceinline__ float &M(int v) { return W.M[v * 64 + lane]; }
@@ -306,7 +312,7 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
     for_up<KS>(NB, S, [&](int s) {
         float p = 0.5f, q = 0.5f, d = 0.0f;
         if (t.valid) {
-            if (t.rec) {
+            if (Ms::kInlineOnly || t.rec) {
                 const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
                 atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p, q, d);
             } else {
@@ -321,7 +327,7 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
     });
     for_up<(KN > 0 ? KN + 2 : 0)>(0, N + 2, [&](int v) { W.M(v) = 0.0f; });
     W.M(t.B.root) = 1.0f;
-    const Node *nd = T.nodes + t.B.node_off;
+    const cptr<Node> nd = T.nodes + t.B.node_off;
     for_up<KN>(0, N, [&](int v) {
         const Node x = load_node(nd + v);
         const float mv = W.M(v);
@@ -341,7 +347,7 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
     for_up<KS>(0, S, [&](int s) { W.G(s) = 0.0f; });
     W.Bm(N) = 0.0f;
     W.Bm(N + 1) = 1.0f;
-    const Node *nd = T.nodes + t.B.node_off;
+    const cptr<Node> nd = T.nodes + t.B.node_off;
     for_down<KN>(N, [&](int v) {
         const Node x = load_node(nd + v);
         const float bh = W.Bm(x.hi), bl = W.Bm(x.lo);
@@ -353,7 +359,7 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
         const float g = t.valid ? wc * W.G(s) * -0.5f : 0.0f;     // dp/da = -1/2
         sc.add_a(t.r, t.valid ? t.sup[(int64_t)s * np] : -1, g, lane);
     });
-    if (t.rec) {
+    if (Ms::kInlineOnly || t.rec) {
         // inline atoms: consecutive atoms on the same variable are summed in registers; a
         // running target is flushed (uniformly across the wave) when the next atom's differs
         int v0 = -1, v1 = -1;
@@ -423,8 +429,9 @@ __device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, in
     Ms W;                                                                                                       \
     bind_msgs(W, base, NN, SS, lane, W##_m, W##_b, W##_p, W##_q, W##_d, W##_g)
 
-inline int msg_variant(int max_nodes, int max_slots, bool lds_only) {
-    if (lds_only) return kMsgLds;
+// Register variants need every atom in an inline record (the CSR path is compiled out).
+inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inline) {
+    if (lds_only || !all_inline) return kMsgLds;
     if (max_nodes <= 4 && max_slots <= 4) return kMsgSmall;
     if (max_nodes <= 20 && max_slots <= 12) return kMsgMedium;
     return kMsgLds;
@@ -433,13 +440,13 @@ inline int msg_variant(int max_nodes, int max_slots, bool lds_only) {
 // Deterministic walk of constraint c at the rounded point (exact check).
 template <class St>
 __device__ __forceinline__ bool walk_state(const TabView &T, const St &st, int c, int r) {
-    const BucketInfo B = T.bucket[T.con_bucket[c]];
+    const BucketInfo B = load_bucket(T.bucket + T.con_bucket[c]);
     const int local = T.con_local[c];
-    const int32_t *s = T.sup + B.sup_base + local;
+    const cptr<int32_t> s = T.sup + B.sup_base + local;
     const int N = B.n_nodes;
     int v = B.root;
     while (v < N) {
-        const Node x = T.nodes[B.node_off + v];
+        const Node x = load_node_lane(T.nodes + B.node_off + v);   // each lane walks its own diagram
         bool tr;
         if (x.slot < B.n_bslots) {
             tr = st.av(r, s[(int64_t)x.slot * B.n_pos]) < 0.0f;

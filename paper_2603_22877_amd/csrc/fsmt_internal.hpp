@@ -27,8 +27,18 @@ struct TplInfo {
     int32_t n_slots;    // support size
     int32_t n_bslots;   // Boolean slots (slots [0, n_bslots) are Booleans)
     int32_t root;       // 0, or n_nodes / n_nodes+1 for constant constraints
-    int32_t pad[3];
+    int32_t lev_off;    // level starts: lev[lev_off + s] = first node of slot s (s <= n_slots)
+    int32_t pad[2];
 };
+
+// A diagram is "big" when its per-lane message columns would take more than 32 KB of LDS
+// per wavefront; big diagrams are evaluated level by level, one wavefront per
+// (constraint, restart), instead of one lane per constraint.
+constexpr int64_t kBigDiagramBytes = 32768;
+inline bool big_diagram(int n_nodes, int n_slots) {
+    const int64_t ss = n_slots > 1 ? n_slots : 1;
+    return (2 * ((int64_t)n_nodes + 2) + 4 * ss) * 64 * 4 > kBigDiagramBytes;
+}
 
 struct BucketInfo {
     int32_t tpl;        // template id
@@ -39,7 +49,9 @@ struct BucketInfo {
     int64_t arec_base;  // offset of the bucket's inline atom records, or -1
     // copy of the template record (one scalar load serves the whole wave)
     int32_t node_off, n_nodes, n_slots, n_bslots, root;
-    int32_t pad[3];
+    int32_t lev_off;    // level starts of the template
+    int32_t big;        // 1: big diagram (level-synchronous kernel), 0: one lane per constraint
+    int32_t pad;
 };
 
 // Inline atom record (atoms with at most two variables whose "<=" coefficients and
@@ -77,6 +89,8 @@ struct DeviceTables {
     double *atom_rhs = nullptr;       // [A]   ("<=" form)
     double *atom_scale = nullptr;     // [A]   1/(sqrt(2)|q|)
     uint8_t *atom_strict = nullptr;   // [A]
+    int32_t *lev = nullptr;           // per template: n_slots + 1 level starts
+    int32_t *big_pos = nullptr;       // positions of the constraints in big buckets
     float *real_lo = nullptr;         // [m] box of D (tightened by single-variable unit atoms)
     float *real_hi = nullptr;         // [m]
     int32_t *hs_ptr = nullptr;        // [H+1] half-spaces of D: q.y <= rhs (multi-variable unit atoms)
@@ -93,9 +107,13 @@ struct fsmt_xbdd {
     int n_bool = 0, n_real = 0, n_atoms = 0, n_cons = 0;
     int n_tpl = 0, n_buckets = 0, n_pos = 0;
     int max_nodes = 0, max_slots = 0;
+    int small_max_nodes = 0, small_max_slots = 0;   // over templates evaluated one lane per constraint
+    int big_max_nodes = 0, big_max_slots = 0;       // over big templates
+    int n_big = 0;                                  // constraints in big buckets
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
     int n_box_units = 0, n_hs = 0, hs_nnz = 0;
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
+    bool all_inline = false;     // every atom slot of every bucket has an inline record
     std::vector<fsmt::TplInfo> h_tpl;
     std::vector<fsmt::BucketInfo> h_bucket;
     std::vector<int32_t> h_bucket_start;

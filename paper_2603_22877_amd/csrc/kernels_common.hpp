@@ -6,21 +6,44 @@
 
 namespace fsmt {
 
+// Address-space-typed device pointers. Kernels find their tables and state through
+// descriptors in device memory; plain pointers read from there would be generic to the
+// compiler (flat loads), and it could not tell that the tables are never written.
+//   cptr: data that no kernel of the launch writes (constant address space: loads at
+//         wave-uniform addresses become scalar loads, the others global loads);
+//   gptr: read-write global memory.
+// Host code fills both with an explicit cast of a device allocation.
+template <class T> using cptr = const __attribute__((address_space(4))) T *;
+template <class T> using gptr = __attribute__((address_space(1))) T *;
+template <class T> using gref = __attribute__((address_space(1))) T &;
+template <class T> inline cptr<T> as_cptr(const T *p) { return (cptr<T>)p; }
+template <class T> inline gptr<T> as_gptr(T *p) { return (gptr<T>)p; }
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+
 // Strided [rows][cols] float view (see fsmt_view).
 struct View {
-    float *data = nullptr;
+    gptr<float> data = nullptr;
     int32_t rows = 0, cols = 0;
     int64_t sr = 0, sv = 0;
-    __host__ __device__ __forceinline__ float &at(int r, int j) const { return data[(int64_t)r * sr + (int64_t)j * sv]; }
-    static View of(const fsmt_view &v) { return View{v.data, v.rows, v.cols, v.stride_r, v.stride_v}; }
+    __device__ __forceinline__ gref<float> at(int r, int j) const { return data[(int64_t)r * sr + (int64_t)j * sv]; }
+    static View of(const fsmt_view &v) { return View{as_gptr(v.data), v.rows, v.cols, v.stride_r, v.stride_v}; }
 };
 
 // Hardware float atomic add in L2 (global_atomic_add_f32) on coarse-grained device memory.
+__device__ __forceinline__ void atomic_add_f32(gptr<float> p, float v) { unsafeAtomicAdd((float *)p, v); }
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) { unsafeAtomicAdd(p, v); }
 
-// Wave-uniform node record through the scalar unit.
-__device__ __forceinline__ Node load_node(const Node *p) {
-    const uint2 raw = *reinterpret_cast<const uint2 *>(p);
+// Index of this thread's wavefront in the block, as a wave-uniform (scalar) value: the
+// compiler does not know that threadIdx.x / 64 is uniform across a wave64.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Node record at a wave-uniform address (a scalar load); its fields are marked uniform so
+// that the message arrays are indexed with scalar indices.
+__device__ __forceinline__ Node load_node(cptr<Node> p) {
+    const u32x2 raw = *(cptr<u32x2>)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane(raw.x), hi = __builtin_amdgcn_readfirstlane(raw.y);
     Node n;
     n.slot = (uint16_t)(lo & 0xFFFFu);
@@ -28,6 +51,26 @@ __device__ __forceinline__ Node load_node(const Node *p) {
     n.lo = (uint16_t)(hi & 0xFFFFu);
     n.pad = 0;
     return n;
+}
+
+// Node record at a per-lane address (a vector load).
+__device__ __forceinline__ Node load_node_lane(cptr<Node> p) {
+    const u32x2 raw = *(cptr<u32x2>)p;
+    Node n;
+    n.slot = (uint16_t)(raw.x & 0xFFFFu);
+    n.hi = (uint16_t)(raw.x >> 16);
+    n.lo = (uint16_t)(raw.y & 0xFFFFu);
+    n.pad = 0;
+    return n;
+}
+
+// Bucket record (64 bytes; one s_load_dwordx16 at a wave-uniform address).
+__device__ __forceinline__ BucketInfo load_bucket(cptr<BucketInfo> p) {
+    static_assert(sizeof(BucketInfo) == 64, "bucket record layout");
+    const i32x16 raw = *(cptr<i32x16>)p;
+    BucketInfo b;
+    __builtin_memcpy(&b, &raw, sizeof(b));
+    return b;
 }
 
 // Sum over a block of up to 1024 threads (result valid in every thread).
@@ -46,8 +89,8 @@ __device__ __forceinline__ float block_sum(float v) {
 
 // Half-spaces q.y <= rhs of the feasible set (multi-variable unit atoms).
 struct HalfSpaces {
-    const int32_t *ptr, *var;
-    const float *coef, *rhs, *inv;
+    cptr<int32_t> ptr, var;
+    cptr<float> coef, rhs, inv;
     int32_t n, nnz;
 };
 
@@ -56,7 +99,7 @@ struct HalfSpaces {
 // Dykstra's alternating projections run from y (half-spaces in order, then the box, per
 // sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no coordinate by more than
 // 4e-7 (1 + |y|), or 256 sweeps. All threads of the block must call it.
-__device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, const float *lo, const float *hi,
+__device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, cptr<float> lo, cptr<float> hi,
                                                 int m, const HalfSpaces &hs) {
     for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
     __syncthreads();

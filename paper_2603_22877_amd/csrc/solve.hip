@@ -25,15 +25,15 @@ constexpr int kMaxLevels = 128;
 struct InstDesc {
     TabView T;
     HalfSpaces hs;
-    float *a, *b;
+    gptr<float> a, b;
     int64_t a_sr, b_sr;
-    float *w, *hist;
-    uint32_t *sat_bits;
-    int32_t *n_unsat, *verdict, *level_done, *steps_done;
-    float *obj;
-    float *part;        // [R][k][n + m + 1] partial gradients and objective (k > 1)
-    int32_t *bar;       // [R] cluster barrier counters (k > 1)
-    int32_t *ctl;       // [R][2] level result published by rank 0: n_unsat, stop (k > 1)
+    gptr<float> w, hist;
+    gptr<uint32_t> sat_bits;
+    gptr<int32_t> n_unsat, verdict, level_done, steps_done;
+    gptr<float> obj;
+    gptr<float> part;       // [R][k][n + m + 1] partial gradients and objective (k > 1)
+    gptr<int32_t> bar;      // [R] cluster barrier counters (k > 1)
+    gptr<int32_t> ctl;      // [R][2] level result published by rank 0: n_unsat, stop (k > 1)
     int32_t R, wg_base, k, pad;
 };
 
@@ -62,7 +62,8 @@ __device__ __forceinline__ int find_inst(const InstDesc *I, int n, int wg) {
 // waiting workgroup leaves, so the grid always drains. Returns false on abort.
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ bool cluster_sync(int32_t *bar, int target, int32_t *abort_flag) {
+__device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, int32_t *abort_flag) {
+    int32_t *bar = (int32_t *)bar_g;
     __syncthreads();
     int ok = 1;
     if (threadIdx.x == 0) {
@@ -88,17 +89,19 @@ __device__ __forceinline__ bool cluster_sync(int32_t *bar, int target, int32_t *
 template <int V> struct SolveWaves { static constexpr int value = 16; };
 template <> struct SolveWaves<kMsgMedium> { static constexpr int value = 8; };
 
-template <int V>
+// kCluster: k workgroups per restart (k read from the descriptor); otherwise k = 1 and the
+// kernel carries none of the cluster's exchange state.
+template <int V, bool kCluster>
 __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
     solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags, int32_t *abort_flag) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int ii = find_inst(insts, P.n_inst, blockIdx.x);
     const InstDesc &I = insts[ii];
     const TabView T = I.T;
     const HalfSpaces hs = I.hs;
-    const int k = I.k;
+    const int k = kCluster ? I.k : 1;
     const int local = blockIdx.x - I.wg_base;
     const int r = local / k, rank = local - r * k;
     const int n = T.n_bool, m = T.n_real, C = T.n_cons;
@@ -106,10 +109,10 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
     float *sa = lds, *sb = sa + n, *ga = sb + m, *gb = ga + n, *pb = gb + m, *ph = pb + m;
     const int NN = P.lds_nodes + 2, SS = P.lds_slots;
     FSMT_MSG_STORE(Ms, W, lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS, lane);
-    float *wrow = I.w + (int64_t)r * C, *hrow = I.hist + (int64_t)r * C;
-    uint32_t *brow = I.sat_bits + (int64_t)r * nw;
+    const gptr<float> wrow = I.w + (int64_t)r * C, hrow = I.hist + (int64_t)r * C;
+    const gptr<uint32_t> brow = I.sat_bits + (int64_t)r * nw;
     const int64_t pstride = (int64_t)n + m + 1;
-    float *prow = k > 1 ? I.part + (int64_t)r * k * pstride : nullptr;
+    const gptr<float> prow = kCluster ? I.part + (int64_t)r * k * pstride : nullptr;
     int bar_target = 0;
 
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -144,11 +147,11 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 oacc += wc * unsat;
                 task_backward(T, t, wc, sc, W, lane);
             }
-            if (k > 1) {
+            if (kCluster) {
                 // publish this workgroup's partial gradient and objective, then sum the
                 // cluster's partials in rank order (every rank gets the same bits)
                 const float op = block_sum(oacc);
-                float *mine = prow + (int64_t)rank * pstride;
+                const gptr<float> mine = prow + (int64_t)rank * pstride;
                 for (int i = threadIdx.x; i < n + m; i += blockDim.x) mine[i] = ga[i];
                 if (threadIdx.x == 0) mine[n + m] = op;
                 bar_target += k;
@@ -237,12 +240,12 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             }
             if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
             stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
-            if (k > 1 && threadIdx.x == 0) {
+            if (kCluster && threadIdx.x == 0) {
                 I.ctl[2 * r] = n_unsat;
                 I.ctl[2 * r + 1] = stop;
             }
         }
-        if (k > 1) {
+        if (kCluster) {
             bar_target += k;
             if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
                 aborted = true;
@@ -285,8 +288,9 @@ static int lds_budget_bytes() {
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > budget)
             budget = v;
-        const void *fns[] = {(const void *)solve_wg_kernel<kMsgLds>, (const void *)solve_wg_kernel<kMsgSmall>,
-                             (const void *)solve_wg_kernel<kMsgMedium>};
+        const void *fns[] = {(const void *)solve_wg_kernel<kMsgLds, false>, (const void *)solve_wg_kernel<kMsgSmall, false>,
+                             (const void *)solve_wg_kernel<kMsgMedium, false>, (const void *)solve_wg_kernel<kMsgLds, true>,
+                             (const void *)solve_wg_kernel<kMsgSmall, true>, (const void *)solve_wg_kernel<kMsgMedium, true>};
         for (const void *f : fns) {
             if (budget > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
                 (void)hipGetLastError();
@@ -353,6 +357,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         device = h->device;
         const int R = S.a.rows;
         if (R <= 0) return set_error(FSMT_EINVAL, "instance %d: no restarts", i);
+        if (h->n_big > 0)
+            return set_error(FSMT_EUNSUPPORTED, "instance %d: %d constraints have diagrams too large for the fused solver "
+                             "(use cop_backward / pgd_step)", i, h->n_big);
         if (S.a.cols != h->n_bool || S.b.rows != R || S.b.cols != h->n_real)
             return set_error(FSMT_EINVAL, "instance %d: state shape does not match the instance", i);
         if ((h->n_bool > 1 && S.a.stride_v != 1) || (h->n_real > 1 && S.b.stride_v != 1) ||
@@ -373,8 +380,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     std::vector<char> use_grid(n_inst, 0);
     for (int i = 0; i < n_inst; ++i) {
         const fsmt_xbdd *h = insts[i];
-        const int mv = msg_variant(h->max_nodes, h->max_slots, h->lds_messages);
-        const size_t wb = mv == kMsgLds ? WaveScratch::bytes(h->max_nodes + 2, std::max(h->max_slots, 1)) : 0;
+        const int mv = msg_variant(h->small_max_nodes, h->small_max_slots, h->lds_messages, h->all_inline);
+        const size_t wb = mv == kMsgLds ? WaveScratch::bytes(h->small_max_nodes + 2, std::max(h->small_max_slots, 1)) : 0;
         const size_t sb = state_floats_of(h) * sizeof(float);
         const bool fits = sb + wb <= budget;
         const int waves = !fits ? 0 : wb ? (int)std::min<size_t>(16, (budget - sb) / wb) : solve_waves(mv);
@@ -423,21 +430,25 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         for (size_t q = 0; q < ia.size(); ++q) {
             const fsmt_xbdd *h = insts[ia[q]];
             state_f = std::max(state_f, state_floats_of(h));
-            maxn = std::max(maxn, h->max_nodes);
-            maxs = std::max(maxs, h->max_slots);
+            maxn = std::max(maxn, h->small_max_nodes);
+            maxs = std::max(maxs, h->small_max_slots);
             total_r += states[ia[q]].a.rows;
             min_tasks = std::min<int64_t>(min_tasks, h->n_pos / 64);
         }
-        bool lds_only = false;
-        for (size_t q = 0; q < ia.size(); ++q) lds_only = lds_only || insts[ia[q]]->lds_messages;
-        const int msg = msg_variant(maxn, maxs, lds_only);
+        bool lds_only = false, all_inline = true;
+        for (size_t q = 0; q < ia.size(); ++q) {
+            lds_only = lds_only || insts[ia[q]]->lds_messages;
+            all_inline = all_inline && insts[ia[q]]->all_inline;
+        }
+        const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
         const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
         const size_t state_bytes = state_f * sizeof(float);
         const int waves = wave_bytes ? (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes) : solve_waves(msg);
         const size_t lds = state_bytes + (size_t)waves * wave_bytes;
-        const void *kern = msg == kMsgSmall    ? (const void *)solve_wg_kernel<kMsgSmall>
-                           : msg == kMsgMedium ? (const void *)solve_wg_kernel<kMsgMedium>
-                                               : (const void *)solve_wg_kernel<kMsgLds>;
+        const bool cl = O.cluster > 1;
+        const void *kern = msg == kMsgSmall    ? (cl ? (const void *)solve_wg_kernel<kMsgSmall, true> : (const void *)solve_wg_kernel<kMsgSmall, false>)
+                           : msg == kMsgMedium ? (cl ? (const void *)solve_wg_kernel<kMsgMedium, true> : (const void *)solve_wg_kernel<kMsgMedium, false>)
+                                               : (cl ? (const void *)solve_wg_kernel<kMsgLds, true> : (const void *)solve_wg_kernel<kMsgLds, false>);
         // workgroups per restart: a cluster of k co-resident workgroups shares one restart's
         // sweep (all of them must be resident at once: their barrier waits for each other)
         int occ = 1;
@@ -464,18 +475,18 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             InstDesc &d = desc[q];
             d.T = TabView::of(h);
             d.hs = halfspaces_of(h);
-            d.a = S.a.data;
-            d.b = S.b.data;
+            d.a = as_gptr(S.a.data);
+            d.b = as_gptr(S.b.data);
             d.a_sr = S.a.stride_r;
             d.b_sr = S.b.stride_r;
-            d.w = S.w;
-            d.hist = S.hist;
-            d.sat_bits = S.sat_bits;
-            d.n_unsat = S.n_unsat;
-            d.verdict = S.verdict;
-            d.level_done = S.level_done;
-            d.steps_done = S.steps_done;
-            d.obj = S.obj;
+            d.w = as_gptr(S.w);
+            d.hist = as_gptr(S.hist);
+            d.sat_bits = as_gptr(S.sat_bits);
+            d.n_unsat = as_gptr(S.n_unsat);
+            d.verdict = as_gptr(S.verdict);
+            d.level_done = as_gptr(S.level_done);
+            d.steps_done = as_gptr(S.steps_done);
+            d.obj = as_gptr(S.obj);
             d.R = S.a.rows;
             d.k = k;
             d.wg_base = (int32_t)wg;
@@ -502,9 +513,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             float *part = (float *)((char *)dbuf + off_part);
             int64_t rb = 0, pb = 0;
             for (InstDesc &d : desc) {
-                d.bar = bar + rb;
-                d.ctl = ctl + 2 * rb;
-                d.part = k > 1 ? part + pb : nullptr;
+                d.bar = as_gptr(bar + rb);
+                d.ctl = as_gptr(ctl + 2 * rb);
+                d.part = k > 1 ? as_gptr(part + pb) : nullptr;
                 rb += d.R;
                 if (k > 1) pb += (int64_t)d.R * k * ((int64_t)d.T.n_bool + d.T.n_real + 1);
             }
@@ -514,12 +525,18 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             } else {
                 const dim3 g((unsigned)wg), b(64 * waves);
                 const InstDesc *d = (const InstDesc *)dbuf;
-                if (msg == kMsgSmall)
-                    hipLaunchKernelGGL(solve_wg_kernel<kMsgSmall>, g, b, lds, st, d, P, flags, abort_flag);
+                if (msg == kMsgSmall && k > 1)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgSmall, true>), g, b, lds, st, d, P, flags, abort_flag);
+                else if (msg == kMsgSmall)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgSmall, false>), g, b, lds, st, d, P, flags, abort_flag);
+                else if (msg == kMsgMedium && k > 1)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, true>), g, b, lds, st, d, P, flags, abort_flag);
                 else if (msg == kMsgMedium)
-                    hipLaunchKernelGGL(solve_wg_kernel<kMsgMedium>, g, b, lds, st, d, P, flags, abort_flag);
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, false>), g, b, lds, st, d, P, flags, abort_flag);
+                else if (k > 1)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLds, true>), g, b, lds, st, d, P, flags, abort_flag);
                 else
-                    hipLaunchKernelGGL(solve_wg_kernel<kMsgLds>, g, b, lds, st, d, P, flags, abort_flag);
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLds, false>), g, b, lds, st, d, P, flags, abort_flag);
                 rc = launch_status("solver kernel");
             }
             (void)hipFreeAsync(dbuf, st);
@@ -539,22 +556,22 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             GridInst &d = gi[q];
             d.T = TabView::of(h);
             d.hs = halfspaces_of(h);
-            d.a = S.a.data;
-            d.b = S.b.data;
+            d.a = as_gptr(S.a.data);
+            d.b = as_gptr(S.b.data);
             d.a_sr = S.a.stride_r;
             d.b_sr = S.b.stride_r;
-            d.ga = S.grad_a;
-            d.gb = S.grad_b;
+            d.ga = as_gptr(S.grad_a);
+            d.gb = as_gptr(S.grad_b);
             d.ga_sr = h->n_bool;
             d.gb_sr = h->n_real;
-            d.w = S.w;
-            d.hist = S.hist;
-            d.sat_bits = S.sat_bits;
-            d.n_unsat = S.n_unsat;
-            d.verdict = S.verdict;
-            d.level_done = S.level_done;
-            d.steps_done = S.steps_done;
-            d.obj = S.obj;
+            d.w = as_gptr(S.w);
+            d.hist = as_gptr(S.hist);
+            d.sat_bits = as_gptr(S.sat_bits);
+            d.n_unsat = as_gptr(S.n_unsat);
+            d.verdict = as_gptr(S.verdict);
+            d.level_done = as_gptr(S.level_done);
+            d.steps_done = as_gptr(S.steps_done);
+            d.obj = as_gptr(S.obj);
             d.R = S.a.rows;
             int rp = 1, lg = 0;
             while (rp < d.R && rp < 64) { rp <<= 1; ++lg; }
@@ -567,13 +584,16 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             tasks += d.R <= 64 ? (int64_t)h->n_pos * d.R_pad / 64 : (int64_t)h->n_pos * (d.R_pad / 64);
             checks += (int64_t)d.R * ((h->n_cons + 255) / 256);
             if (!S.grad_a || !S.grad_b) scratch_floats += (int64_t)d.R * (h->n_bool + h->n_real);
-            maxn = std::max(maxn, h->max_nodes);
-            maxs = std::max(maxs, h->max_slots);
+            maxn = std::max(maxn, h->small_max_nodes);
+            maxs = std::max(maxs, h->small_max_slots);
             if (h->n_hs) step_lds = std::max(step_lds, (size_t)(2 * h->n_real + h->hs_nnz) * sizeof(float));
         }
-        bool lds_only = false;
-        for (size_t q = 0; q < ib.size(); ++q) lds_only = lds_only || insts[ib[q]]->lds_messages;
-        const int msg = msg_variant(maxn, maxs, lds_only);
+        bool lds_only = false, all_inline = true;
+        for (size_t q = 0; q < ib.size(); ++q) {
+            lds_only = lds_only || insts[ib[q]]->lds_messages;
+            all_inline = all_inline && insts[ib[q]]->all_inline;
+        }
+        const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
         const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
         if (wave_bytes > 65536) rc = set_error(FSMT_ELIMIT, "diagram too large for the grid schedule");
         if (step_lds > 65536) rc = set_error(FSMT_ELIMIT, "projection work arrays exceed LDS");
@@ -595,8 +615,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             float *grd = (float *)(base + off_grd);
             for (GridInst &d : gi) {
                 if (!d.ga || !d.gb) {
-                    d.ga = grd;
-                    d.gb = grd + (int64_t)d.R * d.T.n_bool;
+                    d.ga = as_gptr(grd);
+                    d.gb = as_gptr(grd + (int64_t)d.R * d.T.n_bool);
                     grd += (int64_t)d.R * (d.T.n_bool + d.T.n_real);
                 }
             }

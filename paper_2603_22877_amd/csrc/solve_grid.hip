@@ -54,7 +54,7 @@ template <int V>
 __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, int n_inst, GridShared S) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
-    const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wib = wave_id(), wpb = blockDim.x >> 6;
     const int NN = S.lds_nodes + 2, SS = S.lds_slots;
     FSMT_MSG_STORE(Ms, W, lds + (size_t)wib * (2 * NN + 4 * SS) * 64, NN, SS, lane);
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
@@ -89,20 +89,21 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
             cur_R = I.R <= 64 ? I.R : 0;
         }
         const bool r_ok = r < I.R && S.stepping[I.rbase + r] != 0;
-        const GlobalState st{View{I.a, I.R, I.T.n_bool, I.a_sr, 1}, View{I.b, I.R, I.T.n_real, I.b_sr, 1}};
-        const GlobalScatter sc{View{I.ga, I.R, I.T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, I.T.n_real, I.gb_sr, 1},
+        const TabView T = I.T;
+        const GlobalState st{View{I.a, I.R, T.n_bool, I.a_sr, 1}, View{I.b, I.R, T.n_real, I.b_sr, 1}};
+        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1},
                                I.R_pad < 64 ? I.R_pad : 64};
-        const TaskCtx t = task_ctx(I.T, pos, r, r_ok);
+        const TaskCtx t = task_ctx(T, pos, r, r_ok);
         const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
         const bool hard = isinf(kappa);
-        const float unsat = task_forward(I.T, t, st, kappa, hard, W);
-        const float wc = t.valid ? I.w[(int64_t)r * I.T.n_cons + t.c] : 0.0f;
+        const float unsat = task_forward(T, t, st, kappa, hard, W);
+        const float wc = t.valid ? I.w[(int64_t)r * T.n_cons + t.c] : 0.0f;
         if (I.R_pad <= 64) {
             oacc += wc * unsat;
         } else if (r < I.R && wc * unsat != 0.0f) {
             atomic_add_f32(S.obj_acc + I.rbase + r, wc * unsat);
         }
-        task_backward(I.T, t, wc, sc, W, lane);
+        task_backward(T, t, wc, sc, W, lane);
     }
     flush();
 }
@@ -116,8 +117,8 @@ __global__ void __launch_bounds__(256) grid_step_kernel(const GridInst *insts, i
     const int r = g - I.rbase;
     if (!S.stepping[g]) return;
     const int n = I.T.n_bool, m = I.T.n_real;
-    float *arow = I.a + (int64_t)r * I.a_sr, *brow = I.b + (int64_t)r * I.b_sr;
-    float *garow = I.ga + (int64_t)r * I.ga_sr, *gbrow = I.gb + (int64_t)r * I.gb_sr;
+    const gptr<float> arow = I.a + (int64_t)r * I.a_sr, brow = I.b + (int64_t)r * I.b_sr;
+    const gptr<float> garow = I.ga + (int64_t)r * I.ga_sr, gbrow = I.gb + (int64_t)r * I.gb_sr;
     float acc = 0.0f;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const float x = arow[i], y = x - S.eta_a * garow[i];
@@ -177,10 +178,10 @@ __global__ void __launch_bounds__(256) grid_check_kernel(const GridInst *insts, 
     const uint64_t mask = __ballot(sat);
     const uint64_t valid = __ballot(c < C);
     if (lane == 0 && valid) {
-        uint32_t *row = I.sat_bits + (int64_t)r * nw;
+        const gptr<uint32_t> row = I.sat_bits + (int64_t)r * nw;
         row[c64 >> 5] = (uint32_t)mask;
         if ((c64 >> 5) + 1 < nw) row[(c64 >> 5) + 1] = (uint32_t)(mask >> 32);
-        atomicAdd(I.n_unsat + r, (int)__popcll(valid & ~mask));
+        atomicAdd((int32_t *)(I.n_unsat + r), (int)__popcll(valid & ~mask));
     }
 }
 
@@ -194,8 +195,8 @@ __global__ void __launch_bounds__(1024) grid_end_kernel(const GridInst *insts, i
     const int C = I.T.n_cons, nw = (C + 31) >> 5;
     const int level = I.level_done[r];
     const bool update = ((level + 1) % S.tau) == 0;
-    float *wr = I.w + (int64_t)r * C, *hr = I.hist + (int64_t)r * C;
-    const uint32_t *br = I.sat_bits + (int64_t)r * nw;
+    const gptr<float> wr = I.w + (int64_t)r * C, hr = I.hist + (int64_t)r * C;
+    const gptr<uint32_t> br = I.sat_bits + (int64_t)r * nw;
     float ws = 0.0f;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const float viol = ((br[c >> 5] >> (c & 31)) & 1u) ? 0.0f : 1.0f;

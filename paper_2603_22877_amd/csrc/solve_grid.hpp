@@ -7,12 +7,12 @@ namespace fsmt {
 struct GridInst {
     TabView T;
     HalfSpaces hs;
-    float *a, *b, *ga, *gb;         // row-major [R][n] rows with unit column stride
+    gptr<float> a, b, ga, gb;       // row-major [R][n] rows with unit column stride
     int64_t a_sr, b_sr, ga_sr, gb_sr;
-    float *w, *hist;                // [R][C]
-    uint32_t *sat_bits;
-    int32_t *n_unsat, *verdict, *level_done, *steps_done;
-    float *obj;
+    gptr<float> w, hist;            // [R][C]
+    gptr<uint32_t> sat_bits;
+    gptr<int32_t> n_unsat, verdict, level_done, steps_done;
+    gptr<float> obj;
     int32_t R, R_pad, log2_rpad, rbase;   // rbase: first global restart index
     int64_t task_base;                    // first sweep task (wave) of this instance
     int64_t check_base;                   // first check block of this instance

@@ -420,23 +420,38 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     h->nnz = (int64_t)a_var.size();
     std::vector<TplInfo> tinfo(T);
     std::vector<Node> nodes;
+    std::vector<int32_t> lev;   // level starts: nodes are sorted by slot, so each level is a range
     for (int t = 0; t < T; ++t) {
         const Template &tp = tpls[t];
-        tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, {0, 0, 0}};
+        tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, (int32_t)lev.size(), {0, 0}};
+        int v = 0;
+        for (int sl = 0; sl <= tp.n_slots; ++sl) {
+            while (v < tp.n_nodes && tp.nodes[v].slot < sl) ++v;
+            lev.push_back(v);
+        }
         nodes.insert(nodes.end(), tp.nodes.begin(), tp.nodes.end());
         h->max_nodes = std::max(h->max_nodes, tp.n_nodes);
         h->max_slots = std::max(h->max_slots, tp.n_slots);
+        if (members[t].empty()) continue;
+        if (big_diagram(tp.n_nodes, tp.n_slots)) {
+            h->big_max_nodes = std::max(h->big_max_nodes, tp.n_nodes);
+            h->big_max_slots = std::max(h->big_max_slots, tp.n_slots);
+        } else {
+            h->small_max_nodes = std::max(h->small_max_nodes, tp.n_nodes);
+            h->small_max_slots = std::max(h->small_max_slots, tp.n_slots);
+        }
     }
     std::vector<BucketInfo> buckets;
-    std::vector<int32_t> bstart{0}, pos_con, con_bucket(C), con_local(C), sup;
+    std::vector<int32_t> bstart{0}, pos_con, con_bucket(C), con_local(C), sup, big_pos;
     for (int t = 0; t < T; ++t) {
         if (members[t].empty()) continue;
         const int nc = (int)members[t].size();
         const int npos = (nc + 63) / 64 * 64;
         const int ns = tpls[t].n_slots;
         const TplInfo &ti = tinfo[t];
+        const int big = big_diagram(ti.n_nodes, ti.n_slots) ? 1 : 0;
         BucketInfo bi{t, bstart.back(), npos, nc, (int64_t)sup.size(), -1, ti.node_off, ti.n_nodes, ti.n_slots,
-                      ti.n_bslots, ti.root, {0, 0, 0}};
+                      ti.n_bslots, ti.root, ti.lev_off, big, 0};
         const int b_id = (int)buckets.size();
         sup.resize(sup.size() + (size_t)ns * npos, 0);
         for (int i = 0; i < npos; ++i) {
@@ -445,6 +460,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             if (c < 0) continue;
             con_bucket[c] = b_id;
             con_local[c] = i;
+            if (big) big_pos.push_back(bstart.back() + i);
             for (int s = 0; s < ns; ++s) sup[bi.sup_base + (int64_t)s * npos + i] = con_ids[con_sup_off[c] + s];
             h->total_nodes += tpls[t].n_nodes;
         }
@@ -557,6 +573,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     }
 
     h->n_box_units = h_box_units;
+    h->n_big = (int)big_pos.size();
     h->n_hs = (int)hs_rhs.size();
     h->hs_nnz = (int)hs_var.size();
     if (host_only) {
@@ -582,6 +599,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.sup, sup, "supports");
     if (!rc) rc = U.put(&h->d.con_bucket, con_bucket, "constraint buckets");
     if (!rc) rc = U.put(&h->d.con_local, con_local, "constraint positions");
+    if (!rc) rc = U.put(&h->d.lev, lev, "level starts");
+    if (!rc) rc = U.put(&h->d.big_pos, big_pos, "big-diagram positions");
+    h->all_inline = all_inline;
     if (all_inline) {   // every atom is reached through its inline record
         a_ptr.assign(1, 0);
         a_var.clear();
@@ -642,6 +662,7 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->n_templates = h->n_tpl;
     s->max_nodes = h->max_nodes;
     s->max_slots = h->max_slots;
+    s->n_big = h->n_big;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

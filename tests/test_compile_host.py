@@ -209,3 +209,22 @@ def test_runtime_calls_reject_host_only_handles():
     with pytest.raises(fsmt.FsmtError) as e:
         fsmt.cop_forward(h, a, a, 1.0, torch.ones(2), torch.zeros(1), stream=0)
     assert e.value.code == _abi.FSMT_EINVAL
+
+
+def test_big_diagrams_are_classified_and_levelized():
+    """Long symmetric constraints are marked big (level-synchronous kernel); nodes of every
+    diagram are stored level by level (slots non-decreasing), children on deeper levels."""
+    p = W.make_random_hybrid(100)
+    h = compile_host(p)
+    info = fsmt.xbdd_info(h)
+    assert info["n_big"] == p.n_cons and info["max_nodes"] > 100
+    for cfg in (1, 2, 3):
+        assert fsmt.xbdd_info(compile_host(W.make_config(cfg)))["n_big"] == 0
+    for c in range(p.n_cons):
+        d = fsmt.xbdd_export_diagram(h, c)
+        nodes, N = d["nodes"], d["n_nodes"]
+        slots = nodes[:, 0]
+        assert np.all(np.diff(slots) >= 0)
+        for v in range(N):
+            for ch in nodes[v, 1:]:
+                assert ch >= N or slots[ch] > slots[v]

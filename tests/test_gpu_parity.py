@@ -82,6 +82,36 @@ def test_message_store_bounds(max_len, seed):
         _compare(p, a, b, kap)
 
 
+@pytest.mark.parametrize("n,R", [(100, 1), (100, 5), (200, 3), (300, 2)])
+def test_big_diagrams_random_hybrid(n, R):
+    """Random hybrid instances: every constraint is a long CARD/NAE/XOR (level kernel)."""
+    p = W.make_random_hybrid(n)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"random hybrid n={n} R={R} nodes={info['max_nodes']} big={info['n_big']}", flush=True)
+    assert info["n_big"] == p.n_cons
+    a, b = W.initial_points(p, R, 6, n)
+    for kap in (0.0, 0.7, 5.0, INF):
+        _compare(p, a, b, kap, w=np.random.default_rng(n).uniform(0.5, 2, (R, p.n_cons)))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("R", [1, 7, 70])
+def test_mixed_small_and_big_diagrams(seed, R):
+    """One launch of each kernel: short constraints one lane each, long ones level by level
+    (CSR atoms with up to 3 nonzeros, so the level kernel's CSR path runs too)."""
+    from workloads.format import KIND_AND, KIND_CARD_GE, KIND_CARD_LE, KIND_CLAUSE, KIND_NAE, KIND_XOR
+    p = W.make_random_formula(4000 + seed, n_bool=16, n_real=5, n_atoms=16, n_cons=80, max_len=32,
+                              allow_repeats=False,
+                              kinds=(KIND_CLAUSE, KIND_AND, KIND_XOR, KIND_NAE, KIND_CARD_LE, KIND_CARD_GE))
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"mixed seed={seed} R={R} big={info['n_big']} of {p.n_cons}", flush=True)
+    assert 0 < info["n_big"] < p.n_cons
+    a, b = W.initial_points(p, R, 96, seed)
+    for kap in (0.4, 3.0):
+        _compare(p, a, b, kap)
+        _compare(p, a, b, kap, layout="cols")
+
+
 def test_fig2_toy_values():
     p = W.make_fig2_toy()
     a = np.array([[0.3], [-0.9], [1.0]], np.float32)

@@ -183,6 +183,34 @@ def test_solver_rejects_bad_options():
     with pytest.raises(fsmt.FsmtError):
         S.solve_batched([h], [st], S.SolveConfig(kappas=[-1.0]))
     assert int(st.level_done.max()) == 0
+    # big diagrams are per-call only: the fused solver refuses them without launching
+    hb = fsmt.xbdd_compile(W.make_random_hybrid(100))
+    ab, bb = W.initial_points(W.make_random_hybrid(100), 2, 6, 0)
+    stb = S.BatchState(hb, ab, bb)
+    with pytest.raises(fsmt.FsmtError) as e:
+        S.solve_batched([hb], [stb], S.SolveConfig(kappas=[0.1]))
+    assert e.value.code == fsmt._abi.FSMT_EUNSUPPORTED
+    assert int(stb.level_done.max()) == 0
+
+
+def test_plain_solver_on_big_diagrams_descends():
+    """The per-call path (level kernel + PGD) lowers the objective of a random hybrid
+    instance whose diagrams are all big."""
+    p = W.make_random_hybrid(200)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, 1, 6, 1)
+    ps = S.PlainSolver(h, R=1)
+    a = torch.as_tensor(a0, device=dev()); b = torch.as_tensor(b0, device=dev())
+    w = torch.ones(p.n_cons, device=dev())
+    obj0 = torch.zeros(1, device=dev())
+    fsmt.cop_forward(h, a, b, 0.5, w, obj0)
+    out = ps.run(a0, b0, S.SolveConfig(kappas=[0.5] * 3, steps_per_level=50, eta_a=0.2, eta_b=0.5, eps=0.0,
+                                        stop_on_sat=0))
+    obj1 = torch.zeros(1, device=dev())
+    fsmt.cop_forward(h, out["a"], out["b"], 0.5, w, obj1)
+    torch.cuda.synchronize()
+    print(f"random hybrid 200: U {float(obj0[0]):.4f} -> {float(obj1[0]):.4f}", flush=True)
+    assert float(obj1[0]) < float(obj0[0])
 
 
 def _run(h, a, b, cfg):
