@@ -17,6 +17,11 @@ public; the generator is in workloads/scheduling.py).
 * roofline: the solver kernel's duration from HIP events on its stream; algorithmic
   FLOP and byte counts per launch (model in the design doc).
 * cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread).
+* paper_protocol: the paper's gradient-timing protocol (Supplementary Note "Gradient
+  Computation Time"): random hybrid instances with n Booleans, n reals and n atoms, 100
+  annealing parameters x 100 points, one cop_backward call (objective + gradient) per
+  parameter; reported next to the paper's L40S figure as context (other hardware, other
+  instances of the same shape).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-tts]
 """
@@ -48,6 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-SAT comparison")
+    ap.add_argument("--no-protocol", action="store_true", help="skip the paper's gradient-timing protocol")
     ap.add_argument("--tts-seeds", type=int, default=5)
     ap.add_argument("--tts-cap", type=float, default=30.0, help="time limit per instance (s)")
     ap.add_argument("--pmc-mode", action="store_true",
@@ -122,40 +128,45 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written
         state = S.BatchState(h, a0, b0)
-        S.solve_batched([h], [state], fixed_cfg(2), stream=st)
+        for i in range(3):                   # three launches of one level each, as timed
+            S.solve_batched([h], [state], fixed_cfg(i + 1), stream=st)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4}))
         return
 
-    levels = max(1, min(args.steps, 128))
-    warm = S.BatchState(h, a0, b0)
-    S.solve_batched([h], [warm], fixed_cfg(max(1, min(args.warmup, 128))), stream=st)
-    torch.cuda.synchronize()
+    # one step = one annealing level = one fused launch (the solver resumes each restart at
+    # its level counter), so warmup and timed launches carry identical work
+    levels = max(1, min(args.steps, 128 - args.warmup))
     state = S.BatchState(h, a0, b0)
+    for i in range(args.warmup):
+        S.solve_batched([h], [state], fixed_cfg(i + 1), stream=st)
+    torch.cuda.synchronize()
+    steps0 = int(state.steps_done.cpu().numpy().min())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(st)
-    S.solve_batched([h], [state], fixed_cfg(levels), stream=st)
+    for i in range(levels):
+        S.solve_batched([h], [state], fixed_cfg(args.warmup + i + 1), stream=st)
     e1.record(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kern_s = e0.elapsed_time(e1) * 1e-3
-    pgd_steps = int(state.steps_done.cpu().numpy().min())
+    kern_s = e0.elapsed_time(e1) * 1e-3 / levels        # average launch (one level)
+    pgd_steps = int(state.steps_done.cpu().numpy().min()) - steps0
     assert pgd_steps == levels * STEPS_PER_LEVEL
     evals = p.n_cons * R * pgd_steps
     value = evals / dt
 
-    fl = flops_per_pass(cost, R) * pgd_steps
-    by = bytes_per_pass(cost, p, R) * pgd_steps
+    # per launch (one level = STEPS_PER_LEVEL PGD iterations over C x R constraint-evals)
+    fl = flops_per_pass(cost, R) * STEPS_PER_LEVEL
+    by = bytes_per_pass(cost, p, R) * STEPS_PER_LEVEL
     ach_tf = fl / kern_s / 1e12
     ach_gbs = by / kern_s / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_solver_sched200.json")
     if os.path.exists(tfile):
         try:
-            tj = json.load(open(tfile))
-            traffic = tj["bytes_per_pgd_step"] * pgd_steps
+            traffic = json.load(open(tfile))["hbm_bytes_per_launch"]
         except Exception:
             traffic = None
 
@@ -172,11 +183,14 @@ def main():
                    "table_bytes": stats["table_bytes"]},
         "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach_tf / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "solve_wg_kernel", "kernel_ms": kern_s * 1e3,
+                     "kernel": "solve_wg_kernel", "kernel_ms_per_launch": kern_s * 1e3,
+                     "flop_per_launch": fl, "bytes_per_launch": by,
                      "hbm_achieved_gbs": ach_gbs, "hbm_frac": ach_gbs / PEAK_HBM_GBS},
     }
     if not args.no_tts:
         out["time_to_sat"] = time_to_sat(args, fsmt, S, W, st)
+    if not args.no_protocol:
+        out["paper_protocol"] = paper_protocol(fsmt, W, st)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a0, b0, kappas[0])
     print(json.dumps(out))
@@ -239,6 +253,44 @@ def time_to_sat(args, fsmt, S, W, st):
             "hyperparameters": {"levels": LEVELS, "kappa": "4 t / (40 mean duration)",
                                 "steps_per_level": STEPS_PER_LEVEL, "eta_a": ETA_A, "eta_b": ETA_B,
                                 "eps": EPS, "rho": 0.5, "gamma": 2.0, "tau": 1}}
+
+
+# mean GPU ms per gradient call reported by the paper for its random hybrid instances
+# (NVIDIA L40S; Supplementary Table "gradient-time", group means over the 10 instances)
+PAPER_L40S_MS = {100: 12.702, 500: 12.603, 1000: 12.653}
+
+
+def paper_protocol(fsmt, W, st, ns=(100, 500, 1000)):
+    """Gradient timing: 100 kappa values (0.00 .. 0.99) x 100 points, one call per kappa."""
+    import torch
+    dev = torch.device("cuda", 0)
+    rows = {}
+    for n in ns:
+        p = W.make_random_hybrid(n)
+        h = fsmt.xbdd_compile(p)
+        a0, b0 = W.initial_points(p, 100, 6, n)
+        a = torch.as_tensor(a0, device=dev)
+        b = torch.as_tensor(b0, device=dev)
+        ga, gb = torch.zeros_like(a), torch.zeros_like(b)
+        w = torch.ones(p.n_cons, device=dev)
+        obj = torch.zeros(100, device=dev)
+        kaps = [0.01 * t for t in range(100)]
+        for k in kaps[:3]:
+            fsmt.cop_backward(h, a, b, k, w, obj, ga, gb, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in kaps:
+            fsmt.cop_backward(h, a, b, k, w, obj, ga, gb, stream=st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = fsmt.xbdd_info(h)
+        rows[str(n)] = {"n_cons": p.n_cons, "max_nodes": info["max_nodes"], "ms_per_call_100_points": dt * 10,
+                        "us_per_point": dt / 10000 * 1e6, "paper_L40S_ms_per_gradient": PAPER_L40S_MS.get(n)}
+    return {"workload": "random hybrid (n Booleans, n reals, n atoms; n/5 CARD and NAE of length "
+                        "min(50, n/5), n/50 XOR of length 50), 100 kappa x 100 points, FP32",
+            "per_n": rows,
+            "note": "the paper does not say whether its figure is per point or per 100-point call; "
+                    "its hardware and instances differ (context, not a target)"}
 
 
 def cpu_baseline(p, a0, b0, kap):

@@ -31,9 +31,9 @@ struct InstDesc {
     gptr<uint32_t> sat_bits;
     gptr<int32_t> n_unsat, verdict, level_done, steps_done;
     gptr<float> obj;
-    gptr<float> part;       // [R][k][n + m + 1] partial gradients and objective (k > 1)
+    gptr<float> part;       // [R][2][k][n + m + 1] partial gradients and objective (k > 1)
     gptr<int32_t> bar;      // [R] cluster barrier counters (k > 1)
-    gptr<int32_t> ctl;      // [R][2] level result published by rank 0: n_unsat, stop (k > 1)
+    gptr<int32_t> ctl;      // [R][2][2] level result published by rank 0: n_unsat, stop (k > 1)
     int32_t R, wg_base, k, pad;
 };
 
@@ -56,19 +56,39 @@ __device__ __forceinline__ int find_inst(const InstDesc *I, int n, int wg) {
     return lo;
 }
 
-// Cluster barrier of the k workgroups that share one restart. Thread 0 publishes this
-// workgroup's writes (agent-scope release), arrives, and waits for the cluster with a
-// bounded spin; on a timeout (or another cluster's abort) it raises the abort flag and every
-// waiting workgroup leaves, so the grid always drains. Returns false on abort.
+// Exchange between the k workgroups that share one restart. Partial gradients, level
+// results and the barrier counter all use agent-scope atomic accesses, which are performed
+// at the device's coherence point (past the per-XCD L2 caches). So no L2 write-back or
+// invalidate is needed: a workgroup makes its stores complete (s_waitcnt) before it
+// arrives, and reads the others' values only after it has seen every arrival. The
+// compiler keeps the accesses in program order around the barrier (signal fences).
+__device__ __forceinline__ void publish(gptr<float> p, float v) {
+    __hip_atomic_store((float *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish(gptr<int32_t> p, int32_t v) {
+    __hip_atomic_store((int32_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float fetch(gptr<float> p) {
+    return __hip_atomic_load((float *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t fetch(gptr<int32_t> p) {
+    return __hip_atomic_load((int32_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cluster barrier: every thread's published stores complete, thread 0 arrives and waits
+// for the cluster with a bounded spin; on a timeout (or another cluster's abort) it raises
+// the abort flag and every waiting workgroup leaves, so the grid always drains. Returns
+// false on abort.
 constexpr unsigned kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, int32_t *abort_flag) {
     int32_t *bar = (int32_t *)bar_g;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's published stores have completed
     __syncthreads();
     int ok = 1;
     if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(bar, 1);
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
@@ -79,9 +99,10 @@ __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, in
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        __threadfence();   // acquire: the cluster's partials and rank 0's level results
     }
-    return __syncthreads_and(ok) != 0;
+    const bool all = __syncthreads_and(ok) != 0;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return all;
 }
 
 // Waves per workgroup of the solver kernel for each message variant: register-resident
@@ -110,9 +131,19 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
     const int NN = P.lds_nodes + 2, SS = P.lds_slots;
     FSMT_MSG_STORE(Ms, W, lds + P.state_floats + (size_t)wave * (2 * NN + 4 * SS) * 64, NN, SS, lane);
     const gptr<float> wrow = I.w + (int64_t)r * C, hrow = I.hist + (int64_t)r * C;
+    // the ERWA weights are written by rank 0 at the end of a level and read by every rank's
+    // sweep: in a cluster they go through the coherence point like the partials
+    auto wload = [&](int c) -> float { return kCluster ? fetch(wrow + c) : (float)wrow[c]; };
+    auto wstore = [&](int c, float v) {
+        if (kCluster) publish(wrow + c, v); else wrow[c] = v;
+    };
     const gptr<uint32_t> brow = I.sat_bits + (int64_t)r * nw;
     const int64_t pstride = (int64_t)n + m + 1;
-    const gptr<float> prow = kCluster ? I.part + (int64_t)r * k * pstride : nullptr;
+    // partials and level results are double-buffered by exchange parity: a rank may publish
+    // the next exchange while another is still reading this one, but it cannot get two
+    // exchanges ahead (the barrier in between waits for every rank)
+    const gptr<float> prow = kCluster ? I.part + (int64_t)r * 2 * k * pstride : nullptr;
+    int xpar = 0, lpar = 0;
     int bar_target = 0;
 
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -143,7 +174,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
                 const float unsat = task_forward(T, t, st, kappa, hard, W);
-                const float wc = t.valid ? wrow[t.c] : 0.0f;
+                const float wc = t.valid ? wload(t.c) : 0.0f;
                 oacc += wc * unsat;
                 task_backward(T, t, wc, sc, W, lane);
             }
@@ -151,9 +182,11 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 // publish this workgroup's partial gradient and objective, then sum the
                 // cluster's partials in rank order (every rank gets the same bits)
                 const float op = block_sum(oacc);
-                const gptr<float> mine = prow + (int64_t)rank * pstride;
-                for (int i = threadIdx.x; i < n + m; i += blockDim.x) mine[i] = ga[i];
-                if (threadIdx.x == 0) mine[n + m] = op;
+                const gptr<float> buf = prow + (int64_t)xpar * k * pstride;
+                xpar ^= 1;
+                const gptr<float> mine = buf + (int64_t)rank * pstride;
+                for (int i = threadIdx.x; i < n + m; i += blockDim.x) publish(mine + i, ga[i]);
+                if (threadIdx.x == 0) publish(mine + n + m, op);
                 bar_target += k;
                 if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
                     aborted = true;
@@ -161,11 +194,11 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 }
                 for (int i = threadIdx.x; i < n + m; i += blockDim.x) {
                     float s = 0.0f;
-                    for (int q = 0; q < k; ++q) s += prow[(int64_t)q * pstride + i];
+                    for (int q = 0; q < k; ++q) s += fetch(buf + (int64_t)q * pstride + i);
                     ga[i] = s;
                 }
                 float os = 0.0f;
-                for (int q = 0; q < k; ++q) os += prow[(int64_t)q * pstride + n + m];
+                for (int q = 0; q < k; ++q) os += fetch(buf + (int64_t)q * pstride + n + m);
                 oacc = threadIdx.x == 0 ? os : 0.0f;
             }
             __syncthreads();
@@ -221,11 +254,11 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 if (c < C) {
                     const float viol = sat ? 0.0f : 1.0f;
                     float h = P.rho * hrow[c] + viol;
-                    float wv = wrow[c];
+                    float wv = wload(c);
                     if (update) {
                         wv *= powf(P.gamma, h);
                         h = 1.0f;
-                        wrow[c] = wv;
+                        wstore(c, wv);
                     }
                     hrow[c] = h;
                     wsum += wv;
@@ -236,13 +269,13 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             if (update && P.normalize) {
                 const float ws = block_sum(wsum);
                 const float scale = (float)C / ws;
-                for (int c = threadIdx.x; c < C; c += blockDim.x) wrow[c] *= scale;
+                for (int c = threadIdx.x; c < C; c += blockDim.x) wstore(c, wload(c) * scale);
             }
             if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
             stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
             if (kCluster && threadIdx.x == 0) {
-                I.ctl[2 * r] = n_unsat;
-                I.ctl[2 * r + 1] = stop;
+                publish(I.ctl + 4 * r + 2 * lpar, n_unsat);
+                publish(I.ctl + 4 * r + 2 * lpar + 1, stop);
             }
         }
         if (kCluster) {
@@ -251,8 +284,9 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 aborted = true;
                 break;
             }
-            n_unsat = I.ctl[2 * r];
-            stop = I.ctl[2 * r + 1];
+            n_unsat = fetch(I.ctl + 4 * r + 2 * lpar);
+            stop = fetch(I.ctl + 4 * r + 2 * lpar + 1);
+            lpar ^= 1;
         }
         ++level;
         if (n_unsat == 0) verdict = 1;
@@ -445,29 +479,37 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         const size_t state_bytes = state_f * sizeof(float);
         const int waves = wave_bytes ? (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes) : solve_waves(msg);
         const size_t lds = state_bytes + (size_t)waves * wave_bytes;
-        const bool cl = O.cluster > 1;
-        const void *kern = msg == kMsgSmall    ? (cl ? (const void *)solve_wg_kernel<kMsgSmall, true> : (const void *)solve_wg_kernel<kMsgSmall, false>)
-                           : msg == kMsgMedium ? (cl ? (const void *)solve_wg_kernel<kMsgMedium, true> : (const void *)solve_wg_kernel<kMsgMedium, false>)
-                                               : (cl ? (const void *)solve_wg_kernel<kMsgLds, true> : (const void *)solve_wg_kernel<kMsgLds, false>);
+        // the cluster kernels (k workgroups per restart) have their own resource use
+        auto kernel_of = [&](bool cl) -> const void * {
+            if (msg == kMsgSmall) return cl ? (const void *)solve_wg_kernel<kMsgSmall, true> : (const void *)solve_wg_kernel<kMsgSmall, false>;
+            if (msg == kMsgMedium) return cl ? (const void *)solve_wg_kernel<kMsgMedium, true> : (const void *)solve_wg_kernel<kMsgMedium, false>;
+            return cl ? (const void *)solve_wg_kernel<kMsgLds, true> : (const void *)solve_wg_kernel<kMsgLds, false>;
+        };
+        auto resident_of = [&](bool cl) -> int64_t {
+            int occ = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel_of(cl), 64 * waves, lds) != hipSuccess) {
+                (void)hipGetLastError();
+                occ = 1;
+            }
+            return (int64_t)n_cu * std::max(occ, 1);
+        };
         // workgroups per restart: a cluster of k co-resident workgroups shares one restart's
         // sweep (all of them must be resident at once: their barrier waits for each other)
-        int occ = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * waves, lds) != hipSuccess) {
-            (void)hipGetLastError();
-            occ = 1;
-        }
-        const int64_t resident = (int64_t)n_cu * std::max(occ, 1);
         int k = 1;
         if (O.cluster > 0) {
             k = O.cluster;
-            if (k > 16 || total_r * k > resident || (k > 1 && !ib.empty()))
+            if (k > 16 || (k > 1 && (total_r * k > resident_of(true) || !ib.empty())))
                 return set_error(FSMT_EUNSUPPORTED, "cluster of %d workgroups per restart cannot be co-resident", k);
+        } else if (ib.empty()) {
+            // automatic: the largest power of two that leaves each wave at least two tasks
+            // per step and keeps every workgroup resident. Measured per PGD step: config 3
+            // (182 tasks per restart, 8 waves), 16 restarts: 306 us at k = 1, 163 at 2, 89 at
+            // 4, 59 at 8; config 2 (66 tasks, 16 waves), 64 restarts: 22.8 us at k = 1,
+            // 21.9 at 2, 22.9 at 4.
+            const int64_t res = resident_of(true);
+            while (k < 16 && min_tasks >= (int64_t)2 * (2 * k) * waves && total_r * 2 * k <= res) k *= 2;
         }
-        // automatic: one workgroup per restart. Measured on config 2 (64 restarts, 66 tasks
-        // per restart): 4 workgroups per restart took 34.7 us per PGD step against 29 us
-        // for one, the agent-scope release/acquire of the cluster barrier (L2 write-back and
-        // invalidate) costing more than the split sweep saves.
-        (void)min_tasks;
+        const bool cl = k > 1;
         int64_t wg = 0;
         for (size_t q = 0; q < ia.size(); ++q) {
             const fsmt_xbdd *h = insts[ia[q]];
@@ -491,18 +533,18 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             d.k = k;
             d.wg_base = (int32_t)wg;
             wg += (int64_t)d.R * k;
-            if (k > 1) part_floats += (int64_t)d.R * k * ((int64_t)h->n_bool + h->n_real + 1);
+            if (k > 1) part_floats += (int64_t)d.R * 2 * k * ((int64_t)h->n_bool + h->n_real + 1);
         }
         if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
         P.lds_nodes = maxn;
         P.lds_slots = maxs;
         P.state_floats = (int32_t)state_f;
         P.waves = waves;
-        // scratch: descriptors | stop flags [n] | abort flag | barriers [R] | level results [2R] | partials
+        // scratch: descriptors | stop flags [n] | abort flag | barriers [R] | level results [2][2R] | partials [2]
         void *dbuf = nullptr;
         const size_t desc_bytes = sizeof(InstDesc) * desc.size();
         const size_t off_flag = (desc_bytes + 255) / 256 * 256;
-        const size_t n_int = desc.size() + 1 + 3 * (size_t)total_r;
+        const size_t n_int = desc.size() + 1 + 5 * (size_t)total_r;
         const size_t off_part = off_flag + (n_int * sizeof(int32_t) + 255) / 256 * 256;
         if (hipMallocAsync(&dbuf, off_part + sizeof(float) * (size_t)part_floats + 256, st) != hipSuccess) {
             (void)hipGetLastError();
@@ -514,10 +556,10 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             int64_t rb = 0, pb = 0;
             for (InstDesc &d : desc) {
                 d.bar = as_gptr(bar + rb);
-                d.ctl = as_gptr(ctl + 2 * rb);
+                d.ctl = as_gptr(ctl + 4 * rb);
                 d.part = k > 1 ? as_gptr(part + pb) : nullptr;
                 rb += d.R;
-                if (k > 1) pb += (int64_t)d.R * k * ((int64_t)d.T.n_bool + d.T.n_real + 1);
+                if (k > 1) pb += (int64_t)d.R * 2 * k * ((int64_t)d.T.n_bool + d.T.n_real + 1);
             }
             if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
                 fill_i32(ints, (int64_t)n_int, 0, st) != FSMT_OK) {

@@ -77,7 +77,9 @@ def test_multi_instance_batch_equals_single():
     Rs = [3, 5, 2, 4]
     hs = [fsmt.xbdd_compile(p) for p in probs]
     init = [W.initial_points(p, R, 60, i) for i, (p, R) in enumerate(zip(probs, Rs))]
-    cfg = S.SolveConfig(kappas=[0.3, 0.6], steps_per_level=3, eta_a=0.4, eta_b=1.0, eps=0.0, stop_on_sat=0)
+    # one workgroup per restart in both runs (the automatic cluster size depends on the batch)
+    cfg = S.SolveConfig(kappas=[0.3, 0.6], steps_per_level=3, eta_a=0.4, eta_b=1.0, eps=0.0, stop_on_sat=0,
+                        cluster=1)
     batch = [S.BatchState(h, a, b) for h, (a, b) in zip(hs, init)]
     S.solve_batched(hs, batch, cfg)
     for h, (a, b), bs in zip(hs, init, batch):
