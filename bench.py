@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-protocol", action="store_true", help="skip the paper's gradient-timing protocol")
     ap.add_argument("--tts-seeds", type=int, default=5)
     ap.add_argument("--tts-cap", type=float, default=30.0, help="time limit per instance (s)")
+    ap.add_argument("--percall-mode", action="store_true",
+                    help="profiling aid: per-call forward + reverse sweeps on placement with 1,200 "
+                         "rectangles (1 and 16 restarts) after a calibration copy")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="one short solver launch plus a 256 MiB copy, for counter collection")
     return ap.parse_args()
@@ -122,53 +125,60 @@ def main():
         return S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=STEPS_PER_LEVEL, eta_a=ETA_A,
                              eta_b=ETA_B, eps=0.0, stop_on_sat=0)
 
-    if args.pmc_mode:
-        src = torch.empty(64 * 1024 * 1024, device=dev)
+    if args.pmc_mode or args.percall_mode:
+        # calibration: one element-wise shader kernel reading 256 MiB and writing 256 MiB
+        src = torch.ones(64 * 1024 * 1024, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)                       # calibration: 256 MiB read + 256 MiB written
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+    if args.percall_mode:
+        percall_placement(fsmt, W, st)
+        print(json.dumps({"percall_mode": True, "copy_bytes": src.numel() * 4}))
+        return
+    if args.pmc_mode:
         state = S.BatchState(h, a0, b0)
-        for i in range(3):                   # three launches of one level each, as timed
-            S.solve_batched([h], [state], fixed_cfg(i + 1), stream=st)
+        S.solve_batched([h], [state], fixed_cfg(2), stream=st)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4}))
         return
 
-    # one step = one annealing level = one fused launch (the solver resumes each restart at
-    # its level counter), so warmup and timed launches carry identical work
-    levels = max(1, min(args.steps, 128 - args.warmup))
-    state = S.BatchState(h, a0, b0)
-    for i in range(args.warmup):
-        S.solve_batched([h], [state], fixed_cfg(i + 1), stream=st)
+    # the K timed steps (annealing levels) are one fused launch; each of the W warmup runs is
+    # an identical launch on a throwaway state, so every launch of the command carries the
+    # same work (the profiler's per-launch average is the timed launch's duration)
+    levels = max(1, min(args.steps, 128))
+    for _ in range(args.warmup):
+        warm = S.BatchState(h, a0, b0)
+        S.solve_batched([h], [warm], fixed_cfg(levels), stream=st)
     torch.cuda.synchronize()
-    steps0 = int(state.steps_done.cpu().numpy().min())
+    state = S.BatchState(h, a0, b0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(st)
-    for i in range(levels):
-        S.solve_batched([h], [state], fixed_cfg(args.warmup + i + 1), stream=st)
+    S.solve_batched([h], [state], fixed_cfg(levels), stream=st)
     e1.record(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kern_s = e0.elapsed_time(e1) * 1e-3 / levels        # average launch (one level)
-    pgd_steps = int(state.steps_done.cpu().numpy().min()) - steps0
+    kern_s = e0.elapsed_time(e1) * 1e-3                 # the launch
+    pgd_steps = int(state.steps_done.cpu().numpy().min())
     assert pgd_steps == levels * STEPS_PER_LEVEL
     evals = p.n_cons * R * pgd_steps
     value = evals / dt
 
-    # per launch (one level = STEPS_PER_LEVEL PGD iterations over C x R constraint-evals)
-    fl = flops_per_pass(cost, R) * STEPS_PER_LEVEL
-    by = bytes_per_pass(cost, p, R) * STEPS_PER_LEVEL
+    # per launch (K levels x STEPS_PER_LEVEL PGD iterations over C x R constraint-evals)
+    fl = flops_per_pass(cost, R) * pgd_steps
+    by = bytes_per_pass(cost, p, R) * pgd_steps
     ach_tf = fl / kern_s / 1e12
     ach_gbs = by / kern_s / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_solver_sched200.json")
+    tfile = os.path.join(ROOT, "profiles", "solve_wg_kernel_sched200.md")
     if os.path.exists(tfile):
-        try:
-            traffic = json.load(open(tfile))["hbm_bytes_per_launch"]
-        except Exception:
-            traffic = None
+        # measured HBM bytes per PGD iteration (scaled FETCH_SIZE + WRITE_SIZE of the solver
+        # kernel in the committed rocprofv3 summary), times the launch's iterations
+        for line in open(tfile):
+            if line.startswith("hbm_bytes_per_pgd_step:"):
+                traffic = float(line.split(":")[1]) * pgd_steps
 
     out = {
         "metric": "constraint-evals/s (fwd+bwd) and time-to-SAT, batched fused vs plain, 1 GPU",
@@ -183,7 +193,7 @@ def main():
                    "table_bytes": stats["table_bytes"]},
         "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach_tf / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "solve_wg_kernel", "kernel_ms_per_launch": kern_s * 1e3,
+                     "kernel": "solve_wg_kernel", "kernel_ms": kern_s * 1e3,
                      "flop_per_launch": fl, "bytes_per_launch": by,
                      "hbm_achieved_gbs": ach_gbs, "hbm_frac": ach_gbs / PEAK_HBM_GBS},
     }
@@ -194,6 +204,25 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a0, b0, kappas[0])
     print(json.dumps(out))
+
+
+def percall_placement(fsmt, W, st):
+    """cop_backward on the paper-scale placement instance (721,800 constraints): 3 calls at
+    1 restart (the tables stream from HBM) and 3 at 16 restarts."""
+    import torch
+    dev = torch.device("cuda", 0)
+    p = W.make_config(5)
+    h = fsmt.xbdd_compile(p)
+    for R in (1, 16):
+        a0, b0 = W.initial_points(p, R, 5, 0)
+        a, b = torch.as_tensor(a0, device=dev), torch.as_tensor(b0, device=dev)
+        ga, gb = torch.zeros_like(a), torch.zeros_like(b)
+        w = torch.ones(p.n_cons, device=dev)
+        obj = torch.zeros(R, device=dev)
+        for _ in range(3):
+            fsmt.cop_backward(h, a, b, 0.1, w, obj, ga, gb, stream=st)
+        torch.cuda.synchronize()
+    h.free()
 
 
 def time_to_sat(args, fsmt, S, W, st):

@@ -117,12 +117,6 @@ __host__ __device__ inline size_t level_wave_floats(int max_nodes, int max_slots
     return (size_t)2 * max_nodes + 2 * ((size_t)max_nodes + 2) + 4 * (size_t)max_slots;
 }
 
-// Orders this wave's LDS accesses: the next level reads what this level added.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
-    __builtin_amdgcn_wave_barrier();
-}
-
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;

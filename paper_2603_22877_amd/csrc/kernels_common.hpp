@@ -94,11 +94,19 @@ struct HalfSpaces {
     int32_t n, nnz;
 };
 
+// Orders this wave's LDS accesses (the next instructions read what this wave wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces.
 // If the clamped point already satisfies every half-space it is the projection; otherwise
 // Dykstra's alternating projections run from y (half-spaces in order, then the box, per
 // sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no coordinate by more than
-// 4e-7 (1 + |y|), or 256 sweeps. All threads of the block must call it.
+// 4e-7 (1 + |y|), or 256 sweeps. The sweeps run on the block's first wavefront alone
+// (one lane for the half-spaces, the wave for the box), ordered by LDS waits instead of
+// block barriers. All threads of the block must call it.
 __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, cptr<float> lo, cptr<float> hi,
                                                 int m, const HalfSpaces &hs) {
     for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
@@ -116,36 +124,41 @@ __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, 
         __syncthreads();
         return;
     }
-    for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = 0.0f;
-    for (int e = threadIdx.x; e < hs.nnz; e += blockDim.x) ph[e] = 0.0f;
-    __syncthreads();
-    for (int sweep = 0; sweep < 256; ++sweep) {
-        int moved = 0;
-        if (threadIdx.x == 0) {
-            for (int t = 0; t < hs.n; ++t) {
-                const int e0 = hs.ptr[t], e1 = hs.ptr[t + 1];
-                float viol = -hs.rhs[t];
-                for (int e = e0; e < e1; ++e) viol += hs.coef[e] * (y[hs.var[e]] + ph[e]);
-                const float sh = viol > 0.0f ? viol * hs.inv[t] : 0.0f;
-                for (int e = e0; e < e1; ++e) {
-                    const int j = hs.var[e];
-                    const float z = y[j] + ph[e], yp = z - sh * hs.coef[e];
-                    if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
-                    ph[e] = z - yp;
-                    y[j] = yp;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (int j = lane; j < m; j += 64) pb[j] = 0.0f;
+        for (int e = lane; e < hs.nnz; e += 64) ph[e] = 0.0f;
+        wave_lds_sync();
+        for (int sweep = 0; sweep < 256; ++sweep) {
+            int moved = 0;
+            if (lane == 0) {
+                for (int t = 0; t < hs.n; ++t) {
+                    const int e0 = hs.ptr[t], e1 = hs.ptr[t + 1];
+                    float viol = -hs.rhs[t];
+                    for (int e = e0; e < e1; ++e) viol += hs.coef[e] * (y[hs.var[e]] + ph[e]);
+                    const float sh = viol > 0.0f ? viol * hs.inv[t] : 0.0f;
+                    for (int e = e0; e < e1; ++e) {
+                        const int j = hs.var[e];
+                        const float z = y[j] + ph[e], yp = z - sh * hs.coef[e];
+                        if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
+                        ph[e] = z - yp;
+                        y[j] = yp;
+                    }
                 }
             }
+            wave_lds_sync();
+            for (int j = lane; j < m; j += 64) {
+                const float z = y[j] + pb[j];
+                const float yp = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);
+                if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
+                pb[j] = z - yp;
+                y[j] = yp;
+            }
+            wave_lds_sync();
+            if (__ballot(moved) == 0) break;
         }
-        __syncthreads();
-        for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            const float z = y[j] + pb[j];
-            const float yp = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);
-            if (fabsf(yp - y[j]) > 4e-7f * (1.0f + fabsf(yp))) moved = 1;
-            pb[j] = z - yp;
-            y[j] = yp;
-        }
-        if (!__syncthreads_or(moved)) break;
     }
+    __syncthreads();
 }
 
 // Sums of two values over the block (results valid in every thread).
