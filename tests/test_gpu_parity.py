@@ -322,3 +322,89 @@ def test_argument_errors_launch_nothing():
         fsmt.cop_forward(h, host, tb, 1.0, T(np.ones(p.n_cons)), obj)
     torch.cuda.synchronize()
     assert float(obj[0]) == 7.0
+
+
+def test_config4_per_instance_oracle_error():
+    """Uneven batch (48 instances, 16 restarts each): FP32 objective and false masses of every
+    instance against the FP64 oracle (up to 3,000 sampled constraints per instance); the
+    table of per-instance errors is printed."""
+    print("config 4 per-instance oracle error", flush=True)
+    probs = W.make_batch_config4()
+    R = 16
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for i, p in enumerate(probs):
+        h = fsmt.xbdd_compile(p)
+        a, b = W.initial_points(p, R, 4, i)
+        kap = 0.5 / p.meta.get("mean_duration", p.meta.get("mean_side", 1.0))
+        unsat = torch.zeros(R, p.n_cons, device=dev())
+        obj = torch.zeros(R, device=dev())
+        fsmt.cop_forward(h, T(a), T(b), kap, T(np.ones(p.n_cons)), obj, unsat)
+        torch.cuda.synchronize()
+        sel = np.arange(p.n_cons, dtype=np.int32) if p.n_cons <= 3000 else \
+            np.sort(rng.choice(p.n_cons, 3000, replace=False)).astype(np.int32)
+        o = oracle.objective(p, a, b, kap, grad=False, sel=sel)
+        g = unsat.cpu().numpy()[:, sel].astype(np.float64)
+        ref = o["unsat"][:, sel]
+        assert_unsat(g.astype(np.float32), ref)
+        rel_u = np.abs(g.sum(1) - ref.sum(1)) / np.maximum(ref.sum(1), 1e-30)
+        err = np.abs(g - ref) / (ref + 1e-7)
+        worst = max(worst, float(rel_u.max()))
+        print(f"instance {i:2d} {p.meta.get('family', '?'):10s} C={p.n_cons:7d} "
+              f"sampled={len(sel):5d} max|dU|/U={rel_u.max():.2e} max per-constraint rel={err.max():.2e}",
+              flush=True)
+        h.free()
+    assert worst <= 1e-5
+
+
+def test_config5_autograd_and_full_check():
+    """Paper-scale placement through torch.autograd.Function (16 restarts): the gradient equals
+    the reverse sweep's, a few projected steps lower U, and the exact check of the final
+    rounded assignment equals the oracle's over all 721,800 constraints."""
+    print("config 5 autograd + full check", flush=True)
+    from paper_2603_22877_amd import solver as S
+    p = W.make_config(5)
+    R = 16
+    a0, b0 = W.initial_points(p, R, 5, 1)
+    h = fsmt.xbdd_compile(p)
+    w = T(np.ones(p.n_cons))
+    kap = 2.0 / p.meta["mean_side"]
+    a = T(a0).requires_grad_(True)
+    b = T(b0).requires_grad_(True)
+    U = S.cop_objective(a, b, h, kap, w)
+    U.sum().backward()
+    ga = torch.zeros(R, p.n_bool, device=dev())
+    gb = torch.zeros(R, p.n_real, device=dev())
+    obj = torch.zeros(R, device=dev())
+    fsmt.cop_backward(h, a.detach(), b.detach(), kap, w, obj, ga, gb)
+    torch.cuda.synchronize()
+    rel = (a.grad - ga).norm() / ga.norm()
+    relb = (b.grad - gb).norm() / gb.norm()
+    assert float(rel) < 1e-5 and float(relb) < 1e-5
+    with torch.no_grad():
+        aa, bb = a.detach().clone(), b.detach().clone()
+    gsq = torch.zeros(R, device=dev())
+    U0 = U.detach().clone()
+    for _ in range(5):
+        ga.zero_()
+        gb.zero_()
+        fsmt.cop_backward(h, aa, bb, kap, w, obj, ga, gb)
+        fsmt.pgd_step(h, aa, bb, ga, gb, 0.05, 0.5, gsq)
+    obj.zero_()
+    fsmt.cop_forward(h, aa, bb, kap, w, obj)
+    torch.cuda.synchronize()
+    print(f"U mean {float(U0.mean()):.2f} -> {float(obj.mean()):.2f}", flush=True)
+    assert float(obj.mean()) < float(U0.mean())
+    nw = (p.n_cons + 31) // 32
+    bits = torch.zeros(R, nw, dtype=torch.int32, device=dev())
+    nu = torch.zeros(R, dtype=torch.int32, device=dev())
+    ver = torch.zeros(R, dtype=torch.int32, device=dev())
+    x = torch.zeros(R, p.n_bool, dtype=torch.int8, device=dev())
+    fsmt.round_and_check(h, aa, bb, x, bits, nu, ver)
+    torch.cuda.synchronize()
+    ch = oracle.check(p, aa.cpu().numpy(), bb.cpu().numpy())
+    np.testing.assert_array_equal(bits.cpu().numpy().view(np.uint32), ch["sat_bits"])
+    np.testing.assert_array_equal(nu.cpu().numpy(), ch["n_unsat"])
+    np.testing.assert_array_equal(ver.cpu().numpy(), ch["verdict"])
+    np.testing.assert_array_equal(x.cpu().numpy(), ch["x"])
+    print(f"n_unsat per restart: {nu.cpu().numpy().tolist()}", flush=True)
