@@ -87,24 +87,13 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
 }
 
 // ------------------------------------------------------------------ big diagrams
-// Level-synchronous passes for diagrams too large for per-lane message columns (long
-// cardinality, not-all-equal and parity constraints): one wavefront per (constraint,
-// chunk of restarts). Nodes are stored level by level (sorted by slot), so a level is a
-// contiguous range; its nodes go to the lanes. The wave stages the constraint's node table
-// in its LDS rows once and reuses it for every restart of the chunk; messages live in LDS
-// rows too: M and Bm per node, P, Q, D, G per slot.
-//   literal probabilities: lane = slot (as in task_forward)
-//   forward : per level, each node adds p M[v] to M[hi] and (1-p) M[v] to M[lo] (LDS
-//             atomics: nodes of one level may share children, which lie on deeper levels)
-//   reverse : per level from the bottom, Bm[v] = p Bm[hi] + (1-p) Bm[lo] (children final),
-//             and the level's sensitivity G[s] = sum_v M[v] (Bm[hi] - Bm[lo]) is a wave sum
-//   scatter : lane = slot, as in task_backward
-constexpr int kLevelChunk = 8;   // restarts per wavefront task
-
+// Level-synchronous passes (see level_eval): one wavefront per (big constraint, chunk of
+// restarts); the wave stages the constraint's node table in its LDS rows once and evaluates
+// the chunk's restarts one after the other.
 struct LevelArgs {
     TabView T;
     cptr<int32_t> lev, big_pos;
-    int32_t n_big, R;
+    int32_t n_big, R, chunk;
     View a, b, w, unsat, ga, gb;
     float *obj;
     double kappa;
@@ -112,145 +101,30 @@ struct LevelArgs {
     int32_t lds_nodes, lds_slots;   // per-wave LDS rows (max over big templates)
 };
 
-// floats of one wave's LDS rows: node table (2 words a node), M, Bm, P, Q, D, G
-__host__ __device__ inline size_t level_wave_floats(int max_nodes, int max_slots) {
-    return (size_t)2 * max_nodes + 2 * ((size_t)max_nodes + 2) + 4 * (size_t)max_slots;
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ Node unpack_node(uint2 raw) {
-    Node n;
-    n.slot = (uint16_t)(raw.x & 0xFFFFu);
-    n.hi = (uint16_t)(raw.x >> 16);
-    n.lo = (uint16_t)(raw.y & 0xFFFFu);
-    n.pad = 0;
-    return n;
-}
-
 template <bool kGrad>
 __global__ void __launch_bounds__(256) cop_level_kernel(LevelArgs A) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wib = wave_id();
     const int wpb = blockDim.x >> 6;
-    const int NMAX = A.lds_nodes, SS = A.lds_slots;
-    float *base = lds + (size_t)wib * level_wave_floats(NMAX, SS);
-    uint2 *NL = reinterpret_cast<uint2 *>(base);
-    float *M = base + 2 * NMAX, *Bm = M + NMAX + 2, *P = Bm + NMAX + 2, *Q = P + SS, *D = Q + SS, *G = D + SS;
-    const TabView &T = A.T;
+    const LevelRows W = LevelRows::at(lds + (size_t)wib * level_wave_floats(A.lds_nodes, A.lds_slots), A.lds_nodes,
+                                      A.lds_slots);
     const GlobalState st{A.a, A.b};
     const GlobalScatter sc{A.ga, A.gb, 64};
-    const int chunks = (A.R + kLevelChunk - 1) / kLevelChunk;
+    const int chunks = (A.R + A.chunk - 1) / A.chunk;
     const int64_t n_tasks = (int64_t)A.n_big * chunks;
     for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < n_tasks; task += (int64_t)gridDim.x * wpb) {
-        const int q = (int)(task / chunks), r0 = (int)(task - (int64_t)q * chunks) * kLevelChunk;
-        const int r1 = r0 + kLevelChunk < A.R ? r0 + kLevelChunk : A.R;
-        const int pos = __builtin_amdgcn_readfirstlane(A.big_pos[q]);
-        const BucketInfo B = load_bucket(T.bucket + __builtin_amdgcn_readfirstlane(T.task_bucket[pos >> 6]));
-        const int c = __builtin_amdgcn_readfirstlane(T.pos_con[pos]);
-        const int local = pos - B.pos_begin;
-        const int N = B.n_nodes, S = B.n_slots, NB = B.n_bslots;
-        const int64_t np = B.n_pos;
-        const cptr<int32_t> sup = T.sup + B.sup_base + local;
-        const cptr<AtomRec> rec = B.arec_base >= 0 ? T.arec + B.arec_base + local : nullptr;
-        const cptr<int32_t> lev = A.lev + B.lev_off;
-        const cptr<u32x2> nd = (cptr<u32x2>)(T.nodes + B.node_off);
-        for (int v = lane; v < N; v += 64) {
-            const u32x2 raw = nd[v];
-            NL[v] = make_uint2(raw.x, raw.y);
-        }
-        wave_lds_sync();
-
+        const int q = (int)(task / chunks), r0 = (int)(task - (int64_t)q * chunks) * A.chunk;
+        const int r1 = r0 + A.chunk < A.R ? r0 + A.chunk : A.R;
+        const LevelCtx L = level_ctx(A.T, A.lev, A.big_pos[q]);
+        level_stage_nodes(A.T, L, W, lane);
         for (int r = r0; r < r1; ++r) {
-            for (int s = lane; s < S; s += 64) {
-                float p, qq, d = 0.0f;
-                if (s < NB) {
-                    const float av = st.av(r, sup[(int64_t)s * np]);
-                    p = (1.0f - av) * 0.5f;
-                    qq = (1.0f + av) * 0.5f;
-                } else if (rec) {
-                    const AtomRec at = load_rec(rec + (int64_t)(s - NB) * np);
-                    atom_literal(rec_z(at, st, r), (double)at.scale, (at.flags & 1u) != 0, A.kappa, A.hard != 0, p, qq,
-                                 d);
-                } else {
-                    const int k = sup[(int64_t)s * np] - T.n_bool;
-                    atom_literal(atom_z_state(T, k, st, r), T.atom_scale[k], T.atom_strict[k] != 0, A.kappa, A.hard != 0,
-                                 p, qq, d);
-                }
-                P[s] = p;
-                Q[s] = qq;
-                D[s] = d;
-            }
-            for (int v = lane; v < N + 2; v += 64) M[v] = 0.0f;
-            wave_lds_sync();
-            if (lane == 0) M[B.root] = 1.0f;
-            wave_lds_sync();
-            for (int s = 0; s < S; ++s) {
-                const int v0 = lev[s], v1 = lev[s + 1];
-                if (v0 == v1) continue;
-                const float p = P[s], qq = Q[s];
-                for (int v = v0 + lane; v < v1; v += 64) {
-                    const Node x = unpack_node(NL[v]);
-                    const float mv = M[v];
-                    atomicAdd(M + x.hi, p * mv);
-                    atomicAdd(M + x.lo, qq * mv);
-                }
-                wave_lds_sync();
-            }
-            const float unsat = M[N + 1];
-            const float wc = A.w.at(r, c);
+            const float wc = A.w.at(r, L.c);
+            const float unsat = level_eval(A.T, L, st, sc, r, A.kappa, A.hard != 0, wc, kGrad, W, lane);
             if (lane == 0) {
-                if (A.unsat.data) A.unsat.at(r, c) = unsat;
+                if (A.unsat.data) A.unsat.at(r, L.c) = unsat;
                 if (A.obj) atomic_add_f32(A.obj + r, wc * unsat);
             }
-            if (kGrad) {
-                if (lane == 0) {
-                    Bm[N] = 0.0f;
-                    Bm[N + 1] = 1.0f;
-                }
-                wave_lds_sync();
-                for (int s = S - 1; s >= 0; --s) {
-                    const int v0 = lev[s], v1 = lev[s + 1];
-                    float g = 0.0f;
-                    if (v0 < v1) {
-                        const float p = P[s], qq = Q[s];
-                        for (int v = v0 + lane; v < v1; v += 64) {
-                            const Node x = unpack_node(NL[v]);
-                            const float bh = Bm[x.hi], bl = Bm[x.lo];
-                            Bm[v] = p * bh + qq * bl;
-                            g += M[v] * (bh - bl);
-                        }
-                        g = wave_sum(g);
-                    }
-                    if (lane == 0) G[s] = g;
-                    wave_lds_sync();
-                }
-                for (int s = lane; s < S; s += 64) {
-                    const float g = wc * G[s];
-                    if (s < NB) {
-                        sc.add_b_direct_a(r, sup[(int64_t)s * np], g * -0.5f);      // dp/da = -1/2
-                    } else if (rec) {
-                        const AtomRec at = load_rec(rec + (int64_t)(s - NB) * np);
-                        const float gz = g * D[s];
-                        if (gz != 0.0f) {
-                            sc.add_b_direct(r, at.v0, gz * at.c0);
-                            if (at.flags & 2u) sc.add_b_direct(r, at.v1, gz * at.c1);
-                        }
-                    } else {
-                        const float gz = g * D[s];
-                        if (gz != 0.0f) {
-                            const int k = sup[(int64_t)s * np] - T.n_bool;
-                            for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
-                                sc.add_b_direct(r, T.atom_var[e], gz * (float)T.atom_coef[e]);
-                        }
-                    }
-                }
-            }
-            wave_lds_sync();   // the next restart overwrites this wave's message rows
         }
     }
 }
@@ -547,8 +421,11 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         L.hard = A.hard;
         L.lds_nodes = h->big_max_nodes;
         L.lds_slots = std::max(h->big_max_slots, 1);
+        int n_cu = 256;
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+        L.chunk = level_chunk((int64_t)h->n_big * R, n_cu);
         const int lwpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / level_wave_bytes));
-        const int64_t ltasks = (int64_t)h->n_big * ((R + kLevelChunk - 1) / kLevelChunk);
+        const int64_t ltasks = (int64_t)h->n_big * ((R + L.chunk - 1) / L.chunk);
         const int lblocks = (int)std::min<int64_t>((ltasks + lwpb - 1) / lwpb, (int64_t)256 * 16);
         if (grad)
             hipLaunchKernelGGL(cop_level_kernel<true>, dim3(lblocks), dim3(64 * lwpb), level_wave_bytes * lwpb, st, L);

@@ -103,7 +103,7 @@ struct GlobalScatter {
     }
     // for divergent call sites (no merging)
     __device__ __forceinline__ void add_b_direct(int r, int j, float g) const { atomic_add_f32(&gb.at(r, j), g); }
-    __device__ __forceinline__ void add_b_direct_a(int r, int i, float g) const { atomic_add_f32(&ga.at(r, i), g); }
+    __device__ __forceinline__ void add_a_direct(int r, int i, float g) const { atomic_add_f32(&ga.at(r, i), g); }
 };
 // LDS: the fused solver's gradient lives in LDS and its atomics stay on the CU.
 struct LdsScatter {
@@ -222,10 +222,13 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
 template <int NM, int SM>
 struct RegMsgs {
     static constexpr int kNodes = NM, kSlots = SM;
-    // At least 9 elements per array: the compiler lowers a uniform dynamic index into a
-    // shorter register array as a compare/select per element, into a longer one as a
-    // single indexed move (GPR indexing).
-    static constexpr int kArrNodes = NM + 2 < 9 ? 9 : NM + 2, kArrSlots = SM < 9 ? 9 : SM;
+    // Node arrays hold the NM nodes, the two terminals and a spare entry that absorbs the
+    // updates of iterations past the diagram's size (index kTrashNode); slot arrays hold a
+    // spare slot (kTrashSlot) likewise. At least 9 elements per array: the compiler lowers
+    // a uniform dynamic index into a shorter register array as a compare/select per
+    // element, into a longer one as a single indexed move (GPR indexing).
+    static constexpr int kTrashNode = NM + 2, kTrashSlot = SM;
+    static constexpr int kArrNodes = NM + 3 < 9 ? 9 : NM + 3, kArrSlots = SM + 1 < 9 ? 9 : SM + 1;
     static constexpr bool kInlineOnly = true;   // every atom slot has an inline record
     // the arrays are separate locals of the kernel (see bind_msgs): a single aggregate
     // indexed dynamically would not be split into registers
@@ -241,6 +244,7 @@ struct RegMsgs {
 struct LdsMsgs {
     static constexpr int kNodes = 0, kSlots = 0;   // unbounded
     static constexpr int kArrNodes = 1, kArrSlots = 1;
+    static constexpr int kTrashNode = 0, kTrashSlot = 0;
     static constexpr bool kInlineOnly = false;      // inline records or the CSR atom table
     WaveScratch W;
     int lane;
@@ -351,15 +355,37 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
         W.Q(s) = q;
         W.D(s) = d;
     });
-    for_up<(KN > 0 ? KN + 2 : 0)>(0, N + 2, [&](int v) { W.M(v) = 0.0f; });
-    W.M(t.B.root) = 1.0f;
     const cptr<Node> nd = T.nodes + t.B.node_off;
-    for_up<KN>(0, N, [&](int v) {
-        const Node x = load_node(nd + v);
-        const float mv = W.M(v);
-        W.M(x.hi) += W.P(x.slot) * mv;
-        W.M(x.lo) += W.Q(x.slot) * mv;
-    });
+    if constexpr (KN > 0) {
+        // registers: every iteration up to the bound runs, so no write to the message
+        // arrays sits under a branch (a guarded indexed write would make the compiler copy
+        // the whole array at the join); iterations past the diagram read a valid node,
+        // move no mass and add into the spare entry
+#pragma unroll
+        for (int v = 0; v < Ms::kArrNodes; ++v) W.M(v) = 0.0f;
+        W.M(t.B.root) = 1.0f;
+        if (N > 0) {
+#pragma unroll
+            for (int v = 0; v < KN; ++v) {
+                const bool live = v < N;
+                const Node x0 = load_node(nd + (live ? v : N - 1));
+                const int slot = live ? x0.slot : 0;
+                const int hi = live ? x0.hi : Ms::kTrashNode, lo = live ? x0.lo : Ms::kTrashNode;
+                const float mv = live ? W.M(v) : 0.0f;
+                W.M(hi) += W.P(slot) * mv;
+                W.M(lo) += W.Q(slot) * mv;
+            }
+        }
+    } else {
+        for_up<0>(0, N + 2, [&](int v) { W.M(v) = 0.0f; });
+        W.M(t.B.root) = 1.0f;
+        for_up<0>(0, N, [&](int v) {
+            const Node x = load_node(nd + v);
+            const float mv = W.M(v);
+            W.M(x.hi) += W.P(x.slot) * mv;
+            W.M(x.lo) += W.Q(x.slot) * mv;
+        });
+    }
     return t.valid ? W.M(N + 1) : 0.0f;
 }
 
@@ -370,16 +396,37 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
     constexpr int KN = Ms::kNodes, KS = Ms::kSlots;
     const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
-    for_up<KS>(0, S, [&](int s) { W.G(s) = 0.0f; });
-    W.Bm(N) = 0.0f;
-    W.Bm(N + 1) = 1.0f;
     const cptr<Node> nd = T.nodes + t.B.node_off;
-    for_down<KN>(N, [&](int v) {
-        const Node x = load_node(nd + v);
-        const float bh = W.Bm(x.hi), bl = W.Bm(x.lo);
-        W.Bm(v) = W.P(x.slot) * bh + W.Q(x.slot) * bl;
-        W.G(x.slot) += W.M(v) * (bh - bl);
-    });
+    if constexpr (KN > 0) {
+        // registers: unconditional iterations as in the forward pass; a dead iteration keeps
+        // Bm[v] (which may be a terminal) and adds into the spare slot
+#pragma unroll
+        for (int s = 0; s < Ms::kArrSlots; ++s) W.G(s) = 0.0f;
+        W.Bm(N) = 0.0f;
+        W.Bm(N + 1) = 1.0f;
+        if (N > 0) {
+#pragma unroll
+            for (int v = KN - 1; v >= 0; --v) {
+                const bool live = v < N;
+                const Node x0 = load_node(nd + (live ? v : N - 1));
+                const int slot = live ? x0.slot : Ms::kTrashSlot;
+                const float bh = W.Bm(x0.hi), bl = W.Bm(x0.lo);
+                const float bv = W.P(x0.slot) * bh + W.Q(x0.slot) * bl;
+                W.Bm(v) = live ? bv : W.Bm(v);
+                W.G(slot) += live ? W.M(v) * (bh - bl) : 0.0f;
+            }
+        }
+    } else {
+        for_up<0>(0, S, [&](int s) { W.G(s) = 0.0f; });
+        W.Bm(N) = 0.0f;
+        W.Bm(N + 1) = 1.0f;
+        for_down<0>(N, [&](int v) {
+            const Node x = load_node(nd + v);
+            const float bh = W.Bm(x.hi), bl = W.Bm(x.lo);
+            W.Bm(v) = W.P(x.slot) * bh + W.Q(x.slot) * bl;
+            W.G(x.slot) += W.M(v) * (bh - bl);
+        });
+    }
     // Boolean slots: distinct variables within a constraint
     for_up<KS>(0, NB, [&](int s) {
         const float g = t.valid ? wc * W.G(s) * -0.5f : 0.0f;     // dp/da = -1/2
@@ -461,6 +508,179 @@ inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inl
     if (max_nodes <= 4 && max_slots <= 4) return kMsgSmall;
     if (max_nodes <= 20 && max_slots <= 12) return kMsgMedium;
     return kMsgLds;
+}
+
+// ---- big diagrams: level-synchronous evaluation of one (constraint, restart) by a wave
+// Nodes are stored level by level (sorted by slot), so a level is a contiguous range; its
+// nodes go to the lanes, and lanes also take the slots for the literal probabilities and
+// the scatter. The wave's LDS rows hold the constraint's node table and the messages: M and
+// Bm per node, P, Q, D, G per slot.
+//   forward : per level, each node adds p M[v] to M[hi] and (1-p) M[v] to M[lo] (LDS
+//             atomics: nodes of one level may share children, which lie on deeper levels)
+//   reverse : per level from the bottom, Bm[v] = p Bm[hi] + (1-p) Bm[lo] (children final),
+//             and the level's sensitivity G[s] = sum_v M[v] (Bm[hi] - Bm[lo]) is a wave sum
+// One wavefront per constraint: only LDS waits order the levels, no barrier.
+// Restarts per wavefront task: each task stages the node table once for its chunk; small
+// chunks give more parallel waves when there are few big constraints.
+inline int level_chunk(int64_t n_big_restarts, int n_cu) {
+    const int64_t target = (int64_t)n_cu * 16;   // about four waves per SIMD
+    int chunk = 1;
+    while (chunk < 8 && n_big_restarts / (2 * chunk) >= target) chunk *= 2;
+    return chunk;
+}
+
+// floats of one wave's LDS rows: node table (2 words a node), M, Bm, P, Q, D, G
+__host__ __device__ inline size_t level_wave_floats(int max_nodes, int max_slots) {
+    return (size_t)2 * max_nodes + 2 * ((size_t)max_nodes + 2) + 4 * (size_t)max_slots;
+}
+
+struct LevelRows {
+    uint2 *NL;
+    float *M, *Bm, *P, *Q, *D, *G;
+    __device__ __forceinline__ static LevelRows at(float *base, int max_nodes, int max_slots) {
+        LevelRows w;
+        w.NL = reinterpret_cast<uint2 *>(base);
+        w.M = base + 2 * max_nodes;
+        w.Bm = w.M + max_nodes + 2;
+        w.P = w.Bm + max_nodes + 2;
+        w.Q = w.P + max_slots;
+        w.D = w.Q + max_slots;
+        w.G = w.D + max_slots;
+        return w;
+    }
+};
+
+struct LevelCtx {
+    BucketInfo B;
+    int c, local;
+    cptr<int32_t> sup, lev;
+    cptr<AtomRec> rec;
+};
+
+__device__ __forceinline__ LevelCtx level_ctx(const TabView &T, cptr<int32_t> lev_all, int pos_in) {
+    LevelCtx L;
+    const int pos = __builtin_amdgcn_readfirstlane(pos_in);
+    L.B = load_bucket(T.bucket + __builtin_amdgcn_readfirstlane(T.task_bucket[pos >> 6]));
+    L.c = __builtin_amdgcn_readfirstlane(T.pos_con[pos]);
+    L.local = pos - L.B.pos_begin;
+    L.sup = T.sup + L.B.sup_base + L.local;
+    L.rec = L.B.arec_base >= 0 ? T.arec + L.B.arec_base + L.local : nullptr;
+    L.lev = lev_all + L.B.lev_off;
+    return L;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ Node unpack_node(uint2 raw) {
+    Node n;
+    n.slot = (uint16_t)(raw.x & 0xFFFFu);
+    n.hi = (uint16_t)(raw.x >> 16);
+    n.lo = (uint16_t)(raw.y & 0xFFFFu);
+    n.pad = 0;
+    return n;
+}
+
+// Copy the constraint's node table into the wave's LDS rows.
+__device__ __forceinline__ void level_stage_nodes(const TabView &T, const LevelCtx &L, const LevelRows &W, int lane) {
+    wave_lds_sync();   // the previous task's readers are done
+    const cptr<u32x2> nd = (cptr<u32x2>)(T.nodes + L.B.node_off);
+    for (int v = lane; v < L.B.n_nodes; v += 64) {
+        const u32x2 raw = nd[v];
+        W.NL[v] = make_uint2(raw.x, raw.y);
+    }
+    wave_lds_sync();
+}
+
+// Forward (and with grad the reverse pass and the scatter of wc * dP[c False]/d(state))
+// for restart r; returns P[c False] in every lane.
+template <class St, class Sc>
+__device__ __forceinline__ float level_eval(const TabView &T, const LevelCtx &L, const St &st, const Sc &sc, int r,
+                                            double kappa, bool hard, float wc, bool grad, const LevelRows &W,
+                                            int lane) {
+    const int N = L.B.n_nodes, S = L.B.n_slots, NB = L.B.n_bslots;
+    const int64_t np = L.B.n_pos;
+    for (int s = lane; s < S; s += 64) {
+        float p, qq, d = 0.0f;
+        if (s < NB) {
+            const float av = st.av(r, L.sup[(int64_t)s * np]);
+            p = (1.0f - av) * 0.5f;
+            qq = (1.0f + av) * 0.5f;
+        } else if (L.rec) {
+            const AtomRec at = load_rec(L.rec + (int64_t)(s - NB) * np);
+            atom_literal(rec_z(at, st, r), (double)at.scale, (at.flags & 1u) != 0, kappa, hard, p, qq, d);
+        } else {
+            const int k = L.sup[(int64_t)s * np] - T.n_bool;
+            atom_literal(atom_z_state(T, k, st, r), T.atom_scale[k], T.atom_strict[k] != 0, kappa, hard, p, qq, d);
+        }
+        W.P[s] = p;
+        W.Q[s] = qq;
+        W.D[s] = d;
+    }
+    for (int v = lane; v < N + 2; v += 64) W.M[v] = 0.0f;
+    wave_lds_sync();
+    if (lane == 0) W.M[L.B.root] = 1.0f;
+    wave_lds_sync();
+    for (int s = 0; s < S; ++s) {
+        const int v0 = L.lev[s], v1 = L.lev[s + 1];
+        if (v0 == v1) continue;
+        const float p = W.P[s], qq = W.Q[s];
+        for (int v = v0 + lane; v < v1; v += 64) {
+            const Node x = unpack_node(W.NL[v]);
+            const float mv = W.M[v];
+            atomicAdd(W.M + x.hi, p * mv);
+            atomicAdd(W.M + x.lo, qq * mv);
+        }
+        wave_lds_sync();
+    }
+    const float unsat = W.M[N + 1];
+    if (grad) {
+        if (lane == 0) {
+            W.Bm[N] = 0.0f;
+            W.Bm[N + 1] = 1.0f;
+        }
+        wave_lds_sync();
+        for (int s = S - 1; s >= 0; --s) {
+            const int v0 = L.lev[s], v1 = L.lev[s + 1];
+            float g = 0.0f;
+            if (v0 < v1) {
+                const float p = W.P[s], qq = W.Q[s];
+                for (int v = v0 + lane; v < v1; v += 64) {
+                    const Node x = unpack_node(W.NL[v]);
+                    const float bh = W.Bm[x.hi], bl = W.Bm[x.lo];
+                    W.Bm[v] = p * bh + qq * bl;
+                    g += W.M[v] * (bh - bl);
+                }
+                g = wave_sum(g);
+            }
+            if (lane == 0) W.G[s] = g;
+            wave_lds_sync();
+        }
+        for (int s = lane; s < S; s += 64) {
+            const float g = wc * W.G[s];
+            if (s < NB) {
+                sc.add_a_direct(r, L.sup[(int64_t)s * np], g * -0.5f);   // dp/da = -1/2
+            } else if (L.rec) {
+                const AtomRec at = load_rec(L.rec + (int64_t)(s - NB) * np);
+                const float gz = g * W.D[s];
+                if (gz != 0.0f) {
+                    sc.add_b_direct(r, at.v0, gz * at.c0);
+                    if (at.flags & 2u) sc.add_b_direct(r, at.v1, gz * at.c1);
+                }
+            } else {
+                const float gz = g * W.D[s];
+                if (gz != 0.0f) {
+                    const int k = L.sup[(int64_t)s * np] - T.n_bool;
+                    for (int e = T.atom_ptr[k]; e < T.atom_ptr[k + 1]; ++e)
+                        sc.add_b_direct(r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+                }
+            }
+        }
+    }
+    wave_lds_sync();   // the next restart overwrites the message rows
+    return unsat;
 }
 
 // Deterministic walk of constraint c at the rounded point (exact check).

@@ -391,9 +391,6 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         device = h->device;
         const int R = S.a.rows;
         if (R <= 0) return set_error(FSMT_EINVAL, "instance %d: no restarts", i);
-        if (h->n_big > 0)
-            return set_error(FSMT_EUNSUPPORTED, "instance %d: %d constraints have diagrams too large for the fused solver "
-                             "(use cop_backward / pgd_step)", i, h->n_big);
         if (S.a.cols != h->n_bool || S.b.rows != R || S.b.cols != h->n_real)
             return set_error(FSMT_EINVAL, "instance %d: state shape does not match the instance", i);
         if ((h->n_bool > 1 && S.a.stride_v != 1) || (h->n_real > 1 && S.b.stride_v != 1) ||
@@ -422,7 +419,11 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         if (O.schedule == 1 && !fits)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: restart state (%zu B) does not fit the persistent "
                              "schedule's LDS (%zu B)", i, sb, budget);
-        use_grid[i] = O.schedule == 2 || !fits || (O.schedule == 0 && prefer_grid(h, states[i].a.rows, waves, n_cu));
+        // big diagrams are evaluated level by level by their own kernel, in the grid schedule
+        if (O.schedule == 1 && h->n_big > 0)
+            return set_error(FSMT_EUNSUPPORTED, "instance %d: %d big diagrams need the grid schedule", i, h->n_big);
+        use_grid[i] = O.schedule == 2 || !fits || h->n_big > 0 ||
+                      (O.schedule == 0 && prefer_grid(h, states[i].a.rows, waves, n_cu));
     }
 
     hipStream_t st = (hipStream_t)stream;
@@ -589,7 +590,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     if (!ib.empty() && !rc) {
         std::vector<GridInst> gi(ib.size());
         int total_r = 0;
-        int64_t tasks = 0, checks = 0, scratch_floats = 0;
+        int64_t tasks = 0, checks = 0, scratch_floats = 0, level_tasks = 0, big_restarts = 0;
+        int lvl_nodes = 0, lvl_slots = 1;
         int maxn = 0, maxs = 1;
         size_t step_lds = 0;
         for (size_t q = 0; q < ib.size(); ++q) {
@@ -622,6 +624,15 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             d.rbase = total_r;
             d.task_base = tasks;
             d.check_base = checks;
+            d.lev = as_cptr(h->d.lev);
+            d.big_pos = as_cptr(h->d.big_pos);
+            d.n_big = h->n_big;
+            d.pad = 0;
+            big_restarts += (int64_t)h->n_big * d.R;
+            if (h->n_big > 0) {
+                lvl_nodes = std::max(lvl_nodes, h->big_max_nodes);
+                lvl_slots = std::max(lvl_slots, h->big_max_slots);
+            }
             total_r += d.R;
             tasks += d.R <= 64 ? (int64_t)h->n_pos * d.R_pad / 64 : (int64_t)h->n_pos * (d.R_pad / 64);
             checks += (int64_t)d.R * ((h->n_cons + 255) / 256);
@@ -638,6 +649,14 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
         const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
         if (wave_bytes > 65536) rc = set_error(FSMT_ELIMIT, "diagram too large for the grid schedule");
+        // level tasks: (big constraint, chunk of restarts), instance-major
+        const int lvl_chunk = level_chunk(big_restarts, n_cu);
+        for (GridInst &d : gi) {
+            d.level_base = level_tasks;
+            level_tasks += (int64_t)d.n_big * ((d.R + lvl_chunk - 1) / lvl_chunk);
+        }
+        const size_t level_bytes = level_tasks > 0 ? level_wave_floats(lvl_nodes, lvl_slots) * sizeof(float) : 0;
+        if (level_bytes > 65536) rc = set_error(FSMT_ELIMIT, "diagram too large for the level-synchronous pass");
         if (step_lds > 65536) rc = set_error(FSMT_ELIMIT, "projection work arrays exceed LDS");
         // device scratch: descriptors, kappas, per-restart flags and accumulators, gradients
         const size_t off_k = (sizeof(GridInst) * gi.size() + 255) / 256 * 256;
@@ -681,6 +700,10 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             S.rho = O.rho;
             S.gamma = O.gamma;
             S.total_tasks = tasks;
+            S.level_tasks = level_tasks;
+            S.level_nodes = lvl_nodes;
+            S.level_slots = lvl_slots;
+            S.level_chunk = lvl_chunk;
             std::vector<double> kap(O.kappas, O.kappas + O.n_levels);
             if (hipMemcpyAsync(base, gi.data(), sizeof(GridInst) * gi.size(), hipMemcpyHostToDevice, gst) != hipSuccess ||
                 (O.n_levels > 0 && hipMemcpyAsync(base + off_k, kap.data(), sizeof(double) * kap.size(),
@@ -697,6 +720,11 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                 plan.sweep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((tasks + plan.sweep_wpb - 1) / plan.sweep_wpb,
                                                                                (int64_t)n_cu * 8));
                 plan.step_lds = step_lds;
+                plan.level_wpb = level_bytes ? (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / level_bytes)) : 1;
+                plan.level_lds = level_bytes * plan.level_wpb;
+                plan.level_blocks = level_tasks > 0 ? (int)std::min<int64_t>((level_tasks + plan.level_wpb - 1) / plan.level_wpb,
+                                                                             (int64_t)n_cu * 16)
+                                                    : 0;
                 plan.check_blocks = checks;
                 plan.use_graph = true;
                 rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, O.n_levels, gst);

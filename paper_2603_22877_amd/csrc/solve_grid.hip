@@ -27,7 +27,10 @@ __device__ __forceinline__ int find_base32(const GridInst *I, int n, int64_t key
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t b = which == 0 ? I[mid].task_base : which == 1 ? (int64_t)I[mid].rbase : I[mid].check_base;
+        const int64_t b = which == 0 ? I[mid].task_base
+                          : which == 1 ? (int64_t)I[mid].rbase
+                          : which == 2 ? I[mid].check_base
+                                       : I[mid].level_base;
         if (b <= key) lo = mid; else hi = mid - 1;
     }
     return lo;
@@ -94,6 +97,7 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1},
                                I.R_pad < 64 ? I.R_pad : 64};
         const TaskCtx t = task_ctx(T, pos, r, r_ok);
+        if (t.B.big) continue;   // evaluated by grid_level_kernel
         const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
         const bool hard = isinf(kappa);
         const float unsat = task_forward(T, t, st, kappa, hard, W);
@@ -106,6 +110,35 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         task_backward(T, t, wc, sc, W, lane);
     }
     flush();
+}
+
+// Big diagrams: one wavefront per (big constraint, chunk of restarts) over every instance,
+// level by level (level_eval), into the same gradient rows and objective accumulators.
+__global__ void __launch_bounds__(256) grid_level_kernel(const GridInst *insts, int n_inst, GridShared S) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, wib = wave_id(), wpb = blockDim.x >> 6;
+    const LevelRows W = LevelRows::at(lds + (size_t)wib * level_wave_floats(S.level_nodes, S.level_slots),
+                                      S.level_nodes, S.level_slots);
+    for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < S.level_tasks; task += (int64_t)gridDim.x * wpb) {
+        const int ii = find_base32(insts, n_inst, task, 3);
+        const GridInst &I = insts[ii];
+        const int chunks = (I.R + S.level_chunk - 1) / S.level_chunk;
+        const int64_t lt = task - I.level_base;
+        const int q = (int)(lt / chunks), r0 = (int)(lt - (int64_t)q * chunks) * S.level_chunk;
+        const int r1 = r0 + S.level_chunk < I.R ? r0 + S.level_chunk : I.R;
+        const TabView T = I.T;
+        const GlobalState st{View{I.a, I.R, T.n_bool, I.a_sr, 1}, View{I.b, I.R, T.n_real, I.b_sr, 1}};
+        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1}, 64};
+        const LevelCtx L = level_ctx(T, I.lev, I.big_pos[q]);
+        level_stage_nodes(T, L, W, lane);
+        for (int r = r0; r < r1; ++r) {
+            if (!S.stepping[I.rbase + r]) continue;   // uniform: one restart at a time
+            const double kappa = S.kappas[I.level_done[r]];
+            const float wc = I.w[(int64_t)r * T.n_cons + L.c];
+            const float unsat = level_eval(T, L, st, sc, r, kappa, isinf(kappa), wc, true, W, lane);
+            if (lane == 0 && wc * unsat != 0.0f) atomic_add_f32(S.obj_acc + I.rbase + r, wc * unsat);
+        }
+    }
 }
 
 // Projected step, one block per restart.
@@ -244,6 +277,11 @@ static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const Grid
         else
             hipLaunchKernelGGL(grid_sweep_kernel<kMsgLds>, g, b, P.sweep_lds, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid sweep"))) return rc;
+        if (P.level_blocks > 0) {
+            hipLaunchKernelGGL(grid_level_kernel, dim3(P.level_blocks), dim3(64 * P.level_wpb), P.level_lds, st, d_insts,
+                               n_inst, S);
+            if ((rc = launch_status("grid level"))) return rc;
+        }
         hipLaunchKernelGGL(grid_step_kernel, dim3(S.total_r), dim3(256), P.step_lds, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid step"))) return rc;
     }

@@ -16,6 +16,9 @@ struct GridInst {
     int32_t R, R_pad, log2_rpad, rbase;   // rbase: first global restart index
     int64_t task_base;                    // first sweep task (wave) of this instance
     int64_t check_base;                   // first check block of this instance
+    cptr<int32_t> lev, big_pos;           // level starts and positions of big diagrams
+    int32_t n_big, pad;
+    int64_t level_base;                   // first level-kernel task of this instance
 };
 
 struct GridShared {
@@ -27,12 +30,17 @@ struct GridShared {
     int32_t lds_nodes, lds_slots;
     float eta_a, eta_b, eps2, rho, gamma;
     int64_t total_tasks;
+    int64_t level_tasks;            // (big constraint, restart chunk) tasks over all instances
+    int32_t level_nodes, level_slots;   // level kernel LDS rows (max over big templates)
+    int32_t level_chunk, pad2;      // restarts per level task
 };
 
 struct GridPlan {
     int steps;
     int sweep_blocks, sweep_wpb;
     int msg;                        // message-store variant of the sweep (MsgVariant)
+    int level_blocks, level_wpb;    // level-synchronous kernel for big diagrams (0 blocks: none)
+    size_t level_lds;
     size_t sweep_lds, step_lds;
     int64_t check_blocks;
     bool use_graph;

@@ -157,8 +157,10 @@ def _autograd():
             obj = torch.zeros(R, device=a.device)
             need = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
             if need:
-                ga = torch.zeros_like(a, memory_format=torch.contiguous_format)
-                gb = torch.zeros_like(b, memory_format=torch.contiguous_format)
+                # variable-major [n][R] storage viewed as [R][n]: the restarts of one
+                # constraint update consecutive words, so the gradient atomics coalesce
+                ga = torch.zeros(a.shape[1], a.shape[0], device=a.device).t()
+                gb = torch.zeros(b.shape[1], b.shape[0], device=b.device).t()
                 cop_backward(handle, a.detach(), b.detach(), kappa, w, obj, ga, gb)
                 ctx.save_for_backward(ga, gb)
             else:

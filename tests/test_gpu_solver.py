@@ -72,6 +72,24 @@ def test_fused_step_random_formulas():
         _assert_step(p, a0, b0, st, 0.7, 0.3, 0.4)
 
 
+@pytest.mark.parametrize("kind,R", [("hybrid", 3), ("hybrid", 12), ("mixed", 5)])
+def test_fused_step_big_diagrams(kind, R):
+    """Instances with big diagrams go to the grid schedule, where the level-synchronous
+    kernel adds their gradient: one fused step matches the oracle (random hybrid: all
+    constraints big; mixed: short constraints one lane each, long ones level by level)."""
+    from workloads.format import KIND_AND, KIND_CARD_GE, KIND_CARD_LE, KIND_CLAUSE, KIND_NAE, KIND_XOR
+    if kind == "hybrid":
+        p = W.make_random_hybrid(100)
+    else:
+        p = W.make_random_formula(4100, n_bool=16, n_real=5, n_atoms=16, n_cons=80, max_len=32,
+                                  allow_repeats=False,
+                                  kinds=(KIND_CLAUSE, KIND_AND, KIND_XOR, KIND_NAE, KIND_CARD_LE, KIND_CARD_GE))
+    print(f"fused step {kind} R={R}", flush=True)
+    h, a0, b0, st = _one_step(p, R, 0.6, 0.3, 0.4, 7)
+    assert fsmt.xbdd_info(h)["n_big"] > 0
+    _assert_step(p, a0, b0, st, 0.6, 0.3, 0.4)
+
+
 def test_multi_instance_batch_equals_single():
     probs = [W.make_config(1), W.make_random_formula(3100, n_cons=60), W.make_fig2_toy(), W.make_config(2)]
     Rs = [3, 5, 2, 4]
@@ -185,12 +203,12 @@ def test_solver_rejects_bad_options():
     with pytest.raises(fsmt.FsmtError):
         S.solve_batched([h], [st], S.SolveConfig(kappas=[-1.0]))
     assert int(st.level_done.max()) == 0
-    # big diagrams are per-call only: the fused solver refuses them without launching
+    # big diagrams run in the grid schedule only: the persistent one refuses them
     hb = fsmt.xbdd_compile(W.make_random_hybrid(100))
     ab, bb = W.initial_points(W.make_random_hybrid(100), 2, 6, 0)
     stb = S.BatchState(hb, ab, bb)
     with pytest.raises(fsmt.FsmtError) as e:
-        S.solve_batched([hb], [stb], S.SolveConfig(kappas=[0.1]))
+        S.solve_batched([hb], [stb], S.SolveConfig(kappas=[0.1], schedule=1))
     assert e.value.code == fsmt._abi.FSMT_EUNSUPPORTED
     assert int(stb.level_done.max()) == 0
 
