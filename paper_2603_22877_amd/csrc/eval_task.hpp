@@ -602,6 +602,12 @@ __device__ __forceinline__ float level_eval(const TabView &T, const LevelCtx &L,
                                             int lane) {
     const int N = L.B.n_nodes, S = L.B.n_slots, NB = L.B.n_bslots;
     const int64_t np = L.B.n_pos;
+    // with fewer than 64 slots, lane s keeps slot s's probabilities and level start s in
+    // registers and the level loops read them with v_readlane instead of memory loads
+    const bool in_regs = S < 64;
+    float p_lane = 0.0f, q_lane = 0.0f;
+    int lev_lane = 0;
+    if (in_regs && lane <= S) lev_lane = L.lev[lane];
     for (int s = lane; s < S; s += 64) {
         float p, qq, d = 0.0f;
         if (s < NB) {
@@ -618,15 +624,31 @@ __device__ __forceinline__ float level_eval(const TabView &T, const LevelCtx &L,
         W.P[s] = p;
         W.Q[s] = qq;
         W.D[s] = d;
+        p_lane = p;
+        q_lane = qq;
     }
+    auto level_of = [&](int s, int &v0, int &v1, float &p, float &qq) {
+        if (in_regs) {
+            v0 = __builtin_amdgcn_readlane(lev_lane, s);
+            v1 = __builtin_amdgcn_readlane(lev_lane, s + 1);
+            p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p_lane), s));
+            qq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q_lane), s));
+        } else {
+            v0 = L.lev[s];
+            v1 = L.lev[s + 1];
+            p = W.P[s];
+            qq = W.Q[s];
+        }
+    };
     for (int v = lane; v < N + 2; v += 64) W.M[v] = 0.0f;
     wave_lds_sync();
     if (lane == 0) W.M[L.B.root] = 1.0f;
     wave_lds_sync();
     for (int s = 0; s < S; ++s) {
-        const int v0 = L.lev[s], v1 = L.lev[s + 1];
+        int v0, v1;
+        float p, qq;
+        level_of(s, v0, v1, p, qq);
         if (v0 == v1) continue;
-        const float p = W.P[s], qq = W.Q[s];
         for (int v = v0 + lane; v < v1; v += 64) {
             const Node x = unpack_node(W.NL[v]);
             const float mv = W.M[v];
@@ -643,10 +665,11 @@ __device__ __forceinline__ float level_eval(const TabView &T, const LevelCtx &L,
         }
         wave_lds_sync();
         for (int s = S - 1; s >= 0; --s) {
-            const int v0 = L.lev[s], v1 = L.lev[s + 1];
+            int v0, v1;
+            float p, qq;
+            level_of(s, v0, v1, p, qq);
             float g = 0.0f;
             if (v0 < v1) {
-                const float p = W.P[s], qq = W.Q[s];
                 for (int v = v0 + lane; v < v1; v += 64) {
                     const Node x = unpack_node(W.NL[v]);
                     const float bh = W.Bm[x.hi], bl = W.Bm[x.lo];
