@@ -334,8 +334,14 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
     constexpr int KN = Ms::kNodes, KS = Ms::kSlots;
     const int N = t.B.n_nodes, S = t.B.n_slots, NB = t.B.n_bslots;
     const int64_t np = t.B.n_pos;
+    // the first Boolean id and the first atom record are requested together before any
+    // slot is evaluated, so their latencies overlap (a clause has one of each)
+    const int id0 = NB > 0 ? t.sup[0] : 0;
+    AtomRec rec0;
+    const bool has_rec0 = (Ms::kInlineOnly || t.rec) && S > NB;
+    if (has_rec0) rec0 = load_rec(t.rec);
     for_up<KS>(0, NB, [&](int s) {
-        const float av = t.valid ? st.av(t.r, t.sup[(int64_t)s * np]) : 0.0f;
+        const float av = t.valid ? st.av(t.r, s == 0 ? id0 : t.sup[(int64_t)s * np]) : 0.0f;
         W.P(s) = (1.0f - av) * 0.5f;
         W.Q(s) = (1.0f + av) * 0.5f;
     });
@@ -343,7 +349,7 @@ __device__ __forceinline__ float task_forward(const TabView &T, const TaskCtx &t
         float p = 0.5f, q = 0.5f, d = 0.0f;
         if (t.valid) {
             if (Ms::kInlineOnly || t.rec) {
-                const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
+                const AtomRec a = s == NB ? rec0 : load_rec(t.rec + (int64_t)(s - NB) * np);
                 atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p, q, d);
             } else {
                 const int k = t.sup[(int64_t)s * np] - T.n_bool;

@@ -173,8 +173,8 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             float oacc = 0.0f;
             for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
+                const float wc = t.valid ? wload(t.c) : 0.0f;   // requested before the forward pass
                 const float unsat = task_forward(T, t, st, kappa, hard, W);
-                const float wc = t.valid ? wload(t.c) : 0.0f;
                 oacc += wc * unsat;
                 task_backward(T, t, wc, sc, W, lane);
             }

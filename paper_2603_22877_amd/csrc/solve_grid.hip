@@ -100,8 +100,8 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         if (t.B.big) continue;   // evaluated by grid_level_kernel
         const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
         const bool hard = isinf(kappa);
+        const float wc = t.valid ? I.w[(int64_t)r * T.n_cons + t.c] : 0.0f;   // requested before the forward pass
         const float unsat = task_forward(T, t, st, kappa, hard, W);
-        const float wc = t.valid ? I.w[(int64_t)r * T.n_cons + t.c] : 0.0f;
         if (I.R_pad <= 64) {
             oacc += wc * unsat;
         } else if (r < I.R && wc * unsat != 0.0f) {
