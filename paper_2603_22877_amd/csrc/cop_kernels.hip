@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
 // ------------------------------------------------------------------ big diagrams
 // Level-synchronous passes (see level_eval): one wavefront per (big constraint, chunk of
 // restarts); the wave stages the constraint's node table in its LDS rows once and evaluates
-// the chunk's restarts one after the other.
+// the chunk's restarts one after the other, keeping the objective's partial sums in lanes.
 struct LevelArgs {
     TabView T;
     cptr<int32_t> lev, big_pos;
@@ -113,20 +113,22 @@ __global__ void __launch_bounds__(256) cop_level_kernel(LevelArgs A) {
     const GlobalScatter sc{A.ga, A.gb, 64};
     const int chunks = (A.R + A.chunk - 1) / A.chunk;
     const int64_t n_tasks = (int64_t)A.n_big * chunks;
+    WaveObjAcc oa{A.obj};
+    // chunk-major task order: a wave's consecutive tasks share their restart chunk
     for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < n_tasks; task += (int64_t)gridDim.x * wpb) {
-        const int q = (int)(task / chunks), r0 = (int)(task - (int64_t)q * chunks) * A.chunk;
-        const int r1 = r0 + A.chunk < A.R ? r0 + A.chunk : A.R;
+        const int ci = (int)(task / A.n_big), q = (int)(task - (int64_t)ci * A.n_big);
+        const int r0 = ci * A.chunk, r1 = r0 + A.chunk < A.R ? r0 + A.chunk : A.R;
+        oa.begin(r0, r1 - r0, lane);
         const LevelCtx L = level_ctx(A.T, A.lev, A.big_pos[q]);
         level_stage_nodes(A.T, L, W, lane);
         for (int r = r0; r < r1; ++r) {
             const float wc = A.w.at(r, L.c);
             const float unsat = level_eval(A.T, L, st, sc, r, A.kappa, A.hard != 0, wc, kGrad, W, lane);
-            if (lane == 0) {
-                if (A.unsat.data) A.unsat.at(r, L.c) = unsat;
-                if (A.obj) atomic_add_f32(A.obj + r, wc * unsat);
-            }
+            if (lane == 0 && A.unsat.data) A.unsat.at(r, L.c) = unsat;
+            oa.add(r - r0, wc * unsat, lane);
         }
     }
+    oa.flush(lane);
 }
 
 // ------------------------------------------------------------------ small kernels

@@ -575,6 +575,31 @@ __device__ __forceinline__ LevelCtx level_ctx(const TabView &T, cptr<int32_t> le
     return L;
 }
 
+// Objective partial sums of one wave for a block of consecutive restarts (lane i holds
+// restart base + i, at most 64): added to the accumulators with one atomic per restart when
+// the wave moves to another block and at the end. One float atomic per (constraint,
+// restart) into a large sum would round away a bias when many constraints add the same
+// value; per-wave partial sums keep the number of such additions small.
+struct WaveObjAcc {
+    float *obj;
+    int base = -1, count = 0;
+    float acc = 0.0f;
+    __device__ __forceinline__ void flush(int lane) {
+        if (obj && base >= 0 && lane < count && acc != 0.0f) atomic_add_f32(obj + base + lane, acc);
+        acc = 0.0f;
+    }
+    __device__ __forceinline__ void begin(int b, int n, int lane) {
+        if (b != base || n != count) {
+            flush(lane);
+            base = b;
+            count = n;
+        }
+    }
+    __device__ __forceinline__ void add(int i, float v, int lane) {
+        if (lane == i) acc += v;
+    }
+};
+
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;

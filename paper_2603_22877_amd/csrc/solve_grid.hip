@@ -119,13 +119,16 @@ __global__ void __launch_bounds__(256) grid_level_kernel(const GridInst *insts, 
     const int lane = threadIdx.x & 63, wib = wave_id(), wpb = blockDim.x >> 6;
     const LevelRows W = LevelRows::at(lds + (size_t)wib * level_wave_floats(S.level_nodes, S.level_slots),
                                       S.level_nodes, S.level_slots);
+    WaveObjAcc oa{S.obj_acc};
+    // chunk-major task order inside an instance: a wave's consecutive tasks share their
+    // restart chunk, so the objective's partial sums stay in lanes
     for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < S.level_tasks; task += (int64_t)gridDim.x * wpb) {
         const int ii = find_base32(insts, n_inst, task, 3);
         const GridInst &I = insts[ii];
-        const int chunks = (I.R + S.level_chunk - 1) / S.level_chunk;
         const int64_t lt = task - I.level_base;
-        const int q = (int)(lt / chunks), r0 = (int)(lt - (int64_t)q * chunks) * S.level_chunk;
-        const int r1 = r0 + S.level_chunk < I.R ? r0 + S.level_chunk : I.R;
+        const int ci = (int)(lt / I.n_big), q = (int)(lt - (int64_t)ci * I.n_big);
+        const int r0 = ci * S.level_chunk, r1 = r0 + S.level_chunk < I.R ? r0 + S.level_chunk : I.R;
+        oa.begin(I.rbase + r0, r1 - r0, lane);
         const TabView T = I.T;
         const GlobalState st{View{I.a, I.R, T.n_bool, I.a_sr, 1}, View{I.b, I.R, T.n_real, I.b_sr, 1}};
         const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1}, 64};
@@ -136,9 +139,10 @@ __global__ void __launch_bounds__(256) grid_level_kernel(const GridInst *insts, 
             const double kappa = S.kappas[I.level_done[r]];
             const float wc = I.w[(int64_t)r * T.n_cons + L.c];
             const float unsat = level_eval(T, L, st, sc, r, kappa, isinf(kappa), wc, true, W, lane);
-            if (lane == 0 && wc * unsat != 0.0f) atomic_add_f32(S.obj_acc + I.rbase + r, wc * unsat);
+            oa.add(r - r0, wc * unsat, lane);
         }
     }
+    oa.flush(lane);
 }
 
 // Projected step, one block per restart.

@@ -408,3 +408,54 @@ def test_config5_autograd_and_full_check():
     np.testing.assert_array_equal(ver.cpu().numpy(), ch["verdict"])
     np.testing.assert_array_equal(x.cpu().numpy(), ch["x"])
     print(f"n_unsat per restart: {nu.cpu().numpy().tolist()}", flush=True)
+
+
+# ---- the paper's scheduling and 3D-placement encodings (index bits, XOR disjunctions)
+def _paper_instance(fam, A, B, k=0):
+    from workloads.paper_suite import make_paper_placement, make_paper_scheduling
+    if fam == "sched":
+        return make_paper_scheduling(A, B, W.seed_seq(8, A, B, k))
+    return make_paper_placement(A, B, W.seed_seq(9, A, B, k))
+
+
+@pytest.mark.parametrize("fam,A,B", [("sched", 16, 2), ("sched", 32, 2), ("sched", 8, 5), ("place", 2, 2),
+                                     ("place", 4, 4), ("place", 8, 8)])
+@pytest.mark.parametrize("R", [1, 5, 16])
+def test_paper_suite_cop_parity(fam, A, B, R):
+    p = _paper_instance(fam, A, B)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"paper {fam} {A}x{B} R={R} cons={p.n_cons} nodes={info['max_nodes']} "
+          f"slots={info['max_slots']} big={info['n_big']}", flush=True)
+    a, b = W.initial_points(p, R, 11, A, B)
+    a[0], b[0] = 0.8 * p.cert_x, p.cert_y        # near the certificate
+    ell = p.meta.get("mean_duration", p.meta.get("mean_side"))
+    w = np.random.default_rng(A * 10 + B).uniform(0.5, 2, (R, p.n_cons))
+    for kap in (0.5 / ell, 4.0 / ell, INF):
+        _compare(p, a, b, kap, w=w)
+
+
+@pytest.mark.parametrize("R", [1, 3])
+def test_paper_placement_big_diagrams(R):
+    """32 macros x 8 layers: 8 index bits per module pair, 28-node diagrams beyond the
+    per-lane message bound, so every non-overlap constraint takes the level kernel."""
+    p = _paper_instance("place", 32, 8)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"paper placement 32x8 R={R} cons={p.n_cons} big={info['n_big']}", flush=True)
+    assert info["n_big"] == p.meta["n_pairs"]
+    a, b = W.initial_points(p, R, 12, R)
+    a[0], b[0] = 0.8 * p.cert_x, p.cert_y
+    for kap in (2.0, 20.0):
+        _compare(p, a, b, kap)
+
+
+@pytest.mark.parametrize("fam,A,B", [("sched", 16, 2), ("sched", 32, 3), ("place", 4, 8), ("place", 32, 8)])
+def test_paper_suite_check_bit_exact(fam, A, B):
+    p = _paper_instance(fam, A, B)
+    a, b = W.initial_points(p, 8, 13, A, B)
+    a[0], b[0] = p.cert_x, p.cert_y
+    a[1], b[1] = p.cert_x, p.cert_y.copy()
+    b[1, 0] += 0.3
+    h = fsmt.xbdd_compile(p)
+    g = _check_gpu(p, h, a, b)
+    _assert_check_equal(g, oracle.check(p, a, b))
+    assert g["verdict"][0] == 1

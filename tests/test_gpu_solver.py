@@ -90,6 +90,26 @@ def test_fused_step_big_diagrams(kind, R):
     _assert_step(p, a0, b0, st, 0.6, 0.3, 0.4)
 
 
+def _paper_instance(fam, A, B, k=0):
+    from workloads.paper_suite import make_paper_placement, make_paper_scheduling
+    if fam == "sched":
+        return make_paper_scheduling(A, B, W.seed_seq(8, A, B, k))
+    return make_paper_placement(A, B, W.seed_seq(9, A, B, k))
+
+
+@pytest.mark.parametrize("fam,A,B,schedule", [("sched", 16, 2, 1), ("sched", 16, 2, 2), ("sched", 32, 3, 2),
+                                              ("place", 4, 4, 1), ("place", 4, 4, 2), ("place", 32, 8, 2)])
+def test_fused_step_paper_suite(fam, A, B, schedule):
+    """One fused step on the paper's encodings (unit-atom projection: precedences, routing
+    adjacency and module bounds are projected onto)."""
+    p = _paper_instance(fam, A, B)
+    ell = p.meta.get("mean_duration", p.meta.get("mean_side"))
+    kap, eta_b = 2.0 / ell, 0.2 * ell * ell
+    print(f"fused step paper {fam} {A}x{B} schedule {schedule}", flush=True)
+    h, a0, b0, st = _one_step(p, 4, kap, 0.5, eta_b, A * 10 + B, schedule)
+    _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
+
+
 def test_multi_instance_batch_equals_single():
     probs = [W.make_config(1), W.make_random_formula(3100, n_cons=60), W.make_fig2_toy(), W.make_config(2)]
     Rs = [3, 5, 2, 4]

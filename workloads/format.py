@@ -166,3 +166,73 @@ class Builder:
             real_lo=self.real_lo, real_hi=self.real_hi, meta=dict(meta or {}))
         p.validate()
         return p
+
+
+class BlockBuilder:
+    """Vectorized construction of a :class:`Problem` from blocks of equally shaped rows.
+
+    ``atoms`` appends K atoms with the same number of terms and comparison; ``constraints``
+    appends K constraints of one kind with the same literal count and EXPR program. Atoms
+    are not interned (the caller makes them distinct).
+    """
+
+    def __init__(self, n_bool: int, n_real: int, real_lo, real_hi):
+        self.n_bool = n_bool
+        self.n_real = n_real
+        self.real_lo = np.broadcast_to(np.asarray(real_lo, np.float64), (n_real,)).copy()
+        self.real_hi = np.broadcast_to(np.asarray(real_hi, np.float64), (n_real,)).copy()
+        self._atoms: list = []
+        self._n_atoms = 0
+        self._cons: list = []
+
+    def atoms(self, vars_, coefs, op: int, rhs) -> np.ndarray:
+        """K atoms ``sum_t coefs[k,t] * y[vars[k,t]]  op  rhs[k]``; returns their variable ids."""
+        v = np.asarray(vars_, np.int32)
+        if v.ndim == 1:
+            v = v[:, None]
+        K = v.shape[0]
+        c = np.broadcast_to(np.asarray(coefs, np.float64), v.shape).copy()
+        r = np.broadcast_to(np.asarray(rhs, np.float64), (K,)).copy()
+        self._atoms.append((v, c, int(op), r))
+        ids = self.n_bool + self._n_atoms + np.arange(K, dtype=np.int64)
+        self._n_atoms += K
+        return ids
+
+    def constraints(self, kind: int, lits, param: int = 0, program=()) -> None:
+        """K constraints of ``kind`` with literal rows ``lits[k]`` (codes from :func:`lit`)."""
+        L = np.asarray(lits, np.int64)
+        if L.ndim == 1:
+            L = L[:, None]
+        self._cons.append((int(kind), L.astype(np.int32), int(param),
+                           np.asarray(program, np.int32)))
+
+    def build(self, meta=None) -> Problem:
+        atom_ptr = np.zeros(self._n_atoms + 1, np.int64)
+        if self._atoms:
+            np.cumsum(np.concatenate([np.full(v.shape[0], v.shape[1]) for v, _, _, _ in self._atoms]),
+                      out=atom_ptr[1:])
+        cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+        atom_var = cat([v.reshape(-1) for v, _, _, _ in self._atoms], np.int32)
+        atom_coef = cat([c.reshape(-1) for _, c, _, _ in self._atoms], np.float64)
+        atom_rhs = cat([r for _, _, _, r in self._atoms], np.float64)
+        atom_op = cat([np.full(v.shape[0], op) for v, _, op, _ in self._atoms], np.int8)
+        C = sum(L.shape[0] for _, L, _, _ in self._cons)
+        con_ptr = np.zeros(C + 1, np.int64)
+        expr_ptr = np.zeros(C + 1, np.int64)
+        if C:
+            np.cumsum(np.concatenate([np.full(L.shape[0], L.shape[1]) for _, L, _, _ in self._cons]),
+                      out=con_ptr[1:])
+            np.cumsum(np.concatenate([np.full(L.shape[0], len(pg)) for _, L, _, pg in self._cons]),
+                      out=expr_ptr[1:])
+        p = Problem(
+            n_bool=self.n_bool, n_real=self.n_real, atom_ptr=atom_ptr, atom_var=atom_var,
+            atom_coef=atom_coef, atom_rhs=atom_rhs, atom_op=atom_op,
+            con_kind=cat([np.full(L.shape[0], k) for k, L, _, _ in self._cons], np.int32),
+            con_ptr=con_ptr,
+            con_lit=cat([L.reshape(-1) for _, L, _, _ in self._cons], np.int32),
+            con_param=cat([np.full(L.shape[0], pa) for _, L, pa, _ in self._cons], np.int32),
+            expr_ptr=expr_ptr,
+            expr_ops=cat([np.tile(pg, L.shape[0]) for _, L, _, pg in self._cons], np.int32),
+            real_lo=self.real_lo, real_hi=self.real_hi, meta=dict(meta or {}))
+        p.validate()
+        return p
