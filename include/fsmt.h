@@ -120,6 +120,8 @@ typedef struct {
     int32_t n_halfspaces;      /* multi-variable unit atoms kept as half-spaces of D */
     int32_t n_big;             /* constraints with big diagrams (evaluated level by level,
                                   one wavefront per constraint and restart) */
+    int32_t n_hs_colors;       /* colour classes of the half-spaces (members share no variable;
+                                  the projection handles a class's members in parallel) */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

@@ -288,7 +288,7 @@ fsmt_status select_device(const fsmt_xbdd *h) {
 
 HalfSpaces halfspaces_of(const fsmt_xbdd *h) {
     return HalfSpaces{as_cptr(h->d.hs_ptr), as_cptr(h->d.hs_var), as_cptr(h->d.hs_coef), as_cptr(h->d.hs_rhs),
-                      as_cptr(h->d.hs_inv), h->n_hs, h->hs_nnz};
+                      as_cptr(h->d.hs_inv), as_cptr(h->d.hs_cstart), h->n_hs, h->hs_nnz, h->n_hs_colors, 0};
 }
 
 static fsmt_status launch_status(const char *what) {
@@ -397,10 +397,12 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         if (grad) {
             if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<true, kMsgSmall>), g, bl, 0, st, A);
             else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<true, kMsgMedium>), g, bl, 0, st, A);
+            else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<true, kMsgLarge>), g, bl, 0, st, A);
             else hipLaunchKernelGGL((cop_kernel<true, kMsgLds>), g, bl, lds, st, A);
         } else {
             if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<false, kMsgSmall>), g, bl, 0, st, A);
             else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<false, kMsgMedium>), g, bl, 0, st, A);
+            else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<false, kMsgLarge>), g, bl, 0, st, A);
             else hipLaunchKernelGGL((cop_kernel<false, kMsgLds>), g, bl, lds, st, A);
         }
         if ((rc = launch_status("cop kernel"))) return rc;

@@ -478,10 +478,11 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
 
 // Message-store variants: a kernel is instantiated per variant and the host picks the
 // smallest whose bounds hold for every diagram of the launch.
-enum MsgVariant { kMsgLds = 0, kMsgSmall = 1, kMsgMedium = 2 };
+enum MsgVariant { kMsgLds = 0, kMsgSmall = 1, kMsgMedium = 2, kMsgLarge = 3 };
 template <int V> struct MsgOf;
 template <> struct MsgOf<kMsgSmall> { using type = RegMsgs<4, 4>; };
 template <> struct MsgOf<kMsgMedium> { using type = RegMsgs<20, 12>; };
+template <> struct MsgOf<kMsgLarge> { using type = RegMsgs<kLargeMaxNodes, kLargeMaxSlots>; };
 template <> struct MsgOf<kMsgLds> { using type = LdsMsgs; };
 
 // Bind a store: an LDS store to the wave's columns (base: this wave's LDS scratch), a
@@ -513,6 +514,7 @@ inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inl
     if (lds_only || !all_inline) return kMsgLds;
     if (max_nodes <= 4 && max_slots <= 4) return kMsgSmall;
     if (max_nodes <= 20 && max_slots <= 12) return kMsgMedium;
+    if (max_nodes <= kLargeMaxNodes && max_slots <= kLargeMaxSlots) return kMsgLarge;
     return kMsgLds;
 }
 

@@ -31,10 +31,15 @@ struct TplInfo {
     int32_t pad[2];
 };
 
-// A diagram is "big" when its per-lane message columns would take more than 32 KB of LDS
-// per wavefront; big diagrams are evaluated level by level, one wavefront per
-// (constraint, restart), instead of one lane per constraint.
-constexpr int64_t kBigDiagramBytes = 32768;
+// A diagram is "big" when its per-lane message columns would take more than 40 KB of LDS
+// per wavefront (four such wavefronts fill a compute unit's LDS); big diagrams are
+// evaluated level by level, one wavefront per (constraint, restart), instead of one lane
+// per constraint. Every diagram within the register bounds below is under the limit.
+constexpr int64_t kBigDiagramBytes = 40960;
+// Bounds of the largest register-resident message store: node messages take nodes + 3
+// registers (two terminals and a spare), which must stay within one 32-register tuple
+// for indexed register access.
+constexpr int kLargeMaxNodes = 29, kLargeMaxSlots = 24;
 inline bool big_diagram(int n_nodes, int n_slots) {
     const int64_t ss = n_slots > 1 ? n_slots : 1;
     return (2 * ((int64_t)n_nodes + 2) + 4 * ss) * 64 * 4 > kBigDiagramBytes;
@@ -98,6 +103,7 @@ struct DeviceTables {
     float *hs_coef = nullptr;
     float *hs_rhs = nullptr;          // [H] q0 - delta
     float *hs_inv = nullptr;          // [H] 1 / |q|^2
+    int32_t *hs_cstart = nullptr;     // [K+1] colour classes: half-spaces of a class share no variable
 };
 
 }  // namespace fsmt
@@ -111,7 +117,7 @@ struct fsmt_xbdd {
     int big_max_nodes = 0, big_max_slots = 0;       // over big templates
     int n_big = 0;                                  // constraints in big buckets
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
-    int n_box_units = 0, n_hs = 0, hs_nnz = 0;
+    int n_box_units = 0, n_hs = 0, hs_nnz = 0, n_hs_colors = 0;
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record
     std::vector<fsmt::TplInfo> h_tpl;

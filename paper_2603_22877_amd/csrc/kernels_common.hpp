@@ -87,11 +87,13 @@ __device__ __forceinline__ float block_sum(float v) {
     return t;
 }
 
-// Half-spaces q.y <= rhs of the feasible set (multi-variable unit atoms).
+// Half-spaces q.y <= rhs of the feasible set (multi-variable unit atoms), stored by colour
+// class: the half-spaces cstart[k] .. cstart[k+1]-1 share no variable.
 struct HalfSpaces {
     cptr<int32_t> ptr, var;
     cptr<float> coef, rhs, inv;
-    int32_t n, nnz;
+    cptr<int32_t> cstart;
+    int32_t n, nnz, n_colors, pad;
 };
 
 // Orders this wave's LDS accesses (the next instructions read what this wave wrote).
@@ -102,22 +104,21 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces.
 // If the clamped point already satisfies every half-space it is the projection; otherwise
-// Dykstra's alternating projections run from y (half-spaces in order, then the box, per
-// sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no coordinate by more than
-// 4e-7 (1 + |y|), or 256 sweeps. The sweeps run on the block's first wavefront alone
-// (one lane for the half-spaces, the wave for the box), ordered by LDS waits instead of
-// block barriers. All threads of the block must call it.
+// Dykstra's alternating projections run from y (the colour classes of half-spaces in order,
+// then the box, per sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no
+// coordinate by more than 4e-7 (1 + |y|), or 256 sweeps. Projecting onto a class is
+// projecting onto each member independently (they share no variable), so the members of a
+// class run on parallel lanes. The sweeps run on the block's first wavefront alone, ordered
+// by LDS waits instead of block barriers. All threads of the block must call it.
 __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, cptr<float> lo, cptr<float> hi,
                                                 int m, const HalfSpaces &hs) {
     for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
     __syncthreads();
     int violated = 0;
-    if (threadIdx.x == 0) {
-        for (int t = 0; t < hs.n && !violated; ++t) {
-            float v = -hs.rhs[t];
-            for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) v += hs.coef[e] * pb[hs.var[e]];
-            violated = v > 0.0f;
-        }
+    for (int t = threadIdx.x; t < hs.n; t += blockDim.x) {
+        float v = -hs.rhs[t];
+        for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) v += hs.coef[e] * pb[hs.var[e]];
+        violated |= v > 0.0f ? 1 : 0;
     }
     if (!__syncthreads_or(violated)) {
         for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = pb[j];
@@ -131,8 +132,8 @@ __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, 
         wave_lds_sync();
         for (int sweep = 0; sweep < 256; ++sweep) {
             int moved = 0;
-            if (lane == 0) {
-                for (int t = 0; t < hs.n; ++t) {
+            for (int k = 0; k < hs.n_colors; ++k) {
+                for (int t = hs.cstart[k] + lane; t < hs.cstart[k + 1]; t += 64) {
                     const int e0 = hs.ptr[t], e1 = hs.ptr[t + 1];
                     float viol = -hs.rhs[t];
                     for (int e = e0; e < e1; ++e) viol += hs.coef[e] * (y[hs.var[e]] + ph[e]);
@@ -145,8 +146,8 @@ __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, 
                         y[j] = yp;
                     }
                 }
+                wave_lds_sync();
             }
-            wave_lds_sync();
             for (int j = lane; j < m; j += 64) {
                 const float z = y[j] + pb[j];
                 const float yp = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);

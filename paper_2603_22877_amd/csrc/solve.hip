@@ -106,9 +106,11 @@ __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, in
 }
 
 // Waves per workgroup of the solver kernel for each message variant: register-resident
-// messages of the larger bound need up to 256 VGPRs, so those workgroups hold 8 waves.
+// messages of the medium bound take about 200 VGPRs (8 waves per workgroup), those of the
+// large bound all 256 (one wave per SIMD, 4 waves per workgroup).
 template <int V> struct SolveWaves { static constexpr int value = 16; };
 template <> struct SolveWaves<kMsgMedium> { static constexpr int value = 8; };
+template <> struct SolveWaves<kMsgLarge> { static constexpr int value = 4; };
 
 // kCluster: k workgroups per restart (k read from the descriptor); otherwise k = 1 and the
 // kernel carries none of the cluster's exchange state.
@@ -324,7 +326,8 @@ static int lds_budget_bytes() {
             budget = v;
         const void *fns[] = {(const void *)solve_wg_kernel<kMsgLds, false>, (const void *)solve_wg_kernel<kMsgSmall, false>,
                              (const void *)solve_wg_kernel<kMsgMedium, false>, (const void *)solve_wg_kernel<kMsgLds, true>,
-                             (const void *)solve_wg_kernel<kMsgSmall, true>, (const void *)solve_wg_kernel<kMsgMedium, true>};
+                             (const void *)solve_wg_kernel<kMsgSmall, true>, (const void *)solve_wg_kernel<kMsgMedium, true>,
+                             (const void *)solve_wg_kernel<kMsgLarge, false>, (const void *)solve_wg_kernel<kMsgLarge, true>};
         for (const void *f : fns) {
             if (budget > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
                 (void)hipGetLastError();
@@ -336,7 +339,9 @@ static int lds_budget_bytes() {
 }
 
 static int solve_waves(int msg) {
-    return msg == kMsgMedium ? SolveWaves<kMsgMedium>::value : SolveWaves<kMsgSmall>::value;
+    return msg == kMsgMedium  ? SolveWaves<kMsgMedium>::value
+           : msg == kMsgLarge ? SolveWaves<kMsgLarge>::value
+                              : SolveWaves<kMsgSmall>::value;
 }
 
 static size_t state_floats_of(const fsmt_xbdd *h) {
@@ -484,6 +489,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         auto kernel_of = [&](bool cl) -> const void * {
             if (msg == kMsgSmall) return cl ? (const void *)solve_wg_kernel<kMsgSmall, true> : (const void *)solve_wg_kernel<kMsgSmall, false>;
             if (msg == kMsgMedium) return cl ? (const void *)solve_wg_kernel<kMsgMedium, true> : (const void *)solve_wg_kernel<kMsgMedium, false>;
+            if (msg == kMsgLarge) return cl ? (const void *)solve_wg_kernel<kMsgLarge, true> : (const void *)solve_wg_kernel<kMsgLarge, false>;
             return cl ? (const void *)solve_wg_kernel<kMsgLds, true> : (const void *)solve_wg_kernel<kMsgLds, false>;
         };
         auto resident_of = [&](bool cl) -> int64_t {
@@ -576,6 +582,10 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                     hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, true>), g, b, lds, st, d, P, flags, abort_flag);
                 else if (msg == kMsgMedium)
                     hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, false>), g, b, lds, st, d, P, flags, abort_flag);
+                else if (msg == kMsgLarge && k > 1)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLarge, true>), g, b, lds, st, d, P, flags, abort_flag);
+                else if (msg == kMsgLarge)
+                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLarge, false>), g, b, lds, st, d, P, flags, abort_flag);
                 else if (k > 1)
                     hipLaunchKernelGGL((solve_wg_kernel<kMsgLds, true>), g, b, lds, st, d, P, flags, abort_flag);
                 else

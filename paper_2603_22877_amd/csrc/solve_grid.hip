@@ -278,6 +278,8 @@ static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const Grid
             hipLaunchKernelGGL(grid_sweep_kernel<kMsgSmall>, g, b, 0, st, d_insts, n_inst, S);
         else if (P.msg == kMsgMedium)
             hipLaunchKernelGGL(grid_sweep_kernel<kMsgMedium>, g, b, 0, st, d_insts, n_inst, S);
+        else if (P.msg == kMsgLarge)
+            hipLaunchKernelGGL(grid_sweep_kernel<kMsgLarge>, g, b, 0, st, d_insts, n_inst, S);
         else
             hipLaunchKernelGGL(grid_sweep_kernel<kMsgLds>, g, b, P.sweep_lds, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid sweep"))) return rc;

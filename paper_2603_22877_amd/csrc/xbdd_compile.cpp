@@ -418,6 +418,14 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     h->n_cons = C;
     h->n_tpl = T;
     h->nnz = (int64_t)a_var.size();
+    // an atom fits an inline record when it has at most two terms and float32-exact
+    // coefficients and right-hand side (the register message stores need every atom so)
+    auto atom_inline_ok = [&](int k) {
+        const int64_t e0 = a_ptr[k], e1 = a_ptr[k + 1];
+        bool ok = (e1 - e0) <= 2 && (double)(float)a_rhs[k] == a_rhs[k] && std::isfinite((float)a_scale[k]);
+        for (int64_t e = e0; e < e1 && ok; ++e) ok = (double)(float)a_coef[e] == a_coef[e];
+        return ok;
+    };
     std::vector<TplInfo> tinfo(T);
     std::vector<Node> nodes;
     std::vector<int32_t> lev;   // level starts: nodes are sorted by slot, so each level is a range
@@ -477,10 +485,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         bool ok = true;
         for (int i = 0; i < bi.n_con && ok; ++i)
             for (int s = bi.n_bslots; s < bi.n_slots && ok; ++s) {
-                const int k = sup[bi.sup_base + (int64_t)s * bi.n_pos + i] - n;
-                const int e0 = a_ptr[k], e1 = a_ptr[k + 1];
-                ok = (e1 - e0) <= 2 && (double)(float)a_rhs[k] == a_rhs[k] && std::isfinite((float)a_scale[k]);
-                for (int e = e0; e < e1 && ok; ++e) ok = (double)(float)a_coef[e] == a_coef[e];
+                ok = atom_inline_ok(sup[bi.sup_base + (int64_t)s * bi.n_pos + i] - n);
             }
         if (!ok) {
             all_inline = false;
@@ -572,7 +577,53 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         }
     }
 
+    // colour classes of the half-spaces (greedy, in order): no two half-spaces of a class
+    // share a variable, so projecting onto a class is projecting onto each of its members
+    // independently, and Dykstra's method runs over the classes with the members of a class
+    // on parallel lanes. Half-spaces are stored class by class; hs_cstart[k] is the first
+    // of class k.
+    std::vector<int32_t> hs_cstart{0};
+    {
+        const int H = (int)hs_rhs.size();
+        std::vector<int32_t> color(H, 0);
+        std::vector<std::vector<int32_t>> var_colors(m);
+        int n_colors = 0;
+        std::vector<char> used;
+        for (int t = 0; t < H; ++t) {
+            used.assign((size_t)n_colors + 1, 0);
+            for (int e = hs_ptr[t]; e < hs_ptr[t + 1]; ++e)
+                for (int32_t k : var_colors[hs_var[e]]) used[k] = 1;
+            int k = 0;
+            while (used[k]) ++k;
+            color[t] = k;
+            n_colors = std::max(n_colors, k + 1);
+            for (int e = hs_ptr[t]; e < hs_ptr[t + 1]; ++e) var_colors[hs_var[e]].push_back(k);
+        }
+        std::vector<int32_t> order(H);
+        for (int t = 0; t < H; ++t) order[t] = t;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return color[x] < color[y]; });
+        std::vector<int32_t> p2{0}, v2;
+        std::vector<float> c2, r2, i2;
+        for (int q = 0; q < H; ++q) {
+            const int t = order[q];
+            for (int e = hs_ptr[t]; e < hs_ptr[t + 1]; ++e) {
+                v2.push_back(hs_var[e]);
+                c2.push_back(hs_coef[e]);
+            }
+            p2.push_back((int32_t)v2.size());
+            r2.push_back(hs_rhs[t]);
+            i2.push_back(hs_inv[t]);
+            if (q + 1 == H || color[order[q + 1]] != color[t]) hs_cstart.push_back(q + 1);
+        }
+        hs_ptr.swap(p2);
+        hs_var.swap(v2);
+        hs_coef.swap(c2);
+        hs_rhs.swap(r2);
+        hs_inv.swap(i2);
+    }
+
     h->n_box_units = h_box_units;
+    h->n_hs_colors = (int)hs_cstart.size() - 1;
     h->n_big = (int)big_pos.size();
     h->n_hs = (int)hs_rhs.size();
     h->hs_nnz = (int)hs_var.size();
@@ -623,6 +674,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.hs_coef, hs_coef, "half-space coefficients");
     if (!rc) rc = U.put(&h->d.hs_rhs, hs_rhs, "half-space rhs");
     if (!rc) rc = U.put(&h->d.hs_inv, hs_inv, "half-space norms");
+    if (!rc) rc = U.put(&h->d.hs_cstart, hs_cstart, "half-space colour classes");
     (void)hipSetDevice(prev);
     if (rc) {
         release(h);
@@ -663,6 +715,7 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->max_nodes = h->max_nodes;
     s->max_slots = h->max_slots;
     s->n_big = h->n_big;
+    s->n_hs_colors = h->n_hs_colors;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

@@ -94,6 +94,21 @@ def test_big_diagrams_random_hybrid(n, R):
         _compare(p, a, b, kap, w=np.random.default_rng(n).uniform(0.5, 2, (R, p.n_cons)))
 
 
+@pytest.mark.parametrize("n,R", [(100, 1), (100, 6), (200, 3)])
+def test_big_diagrams_inline_records(n, R):
+    """Random hybrid instances with float32 right-hand sides: every atom has an inline
+    record, so the level kernel reads the records instead of the CSR atom table."""
+    import dataclasses
+    p = W.make_random_hybrid(n)
+    p = dataclasses.replace(p, atom_rhs=p.atom_rhs.astype(np.float32).astype(np.float64))
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"random hybrid inline n={n} R={R} big={info['n_big']}", flush=True)
+    assert info["n_big"] == p.n_cons
+    a, b = W.initial_points(p, R, 16, n)
+    for kap in (0.7, 5.0):
+        _compare(p, a, b, kap, w=np.random.default_rng(n).uniform(0.5, 2, (R, p.n_cons)))
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 @pytest.mark.parametrize("R", [1, 7, 70])
 def test_mixed_small_and_big_diagrams(seed, R):
@@ -418,8 +433,8 @@ def _paper_instance(fam, A, B, k=0):
     return make_paper_placement(A, B, W.seed_seq(9, A, B, k))
 
 
-@pytest.mark.parametrize("fam,A,B", [("sched", 16, 2), ("sched", 32, 2), ("sched", 8, 5), ("place", 2, 2),
-                                     ("place", 4, 4), ("place", 8, 8)])
+@pytest.mark.parametrize("fam,A,B", [("sched", 16, 2), ("sched", 32, 2), ("sched", 8, 5), ("sched", 64, 2),
+                                     ("place", 2, 2), ("place", 4, 4), ("place", 8, 4), ("place", 8, 8)])
 @pytest.mark.parametrize("R", [1, 5, 16])
 def test_paper_suite_cop_parity(fam, A, B, R):
     p = _paper_instance(fam, A, B)
@@ -434,18 +449,56 @@ def test_paper_suite_cop_parity(fam, A, B, R):
         _compare(p, a, b, kap, w=w)
 
 
-@pytest.mark.parametrize("R", [1, 3])
-def test_paper_placement_big_diagrams(R):
-    """32 macros x 8 layers: 8 index bits per module pair, 28-node diagrams beyond the
-    per-lane message bound, so every non-overlap constraint takes the level kernel."""
+@pytest.mark.parametrize("R,kap", [(1, 2.0), (2, 20.0)])
+def test_paper_placement_large_register_store(R, kap):
+    """32 macros x 8 layers: 8 index bits per module pair, 28-node / 20-slot diagrams in the
+    largest register store (one lane per constraint), and with LDS messages forced in LDS
+    columns (36 KB per wavefront). Both against one oracle evaluation (about 30 s per
+    restart on one core)."""
     p = _paper_instance("place", 32, 8)
     info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
-    print(f"paper placement 32x8 R={R} cons={p.n_cons} big={info['n_big']}", flush=True)
-    assert info["n_big"] == p.meta["n_pairs"]
+    lds = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY, messages=1))
+    print(f"paper placement 32x8 R={R} cons={p.n_cons} nodes={info['max_nodes']} big={info['n_big']}", flush=True)
+    assert info["max_nodes"] == 28 and info["n_big"] == 0 and lds["n_big"] == 0
     a, b = W.initial_points(p, R, 12, R)
     a[0], b[0] = 0.8 * p.cert_x, p.cert_y
-    for kap in (2.0, 20.0):
-        _compare(p, a, b, kap)
+    o = oracle.objective(p, a, b, kap)
+    for messages in ("auto", "lds"):
+        h = fsmt.xbdd_compile(p, messages=MSG[messages])
+        g = _run_cop(p, h, a, b, kap)
+        assert_objective(g["U_fwd"], o["U"], p.n_cons)
+        assert_objective(g["U"], o["U"], p.n_cons)
+        assert_unsat(g["unsat"], o["unsat"])
+        assert_gradient(g["grad_a"], o["grad_a"], o["absg_a"], "grad_a")
+        assert_gradient(g["grad_b"], o["grad_b"], o["absg_b"], "grad_b")
+        h.free()
+
+
+def test_paper_placement_64x8_sampled():
+    """64 macros x 8 layers (410,304 constraints, 31-node / 22-slot diagrams beyond the
+    register bounds: one lane per constraint with LDS message columns). The full oracle is
+    too slow here, so sampled constraints are checked one by one against the oracle's
+    per-constraint probability at the same literal probabilities, and the objective against
+    the sum of the per-constraint values."""
+    p = _paper_instance("place", 64, 8)
+    h = fsmt.xbdd_compile(p)
+    info = fsmt.xbdd_info(h)
+    print(f"paper placement 64x8 cons={p.n_cons} big={info['n_big']}", flush=True)
+    assert info["max_nodes"] == 31 and info["n_big"] == 0
+    R, kap = 2, 10.0
+    a, b = W.initial_points(p, R, 14, 2)
+    a[0], b[0] = 0.8 * p.cert_x, p.cert_y
+    g = _run_cop(p, h, a, b, kap)
+    rng = np.random.default_rng(3)
+    sample = np.concatenate([rng.choice(p.meta["n_routing"] * 7, 8, replace=False),
+                             p.n_cons - 1 - rng.choice(p.n_cons // 2, 24, replace=False)])
+    for r in range(R):
+        pv = oracle.variable_probs(p, a[r], b[r], kap)
+        ref = np.array([oracle.cop_one(p, int(c), pv)[1] for c in sample])
+        assert_unsat(g["unsat"][r, sample], ref)
+        assert abs(g["U"][r] - g["unsat"][r].astype(np.float64).sum()) <= 1e-5 * g["U"][r] + 1e-6 * p.n_cons
+    assert np.all(np.isfinite(g["grad_a"])) and np.all(np.isfinite(g["grad_b"]))
+    h.free()
 
 
 @pytest.mark.parametrize("fam,A,B", [("sched", 16, 2), ("sched", 32, 3), ("place", 4, 8), ("place", 32, 8)])

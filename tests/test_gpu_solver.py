@@ -98,7 +98,8 @@ def _paper_instance(fam, A, B, k=0):
 
 
 @pytest.mark.parametrize("fam,A,B,schedule", [("sched", 16, 2, 1), ("sched", 16, 2, 2), ("sched", 32, 3, 2),
-                                              ("place", 4, 4, 1), ("place", 4, 4, 2), ("place", 32, 8, 2)])
+                                              ("sched", 64, 2, 1), ("sched", 64, 2, 2), ("place", 4, 4, 1),
+                                              ("place", 4, 4, 2), ("place", 32, 8, 1), ("place", 32, 8, 2)])
 def test_fused_step_paper_suite(fam, A, B, schedule):
     """One fused step on the paper's encodings (unit-atom projection: precedences, routing
     adjacency and module bounds are projected onto)."""
@@ -106,7 +107,8 @@ def test_fused_step_paper_suite(fam, A, B, schedule):
     ell = p.meta.get("mean_duration", p.meta.get("mean_side"))
     kap, eta_b = 2.0 / ell, 0.2 * ell * ell
     print(f"fused step paper {fam} {A}x{B} schedule {schedule}", flush=True)
-    h, a0, b0, st = _one_step(p, 4, kap, 0.5, eta_b, A * 10 + B, schedule)
+    R = 1 if p.n_cons > 50000 else 4            # the oracle takes ~30 s per restart at 32 x 8
+    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, A * 10 + B, schedule)
     _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
 
 

@@ -124,7 +124,15 @@ def test_scheduling_feasibility_windows():
         j, w = q // nw, q % nw
         lits = _lits(p, nd + P + q)
         dw = _atom(p, lits[-2] >> 1)[3]
-        assert _atom(p, lits[-1] >> 1)[3] == pytest.approx(dw + T - t[j], abs=1e-12)
+        assert _atom(p, lits[-1] >> 1)[3] == pytest.approx(dw + T - t[j], abs=4e-7)
+
+
+@pytest.mark.parametrize("make", [lambda: sched(16, 3), lambda: place(4, 8)])
+def test_constants_are_float32(make):
+    """Atom coefficients and right-hand sides are float32 values (exact device records)."""
+    p = make()
+    for x in (p.atom_coef, p.atom_rhs):
+        np.testing.assert_array_equal(x.astype(np.float32).astype(np.float64), x)
 
 
 def test_placement_constraints_are_the_methods_formulas():
@@ -207,3 +215,44 @@ def test_placement_diagram_sizes(nm, nl):
     c = int(np.nonzero(p.con_kind == KIND_EXPR)[0][0])
     d = fsmt.xbdd_export_diagram(h, c)
     assert (d["n_nodes"], d["n_slots"], d["n_bslots"]) == (3 * nb + 4, 2 * nb + 4, 2 * nb)
+
+
+def test_big_diagram_threshold():
+    """One lane per constraint up to 40 KB of LDS message columns per wavefront
+    ((2 (nodes + 2) + 4 slots) x 64 lanes x 4 bytes), in registers or LDS: the 28-node
+    placement pair diagrams either way, and clauses of up to 26 distinct atoms (n nodes,
+    n slots); a clause of 27 atoms (41.5 KB) is big (level kernel)."""
+    from workloads.format import BlockBuilder
+    host = fsmt.FSMT_HOST_ONLY
+    p = place(32, 8)
+    for messages in (0, 1):
+        assert fsmt.xbdd_info(fsmt.xbdd_compile(p, device=host, messages=messages))["n_big"] == 0
+    rng = np.random.default_rng(9)
+    for L, big in ((26, False), (27, True)):
+        bb = BlockBuilder(0, 6, -1.0, 1.0)
+        ids = bb.atoms(rng.integers(0, 6, (40, 2)), [1.0, -1.0], OP_LE, np.float32(0.25))
+        bb.constraints(KIND_CLAUSE, 2 * np.stack([rng.choice(ids, L, replace=False) for _ in range(3)]))
+        info = fsmt.xbdd_info(fsmt.xbdd_compile(bb.build(), device=host))
+        assert info["max_nodes"] == L and info["n_big"] == (3 if big else 0)
+
+
+@pytest.mark.parametrize("make", [lambda: place(16, 4), lambda: sched(32, 3, dep_prob=0.6)])
+def test_halfspace_colour_classes(make):
+    """Half-spaces (two-variable unit atoms: routing adjacency, dependencies) are split into
+    colour classes whose members share no variable; greedy colouring uses at least the
+    largest variable degree and at most one more than the largest conflict count."""
+    from collections import Counter
+    p = make()
+    hs = []
+    for c in range(p.n_cons):
+        lits = _lits(p, c)
+        if p.con_kind[c] == KIND_CLAUSE and len(lits) == 1 and (lits[0] >> 1) >= p.n_bool:
+            v = _atom(p, lits[0] >> 1)[0]
+            if len(v) > 1:
+                hs.append(v)
+    deg = Counter(j for v in hs for j in v)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    assert info["n_halfspaces"] == len(hs) > 0
+    lo = max(deg.values())
+    hi = 1 + max(sum(deg[j] - 1 for j in v) for v in hs)
+    assert lo <= info["n_hs_colors"] <= hi

@@ -12,6 +12,9 @@ support of a pair constraint interleaves the two items' bits (x_0j, x_0j', x_1j,
 ...). The diagram of "some bit differs, or an atom holds" is then a chain of three nodes
 per bit followed by the atoms, instead of a tree over all bits of the first item.
 
+Every constant of an instance (durations, start offsets, sizes and the right-hand sides
+built from them) is a float32 value, so the device keeps atoms as exact float32 records.
+
 Truth convention of the package: a Boolean's value -1 is True, so bit value 1 is a = -1.
 """
 from __future__ import annotations
@@ -54,6 +57,11 @@ def index_differs_program(n_bits: int, n_tail: int, tail_and: bool = False):
     return prog
 
 
+def _f32(x):
+    """Round instance constants to float32 values (kept as float64 arrays)."""
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
 def _bits_of(values, n_bits: int) -> np.ndarray:
     """[len(values), n_bits] 0/1 array of the binary digits (bit 0 first)."""
     v = np.asarray(values, np.int64)
@@ -91,8 +99,8 @@ def make_paper_scheduling(n_workers: int, ratio: int, seed_seq, dep_prob: float 
         raise ValueError("ratio must be >= 1")
     rng = np.random.Generator(np.random.PCG64(seed_seq))
     nw, nj = n_workers, ratio * n_workers
-    d = rng.uniform(0.0, 1.0, nw)
-    t = rng.uniform(0.0, 1.0, nj)
+    d = _f32(rng.uniform(0.0, 1.0, nw))
+    t = _f32(rng.uniform(0.0, 1.0, nj))
     order = rng.permutation(nj)
     deps = []                                   # (pred, succ)
     for k in range(1, nj):
@@ -130,7 +138,7 @@ def make_paper_scheduling(n_workers: int, ratio: int, seed_seq, dep_prob: float 
         fj = np.repeat(np.arange(nj), nw)
         fw = np.tile(np.arange(nw), nj)
         C = bb.atoms(fj, [1.0], OP_GE, d[fw])
-        D = bb.atoms(fj, [1.0], OP_LE, d[fw] + T - t[fj])
+        D = bb.atoms(fj, [1.0], OP_LE, _f32(d[fw] + T - t[fj]))
         wb = _bits_of(fw, L)
         # "bit i of job j differs from bit i of w": x_ij if w's bit is 0, not x_ij if it is 1
         blits = np.stack([_bits_lit(xid(i, fj), wb[:, i]) for i in range(L)], 1)
@@ -185,6 +193,7 @@ def make_paper_placement(n_macros: int, n_layers: int, seed_seq) -> Problem:
     along_x = rng.random(n_sm) < 0.5
     w[o_sm:] = np.where(along_x, 0.1, 0.05)
     h[o_sm:] = np.where(along_x, 0.05, 0.1)
+    w, h = _f32(w), _f32(h)
 
     mid = lambda i, j: i * N + np.asarray(j, np.int64)            # noqa: E731
     lid = lambda i, j: (Lm + i) * N + np.asarray(j, np.int64)     # noqa: E731
@@ -219,7 +228,7 @@ def make_paper_placement(n_macros: int, n_layers: int, seed_seq) -> Problem:
     j = np.arange(N)
     for V, size in ((X, w), (Y, h)):
         bb.constraints(KIND_CLAUSE, _bits_lit(bb.atoms(V(j), [1.0], OP_GE, 0.0))[:, None])
-        bb.constraints(KIND_CLAUSE, _bits_lit(bb.atoms(V(j), [1.0], OP_LE, 1.0 - size))[:, None])
+        bb.constraints(KIND_CLAUSE, _bits_lit(bb.atoms(V(j), [1.0], OP_LE, _f32(1.0 - size)))[:, None])
 
     p = bb.build(meta=dict(family="paper_placement", n_macros=nm, n_layers=nl, n_modules=N,
                            n_macro_bits=Lm, n_layer_bits=Ll, n_pairs=int(jj.shape[0]),
