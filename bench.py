@@ -16,12 +16,20 @@ public; the generator is in workloads/scheduling.py).
   same hyperparameters, median and PAR-2 over instance seeds.
 * roofline: the solver kernel's duration from HIP events on its stream; algorithmic
   FLOP and byte counts per launch (model in the design doc).
-* cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread).
+* cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread);
+  cpu_baseline_all_cores: the same on up to 16 host threads.
 * paper_protocol: the paper's gradient-timing protocol (Supplementary Note "Gradient
   Computation Time"): random hybrid instances with n Booleans, n reals and n atoms, 100
   annealing parameters x 100 points, one cop_backward call (objective + gradient) per
   parameter; reported next to the paper's L40S figure as context (other hardware, other
-  instances of the same shape).
+  instances of the same shape); also on the scheduling instance above.
+
+Other modes (each prints its own JSON line instead of the main one):
+
+* --suite scheduling|placement: PAR-2 of the fused solver on the paper's own encodings
+  (Booleanized worker / macro / layer indices, XOR disjunctions; workloads/paper_suite.py).
+* --scale-mode: fixed-work fused-solver throughput at the largest sizes of those suites.
+* --pmc-mode, --percall-mode: short runs for hardware-counter collection.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-tts]
 """
@@ -54,7 +62,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-SAT comparison")
     ap.add_argument("--no-protocol", action="store_true", help="skip the paper's gradient-timing protocol")
-    ap.add_argument("--tts-seeds", type=int, default=5)
+    ap.add_argument("--tts-seeds", type=int, default=10)
     ap.add_argument("--tts-cap", type=float, default=30.0, help="time limit per instance (s)")
     ap.add_argument("--percall-mode", action="store_true",
                     help="profiling aid: per-call forward + reverse sweeps on placement with 1,200 "
@@ -220,6 +228,7 @@ def main():
         out["paper_protocol"] = paper_protocol(fsmt, W, st)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a0, b0, kappas[0])
+        out["cpu_baseline_all_cores"] = cpu_baseline(p, a0, b0, kappas[0], threads=min(16, os.cpu_count() or 1))
     print(json.dumps(out))
 
 
@@ -332,8 +341,30 @@ def paper_protocol(fsmt, W, st, ns=(100, 500, 1000)):
         info = fsmt.xbdd_info(h)
         rows[str(n)] = {"n_cons": p.n_cons, "max_nodes": info["max_nodes"], "ms_per_call_100_points": dt * 10,
                         "us_per_point": dt / 10000 * 1e6, "paper_L40S_ms_per_gradient": PAPER_L40S_MS.get(n)}
+    # the same protocol on the benchmark's scheduling instance (200 jobs on 10 machines)
+    p = W.make_config(2)
+    h = fsmt.xbdd_compile(p)
+    a0, b0 = W.initial_points(p, 100, 2, 7)
+    a, b = torch.as_tensor(a0, device=dev), torch.as_tensor(b0, device=dev)
+    ga, gb = torch.zeros_like(a), torch.zeros_like(b)
+    w = torch.ones(p.n_cons, device=dev)
+    obj = torch.zeros(100, device=dev)
+    ell = p.meta["mean_duration"]
+    kaps = [0.01 * t / ell for t in range(100)]
+    for k in kaps[:3]:
+        fsmt.cop_backward(h, a, b, k, w, obj, ga, gb, stream=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in kaps:
+        fsmt.cop_backward(h, a, b, k, w, obj, ga, gb, stream=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rows["scheduling 200x10"] = {"n_cons": p.n_cons, "max_nodes": fsmt.xbdd_info(h)["max_nodes"],
+                                 "ms_per_call_100_points": dt * 10, "us_per_point": dt / 10000 * 1e6,
+                                 "paper_L40S_ms_per_gradient": None}
     return {"workload": "random hybrid (n Booleans, n reals, n atoms; n/5 CARD and NAE of length "
-                        "min(50, n/5), n/50 XOR of length 50), 100 kappa x 100 points, FP32",
+                        "min(50, n/5), n/50 XOR of length 50), 100 kappa x 100 points, FP32; and the "
+                        "scheduling instance of the main line (kappa 0 .. 0.99 / mean duration)",
             "per_n": rows,
             "note": "the paper does not say whether its figure is per point or per 100-point call; "
                     "its hardware and instances differ (context, not a target)"}
@@ -425,21 +456,33 @@ def paper_scale(args, fsmt, S):
     return {"scale_mode": True, "per_instance": out}
 
 
-def cpu_baseline(p, a0, b0, kap):
-    """The FP64 oracle, single-threaded, on a sample of the same workload (~10 s)."""
+def cpu_baseline(p, a0, b0, kap, threads: int = 1):
+    """The FP64 oracle on a sample of the same workload (~10 s): one restart point per call,
+    cycling over the restarts, on ``threads`` threads (the oracle's C calls release the
+    interpreter lock and keep no shared state)."""
+    import threading
     import oracle
     op = oracle.OracleProblem(p)
     R = a0.shape[0]
+    counts = [0] * threads
     t0 = time.perf_counter()
-    done = 0
-    while time.perf_counter() - t0 < 10.0:
-        r = done % R
-        oracle.objective(op, a0[r:r + 1], b0[r:r + 1], kap, per_constraint=False)
-        done += 1
+
+    def work(i):
+        while time.perf_counter() - t0 < 10.0:
+            r = (counts[i] * threads + i) % R
+            oracle.objective(op, a0[r:r + 1], b0[r:r + 1], kap, per_constraint=False)
+            counts[i] += 1
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
     dt = time.perf_counter() - t0
-    return {"value": p.n_cons * done / dt, "unit": "constraint-evals/s", "cores": 1, "kind": "oracle",
+    done = sum(counts)
+    return {"value": p.n_cons * done / dt, "unit": "constraint-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"objective + gradient of all {p.n_cons} constraints at {done} restart points "
-                      f"(cycling over the 64), FP64, one thread, ~10 s"}
+                      f"(cycling over the {R}), FP64, {threads} thread{'s' if threads > 1 else ''}, ~10 s"}
 
 
 if __name__ == "__main__":
