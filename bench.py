@@ -77,6 +77,10 @@ def parse():
     ap.add_argument("--per-cell", type=int, default=3, help="instances per cell (the paper has 10)")
     ap.add_argument("--limit", type=float, default=30.0, help="PAR-2 time limit per instance (s)")
     ap.add_argument("--suite-restarts", type=int, default=64)
+    ap.add_argument("--configs-mode", action="store_true",
+                    help="fixed-work fused-solver throughput on placement 150 x 256 restarts, the "
+                         "uneven 48-instance batch and placement 1,200 x 16 restarts, and time-to-SAT "
+                         "on placement 150")
     ap.add_argument("--scale-mode", action="store_true",
                     help="fixed-work solver throughput on the paper's largest encodings "
                          "(scheduling 256 workers x 5, placement 64 macros x 8 layers)")
@@ -133,6 +137,9 @@ def main():
         return
     if args.scale_mode:
         print(json.dumps(paper_scale(args, fsmt, S)))
+        return
+    if args.configs_mode:
+        print(json.dumps(other_configs(args, fsmt, S)))
         return
     p = W.make_config(2)
     R = W.RESTARTS[2]
@@ -224,6 +231,7 @@ def main():
     }
     if not args.no_tts:
         out["time_to_sat"] = time_to_sat(args, fsmt, S, W, st)
+        out["time_to_sat_index_encoding"] = time_to_sat_hard(args, fsmt, S, W, st)
     if not args.no_protocol:
         out["paper_protocol"] = paper_protocol(fsmt, W, st)
     if not args.no_cpu_baseline:
@@ -308,6 +316,51 @@ def time_to_sat(args, fsmt, S, W, st):
             "hyperparameters": {"levels": LEVELS, "kappa": "4 t / (40 mean duration)",
                                 "steps_per_level": STEPS_PER_LEVEL, "eta_a": ETA_A, "eta_b": ETA_B,
                                 "eps": EPS, "rho": 0.5, "gamma": 2.0, "tau": 1}}
+
+
+def time_to_sat_hard(args, fsmt, S, W, st, cap=15.0):
+    """Batched (64 restarts per fused launch) vs plain (one restart at a time, per-call
+    launches) time-to-SAT on the paper's scheduling encoding, 16 workers x 32 jobs, where a
+    single restart rarely succeeds (two instances the batched path solves)."""
+    import torch
+    from workloads.paper_suite import make_paper_scheduling
+    res = {"batched_s": [], "plain_s": [], "batched_restarts": [], "plain_restarts": []}
+    for k in (0, 1):
+        p = make_paper_scheduling(16, 2, W.seed_seq(8, 16, 2, k))
+        t0 = time.perf_counter()
+        h = fsmt.xbdd_compile(p)
+        cfg = _suite_cfg(S, p)
+        tb, att = None, 0
+        while time.perf_counter() - t0 < cap:
+            state = S.BatchState(h, *W.initial_points(p, 64, 55, 16, 2, k, att))
+            S.solve_batched([h], [state], cfg, stream=st)
+            torch.cuda.synchronize()
+            att += 1
+            if state.verdict.cpu().numpy().max() == 1:
+                tb = time.perf_counter() - t0
+                break
+        res["batched_s"].append(tb)
+        res["batched_restarts"].append(64 * att)
+        plain = S.PlainSolver(h, R=1)
+        t0 = time.perf_counter()
+        tp, r = None, 0
+        while time.perf_counter() - t0 < cap:
+            out = plain.run(*W.initial_points(p, 1, 56, 16, 2, k, r), cfg, stream=st)
+            torch.cuda.synchronize()
+            r += 1
+            if out["verdict"] == 1:
+                tp = time.perf_counter() - t0
+                break
+        res["plain_s"].append(tp)
+        res["plain_restarts"].append(r)
+        h.free()
+    sc = lambda ts: [t if t is not None else 2 * cap for t in ts]  # noqa: E731
+    return {"workload": "paper's scheduling encoding, 16 workers x 32 jobs (instances 0 and 1)",
+            "cap_s": cap, "batched_par2_s": float(np.mean(sc(res["batched_s"]))),
+            "plain_par2_s": float(np.mean(sc(res["plain_s"]))),
+            "batched_solved": sum(t is not None for t in res["batched_s"]),
+            "plain_solved": sum(t is not None for t in res["plain_s"]), "per_instance": res,
+            "hyperparameters": SUITE_HP}
 
 
 # mean GPU ms per gradient call reported by the paper for its random hybrid instances
@@ -422,6 +475,64 @@ def paper_suite(args, S):
             "restarts": R, "cells": rows, "hyperparameters": SUITE_HP, "n_gpus": 1, "data": "synthetic",
             "note": "wall time per instance includes diagram compilation and upload; the paper's "
                     "limit is 1000 s on its own instances and hardware"}
+
+
+def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20):
+    """One warm-up and one timed fused call of ``levels`` x ``steps`` PGD iterations."""
+    import torch
+    import workloads as W
+    hs = [fsmt.xbdd_compile(p) for p in probs]
+    init = [W.initial_points(p, R, *keys, i) for i, p in enumerate(probs)]
+    ell = [p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)) for p in probs]
+    cfg = S.SolveConfig(kappas=S.kappa_schedule(min(ell), levels), steps_per_level=steps, eta_a=ETA_A,
+                        eta_b=ETA_B, eps=0.0, stop_on_sat=0)
+    for _ in range(2):
+        states = [S.BatchState(h, a, b) for h, (a, b) in zip(hs, init)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.solve_batched(hs, states, cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    it = levels * steps
+    evals = sum(p.n_cons for p in probs) * R * it
+    for h in hs:
+        h.free()
+    return {"instances": len(probs), "n_cons_total": int(sum(p.n_cons for p in probs)), "restarts": R,
+            "pgd_steps": it, "ms_per_pgd_step": dt / it * 1e3, "constraint_evals_per_s": evals / dt,
+            "includes": "one fused call: sweeps, projections, one check + ERWA"}
+
+
+def other_configs(args, fsmt, S):
+    """Rates of the fused solver on the other workloads, and time-to-SAT on placement 150."""
+    import torch
+    import workloads as W
+    out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_config(3)], 256, (3, 0)),
+           "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0)),
+           "placement 1200 x 16 restarts": _fixed_work(fsmt, S, [W.make_config(5)], 16, (5, 0), steps=10)}
+    # time to SAT with the paper-encoding hyperparameters (eta_b scaled by the side length)
+    cap = min(args.tts_cap, 10.0)
+    ts = []
+    for seed in range(3):
+        p = W.make_config(3, seed)
+        h = fsmt.xbdd_compile(p)
+        cfg = _suite_cfg(S, p)
+        t0, done, att = time.perf_counter(), None, 0
+        while time.perf_counter() - t0 < cap:
+            st = S.BatchState(h, *W.initial_points(p, 256, 3, seed, 100 + att))
+            S.solve_batched([h], [st], cfg)
+            torch.cuda.synchronize()
+            if st.verdict.cpu().numpy().max() == 1:
+                done = time.perf_counter() - t0
+                break
+            att += 1
+        ts.append(done)
+        h.free()
+    sc = [t if t is not None else 2 * cap for t in ts]
+    out["time_to_sat placement 150, 256 restarts"] = {
+        "instances": len(ts), "solved": sum(t is not None for t in ts), "cap_s": cap,
+        "median_s": float(statistics.median(sc)), "par2_s": float(np.mean(sc)), "per_instance_s": ts,
+        "hyperparameters": SUITE_HP}
+    return {"configs_mode": True, **out}
 
 
 def paper_scale(args, fsmt, S):
