@@ -368,3 +368,33 @@ def test_cluster_split_agrees_with_single_workgroup_over_levels():
     np.testing.assert_array_equal(A.level_done.cpu().numpy(), B.level_done.cpu().numpy())
     np.testing.assert_array_equal(A.steps_done.cpu().numpy(), B.steps_done.cpu().numpy())
     assert B.verdict.cpu().numpy().min() >= 0        # no barrier abort
+
+
+def test_unsat_instance_returns_unknown():
+    """A planted contradiction (x and not x) beside satisfiable constraints: the fused solver
+    runs every level and reports no SAT, the plain path too, and the PAR-2 harness scores the
+    instance at twice its limit after restarting from new seeds."""
+    from workloads.format import KIND_CLAUSE, Builder, lit
+    from paper_2603_22877_amd import par2 as P2
+    b = Builder(n_bool=3, n_real=2, real_lo=[-1.0, -1.0], real_hi=[1.0, 1.0])
+    y0 = b.atom([0, 1], [1.0, -1.0], 0, 0.25)
+    b.add(KIND_CLAUSE, [lit(0)])
+    b.add(KIND_CLAUSE, [lit(0, neg=True)])
+    b.add(KIND_CLAUSE, [lit(1), lit(y0)])
+    b.add(KIND_CLAUSE, [lit(2, neg=True), lit(y0, neg=True)])
+    p = b.build()
+    h = fsmt.xbdd_compile(p)
+    R, levels = 8, 4
+    cfg = S.SolveConfig(kappas=S.kappa_schedule(0.5, levels), steps_per_level=20, eta_a=0.5, eta_b=0.1,
+                        eps=1e-2, stop_on_sat=2)
+    st = S.BatchState(h, *W.initial_points(p, R, 70, 0))
+    S.solve_batched([h], [st], cfg)
+    torch.cuda.synchronize()
+    assert np.all(st.verdict.cpu().numpy() == 0)
+    assert np.all(st.level_done.cpu().numpy() == levels)
+    assert np.all(st.n_unsat.cpu().numpy() >= 1)
+    out = S.PlainSolver(h, R=1).run(*W.initial_points(p, 1, 70, 1), cfg)
+    assert out["verdict"] == 0 and out["level"] == levels
+    r = P2.run_instance(p, cfg, 4, 0.3, lambda q, R_, att: W.initial_points(q, R_, 71, att), name="unsat")
+    assert not r.solved and r.attempts >= 1 and r.best_unsat >= 1
+    assert r.score(0.3) == 0.6 and P2.par2([r], 0.3) == 0.6

@@ -256,3 +256,13 @@ def test_halfspace_colour_classes(make):
     lo = max(deg.values())
     hi = 1 + max(sum(deg[j] - 1 for j in v) for v in hs)
     assert lo <= info["n_hs_colors"] <= hi
+
+
+def test_par2_scoring():
+    """PAR-2: the wall time when solved within the limit, twice the limit otherwise."""
+    from paper_2603_22877_amd.par2 import InstanceResult, par2
+    rs = [InstanceResult("a", True, 1.5, 0.1, 1, 3, 0, 10), InstanceResult("b", False, 20.0, 0.1, 4, 80, 2, 10),
+          InstanceResult("c", True, 25.0, 0.1, 9, 5, 0, 10)]
+    assert [r.score(20.0) for r in rs] == [1.5, 40.0, 40.0]
+    assert par2(rs, 20.0) == pytest.approx(81.5 / 3)
+    assert par2([], 20.0) == 0.0
