@@ -92,7 +92,9 @@ def make_paper_scheduling(n_workers: int, ratio: int, seed_seq, dep_prob: float 
     rounding to float32); the feasibility clause is read
     per worker, with the two bounds joined by AND (the paper prints it for one worker
     symbolically with an OR between the bounds, which would hold for any y_j). Start times
-    are boxed to [0, max_w d_w + T].
+    are boxed to the hull of the job's windows, [min_w d_w, max_w d_w + T - t_j]: bounds the
+    feasibility constraints imply, so the solutions are unchanged, while a start far beyond
+    every window (where the smoothed atoms have no gradient left) is cut off.
     """
     L = _log2(n_workers, "n_workers")
     if ratio < 1:
@@ -119,10 +121,13 @@ def make_paper_scheduling(n_workers: int, ratio: int, seed_seq, dep_prob: float 
         worker[j], y[j] = w, start[w]
         free[w] = start[w] + t[j] + gap
     T = float(np.max(free - d))
-    y_hi = float(d.max() + T)
+    # start-time box: the hull of the job's windows over all workers, which the feasibility
+    # constraints imply (whatever its worker, job j starts in [min_w d_w, max_w d_w + T - t_j])
+    y_lo = np.full(nj, float(d.min()))
+    y_hi = float(d.max()) + T - t
 
     xid = lambda i, j: i * nj + np.asarray(j, np.int64)  # noqa: E731
-    bb = BlockBuilder(L * nj, nj, 0.0, y_hi)
+    bb = BlockBuilder(L * nj, nj, y_lo, y_hi)
     if deps:
         dp = np.asarray(deps, np.int64)
         a = bb.atoms(np.stack([dp[:, 1], dp[:, 0]], 1), [1.0, -1.0], OP_GE, t[dp[:, 0]])
