@@ -358,13 +358,22 @@ using namespace fsmt;
 // schedule needs the restart's state in LDS and costs ceil(tasks / waves) sequential tasks
 // per step on one CU; the grid schedule spreads tasks x restarts over all CUs (about 8 waves
 // each) and pays two launches per step (about 20 task-times).
-static bool prefer_grid(const fsmt_xbdd *h, int R, int waves_a, int n_cu) {
+static bool prefer_grid(const fsmt_xbdd *h, int R, int64_t R_batch, int waves_a, int n_cu) {
+    // persistent: a restart's tasks over its cluster of k workgroups (k as chosen below, with
+    // every restart of the batch resident at once), plus the exchange of k partial
+    // gradients per step
     const double tasks_a = (double)h->n_pos / 64.0;                  // per restart, lane = constraint
-    const double t_a = std::ceil(tasks_a / std::max(1, waves_a));
+    const int wa = std::max(1, waves_a);
+    int k = 1;
+    while (k < 16 && tasks_a >= 2.0 * (2 * k) * wa && R_batch * 2 * k <= n_cu) k *= 2;
+    const double exchange = k > 1 ? 4.0 + (double)(h->n_bool + h->n_real) * k / (wa * 64.0 * 16.0) : 0.0;
+    const double t_a = std::ceil(tasks_a / (wa * k)) + exchange;
+    // grid: every (constraint, restart) lane over the device, as many waves per CU as the
+    // message store's registers allow, plus the launches of a step
     int rp = 1;
     while (rp < R && rp < 64) rp <<= 1;
     const double lanes = (double)h->n_pos * (R <= 64 ? rp : std::ceil(R / 64.0) * 64.0);
-    const double t_b = std::ceil(lanes / 64.0 / (8.0 * n_cu)) + 20.0;
+    const double t_b = std::ceil(lanes / 64.0 / ((double)wa * n_cu)) + 20.0;
     return t_b < t_a;
 }
 
@@ -414,6 +423,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     std::vector<char> use_grid(n_inst, 0);
+    int64_t r_batch = 0;
+    for (int i = 0; i < n_inst; ++i) r_batch += states[i].a.rows;
     for (int i = 0; i < n_inst; ++i) {
         const fsmt_xbdd *h = insts[i];
         const int mv = msg_variant(h->small_max_nodes, h->small_max_slots, h->lds_messages, h->all_inline);
@@ -428,7 +439,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         if (O.schedule == 1 && h->n_big > 0)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: %d big diagrams need the grid schedule", i, h->n_big);
         use_grid[i] = O.schedule == 2 || !fits || h->n_big > 0 ||
-                      (O.schedule == 0 && prefer_grid(h, states[i].a.rows, waves, n_cu));
+                      (O.schedule == 0 && prefer_grid(h, states[i].a.rows, r_batch, waves, n_cu));
     }
 
     hipStream_t st = (hipStream_t)stream;
@@ -737,7 +748,24 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                                                     : 0;
                 plan.check_blocks = checks;
                 plan.use_graph = true;
-                rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, O.n_levels, gst);
+                // replay only the levels some restart still has to run: a call that resumes a
+                // schedule (level_done > 0) would otherwise replay every finished level as
+                // launches with nothing to do
+                int first = O.n_levels;
+                for (size_t q = 0; q < ib.size() && !rc; ++q) {
+                    const fsmt_solve_state &St = states[ib[q]];
+                    const int R = St.a.rows;
+                    std::vector<int32_t> lv((size_t)R), vd((size_t)R);
+                    if (hipMemcpyAsync(lv.data(), St.level_done, sizeof(int32_t) * R, hipMemcpyDeviceToHost, gst) != hipSuccess ||
+                        hipMemcpyAsync(vd.data(), St.verdict, sizeof(int32_t) * R, hipMemcpyDeviceToHost, gst) != hipSuccess ||
+                        hipStreamSynchronize(gst) != hipSuccess) {
+                        rc = set_error(FSMT_EHIP, "reading level counters failed");
+                        break;
+                    }
+                    for (int r = 0; r < R; ++r)
+                        if (!(vd[r] == 1 && O.stop_on_sat != 0)) first = std::min(first, std::max(lv[r], 0));
+                }
+                if (!rc) rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, O.n_levels - first, gst);
             }
             (void)hipFreeAsync(buf, gst);
         }
