@@ -122,6 +122,8 @@ typedef struct {
                                   one wavefront per constraint and restart) */
     int32_t n_hs_colors;       /* colour classes of the half-spaces (members share no variable;
                                   the projection handles a class's members in parallel) */
+    int32_t n_pair;            /* constraints of the form OR_i (x_2i XOR x_2i+1) OR atoms, whose
+                                  forward and reverse sweeps run in closed form */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

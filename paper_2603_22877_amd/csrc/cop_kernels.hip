@@ -40,7 +40,7 @@ struct CopArgs {
     int32_t lds_nodes, lds_slots;  // per-wave LDS geometry (max over templates)
 };
 
-template <bool kGrad, int V>
+template <bool kGrad, int V, bool kPair>
 __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
         const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
         if (t.B.big) continue;   // evaluated by cop_level_kernel
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;   // requested before the forward pass
-        const float unsat = task_forward(A.T, t, st, A.kappa, A.hard != 0, W);
+        const float unsat = task_eval<kGrad, kPair>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         if (A.obj) {
             if (A.R_pad <= 64) {
@@ -77,7 +77,6 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
                 atomic_add_f32(A.obj + r, wc * unsat);
             }
         }
-        if (kGrad) task_backward(A.T, t, wc, sc, W, lane);
     }
     // objective: reduce lanes holding the same restart, one atomic per restart and wave
     if (A.obj && A.R_pad <= 64) {
@@ -297,6 +296,14 @@ static fsmt_status launch_status(const char *what) {
     return FSMT_OK;
 }
 
+template <bool kGrad, bool kPair>
+static void launch_cop(int msg, dim3 g, dim3 bl, size_t lds, hipStream_t st, const CopArgs &A) {
+    if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgSmall, kPair>), g, bl, 0, st, A);
+    else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgMedium, kPair>), g, bl, 0, st, A);
+    else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLarge, kPair>), g, bl, 0, st, A);
+    else hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLds, kPair>), g, bl, lds, st, A);
+}
+
 static int blocks_for(int64_t n, int threads, int cap = 4096) {
     int64_t b = (n + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -349,7 +356,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     // one lane per constraint for the small diagrams, one wavefront per (constraint,
     // restart) for the big ones
     const int NN = h->small_max_nodes + 2, SS = std::max(h->small_max_slots, 1);
-    const int msg = msg_variant(h->small_max_nodes, h->small_max_slots, h->lds_messages, h->all_inline);
+    const int msg = msg_variant(h->small_max_nodes, h->small_max_slots, lds_store(h), h->all_inline);
     const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(NN, SS) : 0;
     const int wpb = wave_bytes ? (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / wave_bytes)) : 4;
     const size_t level_wave_bytes = level_wave_floats(h->big_max_nodes, std::max(h->big_max_slots, 1)) * sizeof(float);
@@ -394,17 +401,11 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
     if (h->n_big < h->n_cons) {
-        if (grad) {
-            if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<true, kMsgSmall>), g, bl, 0, st, A);
-            else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<true, kMsgMedium>), g, bl, 0, st, A);
-            else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<true, kMsgLarge>), g, bl, 0, st, A);
-            else hipLaunchKernelGGL((cop_kernel<true, kMsgLds>), g, bl, lds, st, A);
-        } else {
-            if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<false, kMsgSmall>), g, bl, 0, st, A);
-            else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<false, kMsgMedium>), g, bl, 0, st, A);
-            else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<false, kMsgLarge>), g, bl, 0, st, A);
-            else hipLaunchKernelGGL((cop_kernel<false, kMsgLds>), g, bl, lds, st, A);
-        }
+        const bool pair = h->n_pair > 0;
+        if (grad)
+            pair ? launch_cop<true, true>(msg, g, bl, lds, st, A) : launch_cop<true, false>(msg, g, bl, lds, st, A);
+        else
+            pair ? launch_cop<false, true>(msg, g, bl, lds, st, A) : launch_cop<false, false>(msg, g, bl, lds, st, A);
         if ((rc = launch_status("cop kernel"))) return rc;
     }
     if (h->n_big > 0) {

@@ -476,6 +476,132 @@ __device__ __forceinline__ void task_backward(const TabView &T, const TaskCtx &t
     }
 }
 
+// ---- pair disjunctions: OR_i (x_{2i} XOR x_{2i+1}) OR a_0 OR ... OR a_{T-1} over the
+// Boolean slots 0..2L-1 and the atom slots 2L..2L+T-1 (L in the bucket record). The diagram
+// is a chain: one node for x_{2i} and two for x_{2i+1} per pair, then one node per atom; a
+// path ends at the false terminal only through the "equal" edges of every pair and the
+// "false" edge of every atom. The forward mass of the false terminal is therefore
+//   F = prod_i e_i * prod_t q_t,  e_i = p_{2i} p_{2i+1} + q_{2i} q_{2i+1},
+// and the reverse sweep's slot sensitivities are F with one factor left out (prefix and
+// suffix products): dF/dp_{2i} = (p_{2i+1} - q_{2i+1}) F / e_i, dF/dp_t = -F / q_t.
+// Forward and reverse run in one pass with every index known at compile time.
+__device__ __forceinline__ float pair_equal(float a0, float a1) {
+    const float p0 = (1.0f - a0) * 0.5f, q0 = (1.0f + a0) * 0.5f;
+    const float p1 = (1.0f - a1) * 0.5f, q1 = (1.0f + a1) * 0.5f;
+    return p0 * p1 + q0 * q1;
+}
+
+template <bool kInl, class St>
+__device__ __forceinline__ void pair_tail(const TabView &T, const TaskCtx &t, const St &st, int u, double kappa,
+                                          bool hard, AtomRec &a, float &q, float &d) {
+    const int64_t np = t.B.n_pos;
+    float p;
+    if (kInl || t.rec) {
+        a = load_rec(t.rec + (int64_t)u * np);
+        atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p, q, d);
+    } else {
+        const int k = t.sup[(int64_t)(t.B.n_bslots + u) * np] - T.n_bool;
+        atom_literal(atom_z_state(T, k, st, t.r), T.atom_scale[k], T.atom_strict[k] != 0, kappa, hard, p, q, d);
+    }
+}
+
+// P[c False] of a pair disjunction (0 for invalid lanes); with kGrad also scatters
+// wc * dF/d(state). Every lane reaches the scatter calls (uniform control flow).
+template <bool kGrad, bool kInl, class St, class Sc>
+__device__ __forceinline__ float pair_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
+                                           float wc, const Sc &sc, int lane) {
+    const int L = t.B.pad, NT = t.B.n_slots - 2 * L;
+    const int64_t np = t.B.n_pos;
+    float e[kPairMaxL], qt[kPairMaxT], dt[kPairMaxT];
+    float E = 1.0f, Q = 1.0f;
+#pragma unroll
+    for (int i = 0; i < kPairMaxL; ++i) {
+        e[i] = 1.0f;
+        if (i < L && t.valid)
+            e[i] = pair_equal(st.av(t.r, t.sup[(int64_t)(2 * i) * np]), st.av(t.r, t.sup[(int64_t)(2 * i + 1) * np]));
+        E *= e[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kPairMaxT; ++u) {
+        qt[u] = 1.0f;
+        dt[u] = 0.0f;
+        if (u < NT && t.valid) {
+            AtomRec a;
+            pair_tail<kInl>(T, t, st, u, kappa, hard, a, qt[u], dt[u]);
+        }
+        Q *= qt[u];
+    }
+    const float F = t.valid ? E * Q : 0.0f;
+    if constexpr (kGrad) {
+        // pairs: rest_i = prod_{j != i} e_j * Q; dF/da_{2i} = rest_i * a_{2i+1} / 2 (dp/da = -1/2)
+        float suf[kPairMaxL + 1];
+        suf[kPairMaxL] = Q;
+#pragma unroll
+        for (int i = kPairMaxL - 1; i >= 0; --i) suf[i] = suf[i + 1] * e[i];
+        float pre = t.valid ? wc : 0.0f;
+#pragma unroll
+        for (int i = 0; i < kPairMaxL; ++i) {
+            if (i < L) {
+                // the pair's values are read again (cached) instead of being kept in registers
+                const int i0 = t.valid ? t.sup[(int64_t)(2 * i) * np] : -1;
+                const int i1 = t.valid ? t.sup[(int64_t)(2 * i + 1) * np] : -1;
+                const float x0 = t.valid ? st.av(t.r, i0) : 0.0f, x1 = t.valid ? st.av(t.r, i1) : 0.0f;
+                const float rest = pre * suf[i + 1];
+                sc.add_a(t.r, i0, 0.5f * rest * x1, lane);
+                sc.add_a(t.r, i1, 0.5f * rest * x0, lane);
+            }
+            pre *= e[i];
+        }
+        // atoms: dF/dp_t = -E prod_{t' != t} q_t'; the b-gradient is that times dp/dz and q
+        float qs[kPairMaxT + 1];
+        qs[kPairMaxT] = 1.0f;
+#pragma unroll
+        for (int u = kPairMaxT - 1; u >= 0; --u) qs[u] = qs[u + 1] * qt[u];
+        float qp = t.valid ? -wc * E : 0.0f;
+        if (kInl || t.rec) {
+            // consecutive atoms on the same variables are summed before the scatter
+            int v0 = -1, v1 = -1;
+            float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+            for (int u = 0; u < kPairMaxT; ++u) {
+                if (u < NT) {
+                    AtomRec a;
+                    a.v0 = a.v1 = -1;
+                    a.c0 = a.c1 = 0.0f;
+                    a.flags = 0;
+                    if (t.valid) a = load_rec(t.rec + (int64_t)u * np);
+                    const float gz = qp * qs[u + 1] * dt[u];
+                    const bool n0 = a.v0 != v0, n1 = a.v1 != v1;
+                    sc.add_b(t.r, n0 ? v0 : -1, n0 ? g0 : 0.0f, lane);
+                    sc.add_b(t.r, n1 ? v1 : -1, n1 ? g1 : 0.0f, lane);
+                    if (n0) { v0 = a.v0; g0 = 0.0f; }
+                    if (n1) { v1 = a.v1; g1 = 0.0f; }
+                    g0 += gz * a.c0;
+                    if (a.flags & 2u) g1 += gz * a.c1;
+                }
+                qp *= qt[u];
+            }
+            sc.add_b(t.r, v0, g0, lane);
+            sc.add_b(t.r, v1, g1, lane);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kPairMaxT; ++u) {
+                const float gz = qp * qs[u + 1] * dt[u];
+                if (u < NT && t.valid && gz != 0.0f) {
+                    const int k = t.sup[(int64_t)(t.B.n_bslots + u) * np] - T.n_bool;
+                    for (int e2 = T.atom_ptr[k]; e2 < T.atom_ptr[k + 1]; ++e2)
+                        sc.add_b_direct(t.r, T.atom_var[e2], gz * (float)T.atom_coef[e2]);
+                }
+                qp *= qt[u];
+            }
+        }
+    }
+    return F;
+}
+
+// One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
+// scattered through the policy.
+
 // Message-store variants: a kernel is instantiated per variant and the host picks the
 // smallest whose bounds hold for every diagram of the launch.
 enum MsgVariant { kMsgLds = 0, kMsgSmall = 1, kMsgMedium = 2, kMsgLarge = 3 };
@@ -508,6 +634,33 @@ __device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, in
         W##_d[Ms::kArrSlots], W##_g[Ms::kArrSlots];                                                             \
     Ms W;                                                                                                       \
     bind_msgs(W, base, NN, SS, lane, W##_m, W##_b, W##_p, W##_q, W##_d, W##_g)
+
+// One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
+// scattered through the policy. Kernels are instantiated with kPair only for launches that
+// hold pair-disjunction templates (the closed-form path adds registers); there a register
+// store is declared per task, so its arrays are live only in the generic branch.
+template <bool kGrad, bool kPair, class St, class Sc, class Ms>
+__device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
+                                           float wc, const Sc &sc, Ms &W, int lane) {
+    if constexpr (kPair) {
+        if (t.B.pad > 0) return pair_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
+        if constexpr (Ms::kNodes > 0) {
+            FSMT_MSG_STORE(Ms, Wt, nullptr, 0, 0, lane);
+            const float unsat = task_forward(T, t, st, kappa, hard, Wt);
+            if constexpr (kGrad) task_backward(T, t, wc, sc, Wt, lane);
+            return unsat;
+        }
+    }
+    const float unsat = task_forward(T, t, st, kappa, hard, W);
+    if constexpr (kGrad) task_backward(T, t, wc, sc, W, lane);
+    return unsat;
+}
+
+// The LDS store is used when asked for, and for instances with pair-disjunction templates:
+// their kernels carry the closed-form path beside the generic one, and the generic
+// templates in LDS leave it the registers (scheduling 256 x 5: 4.2 ms per PGD step against
+// 5.4 ms with register stores; placement 64 x 8: 1.69 against 1.62 ms).
+inline bool lds_store(const fsmt_xbdd *h) { return h->lds_messages || h->n_pair > 0; }
 
 // Register variants need every atom in an inline record (the CSR path is compiled out).
 inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inline) {

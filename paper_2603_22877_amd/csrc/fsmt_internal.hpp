@@ -28,7 +28,7 @@ struct TplInfo {
     int32_t n_bslots;   // Boolean slots (slots [0, n_bslots) are Booleans)
     int32_t root;       // 0, or n_nodes / n_nodes+1 for constant constraints
     int32_t lev_off;    // level starts: lev[lev_off + s] = first node of slot s (s <= n_slots)
-    int32_t pad[2];
+    int32_t pad[2];     // pad[0]: pair count L of a pair disjunction, else 0
 };
 
 // A diagram is "big" when its per-lane message columns would take more than 40 KB of LDS
@@ -40,6 +40,10 @@ constexpr int64_t kBigDiagramBytes = 40960;
 // registers (two terminals and a spare), which must stay within one 32-register tuple
 // for indexed register access.
 constexpr int kLargeMaxNodes = 29, kLargeMaxSlots = 24;
+// Pair disjunctions OR_i (x_{2i} XOR x_{2i+1}) OR a_0 OR ... OR a_{T-1} (index bits that
+// differ, or one of T atoms) are evaluated in closed form (see pair_eval) up to these sizes;
+// their templates carry L in TplInfo::pad[0] / BucketInfo::pad (0: generic diagram).
+constexpr int kPairMaxL = 10, kPairMaxT = 4;
 inline bool big_diagram(int n_nodes, int n_slots) {
     const int64_t ss = n_slots > 1 ? n_slots : 1;
     return (2 * ((int64_t)n_nodes + 2) + 4 * ss) * 64 * 4 > kBigDiagramBytes;
@@ -118,6 +122,7 @@ struct fsmt_xbdd {
     int n_big = 0;                                  // constraints in big buckets
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
     int n_box_units = 0, n_hs = 0, hs_nnz = 0, n_hs_colors = 0;
+    int64_t n_pair = 0;               // constraints evaluated as pair disjunctions (closed form)
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record
     std::vector<fsmt::TplInfo> h_tpl;

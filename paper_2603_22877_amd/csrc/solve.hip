@@ -114,7 +114,7 @@ template <> struct SolveWaves<kMsgLarge> { static constexpr int value = 4; };
 
 // kCluster: k workgroups per restart (k read from the descriptor); otherwise k = 1 and the
 // kernel carries none of the cluster's exchange state.
-template <int V, bool kCluster>
+template <int V, bool kCluster, bool kPair>
 __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
     solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags, int32_t *abort_flag) {
     using Ms = typename MsgOf<V>::type;
@@ -176,9 +176,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
                 const float wc = t.valid ? wload(t.c) : 0.0f;   // requested before the forward pass
-                const float unsat = task_forward(T, t, st, kappa, hard, W);
-                oacc += wc * unsat;
-                task_backward(T, t, wc, sc, W, lane);
+                oacc += wc * task_eval<true, kPair>(T, t, st, kappa, hard, wc, sc, W, lane);
             }
             if (kCluster) {
                 // publish this workgroup's partial gradient and objective, then sum the
@@ -316,6 +314,22 @@ static fsmt_status launch_status(const char *what) {
     return FSMT_OK;
 }
 
+template <int V, bool kPair>
+static const void *solve_kernel_fn_v(bool cl) {
+    return cl ? (const void *)solve_wg_kernel<V, true, kPair> : (const void *)solve_wg_kernel<V, false, kPair>;
+}
+template <bool kPair>
+static const void *solve_kernel_fn_p(int msg, bool cl) {
+    if (msg == kMsgSmall) return solve_kernel_fn_v<kMsgSmall, kPair>(cl);
+    if (msg == kMsgMedium) return solve_kernel_fn_v<kMsgMedium, kPair>(cl);
+    if (msg == kMsgLarge) return solve_kernel_fn_v<kMsgLarge, kPair>(cl);
+    return solve_kernel_fn_v<kMsgLds, kPair>(cl);
+}
+// The persistent solver kernel for a message variant, cluster mode and pair-disjunction path.
+static const void *solve_kernel_fn(int msg, bool cl, bool pair) {
+    return pair ? solve_kernel_fn_p<true>(msg, cl) : solve_kernel_fn_p<false>(msg, cl);
+}
+
 static int lds_budget_bytes() {
     static int budget = -1;
     if (budget < 0) {
@@ -324,10 +338,10 @@ static int lds_budget_bytes() {
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > budget)
             budget = v;
-        const void *fns[] = {(const void *)solve_wg_kernel<kMsgLds, false>, (const void *)solve_wg_kernel<kMsgSmall, false>,
-                             (const void *)solve_wg_kernel<kMsgMedium, false>, (const void *)solve_wg_kernel<kMsgLds, true>,
-                             (const void *)solve_wg_kernel<kMsgSmall, true>, (const void *)solve_wg_kernel<kMsgMedium, true>,
-                             (const void *)solve_wg_kernel<kMsgLarge, false>, (const void *)solve_wg_kernel<kMsgLarge, true>};
+        std::vector<const void *> fns;
+        for (int msg : {kMsgLds, kMsgSmall, kMsgMedium, kMsgLarge})
+            for (int cl = 0; cl < 2; ++cl)
+                for (int pair = 0; pair < 2; ++pair) fns.push_back(solve_kernel_fn(msg, cl != 0, pair != 0));
         for (const void *f : fns) {
             if (budget > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
                 (void)hipGetLastError();
@@ -427,7 +441,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     for (int i = 0; i < n_inst; ++i) r_batch += states[i].a.rows;
     for (int i = 0; i < n_inst; ++i) {
         const fsmt_xbdd *h = insts[i];
-        const int mv = msg_variant(h->small_max_nodes, h->small_max_slots, h->lds_messages, h->all_inline);
+        const int mv = msg_variant(h->small_max_nodes, h->small_max_slots, lds_store(h), h->all_inline);
         const size_t wb = mv == kMsgLds ? WaveScratch::bytes(h->small_max_nodes + 2, std::max(h->small_max_slots, 1)) : 0;
         const size_t sb = state_floats_of(h) * sizeof(float);
         const bool fits = sb + wb <= budget;
@@ -488,7 +502,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         }
         bool lds_only = false, all_inline = true;
         for (size_t q = 0; q < ia.size(); ++q) {
-            lds_only = lds_only || insts[ia[q]]->lds_messages;
+            lds_only = lds_only || lds_store(insts[ia[q]]);
             all_inline = all_inline && insts[ia[q]]->all_inline;
         }
         const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
@@ -497,12 +511,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         const int waves = wave_bytes ? (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes) : solve_waves(msg);
         const size_t lds = state_bytes + (size_t)waves * wave_bytes;
         // the cluster kernels (k workgroups per restart) have their own resource use
-        auto kernel_of = [&](bool cl) -> const void * {
-            if (msg == kMsgSmall) return cl ? (const void *)solve_wg_kernel<kMsgSmall, true> : (const void *)solve_wg_kernel<kMsgSmall, false>;
-            if (msg == kMsgMedium) return cl ? (const void *)solve_wg_kernel<kMsgMedium, true> : (const void *)solve_wg_kernel<kMsgMedium, false>;
-            if (msg == kMsgLarge) return cl ? (const void *)solve_wg_kernel<kMsgLarge, true> : (const void *)solve_wg_kernel<kMsgLarge, false>;
-            return cl ? (const void *)solve_wg_kernel<kMsgLds, true> : (const void *)solve_wg_kernel<kMsgLds, false>;
-        };
+        bool pair = false;
+        for (size_t q = 0; q < ia.size(); ++q) pair = pair || insts[ia[q]]->n_pair > 0;
+        auto kernel_of = [&](bool cl) -> const void * { return solve_kernel_fn(msg, cl, pair); };
         auto resident_of = [&](bool cl) -> int64_t {
             int occ = 1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel_of(cl), 64 * waves, lds) != hipSuccess) {
@@ -585,23 +596,10 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             } else {
                 const dim3 g((unsigned)wg), b(64 * waves);
                 const InstDesc *d = (const InstDesc *)dbuf;
-                if (msg == kMsgSmall && k > 1)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgSmall, true>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (msg == kMsgSmall)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgSmall, false>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (msg == kMsgMedium && k > 1)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, true>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (msg == kMsgMedium)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgMedium, false>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (msg == kMsgLarge && k > 1)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLarge, true>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (msg == kMsgLarge)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLarge, false>), g, b, lds, st, d, P, flags, abort_flag);
-                else if (k > 1)
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLds, true>), g, b, lds, st, d, P, flags, abort_flag);
-                else
-                    hipLaunchKernelGGL((solve_wg_kernel<kMsgLds, false>), g, b, lds, st, d, P, flags, abort_flag);
-                rc = launch_status("solver kernel");
+                void *args[] = {(void *)&d, (void *)&P, (void *)&flags, (void *)&abort_flag};
+                const hipError_t le = hipLaunchKernel(kernel_of(k > 1), g, b, args, lds, st);
+                rc = le != hipSuccess ? set_error(FSMT_EHIP, "solver kernel: %s", hipGetErrorString(le))
+                                      : launch_status("solver kernel");
             }
             (void)hipFreeAsync(dbuf, st);
         }
@@ -664,7 +662,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         }
         bool lds_only = false, all_inline = true;
         for (size_t q = 0; q < ib.size(); ++q) {
-            lds_only = lds_only || insts[ib[q]]->lds_messages;
+            lds_only = lds_only || lds_store(insts[ib[q]]);
             all_inline = all_inline && insts[ib[q]]->all_inline;
         }
         const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
@@ -748,6 +746,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                                                     : 0;
                 plan.check_blocks = checks;
                 plan.use_graph = true;
+                plan.pair = false;
+                for (size_t q = 0; q < ib.size(); ++q) plan.pair = plan.pair || insts[ib[q]]->n_pair > 0;
                 // replay only the levels some restart still has to run: a call that resumes a
                 // schedule (level_done > 0) would otherwise replay every finished level as
                 // launches with nothing to do

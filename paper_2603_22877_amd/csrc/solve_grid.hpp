@@ -44,6 +44,7 @@ struct GridPlan {
     size_t sweep_lds, step_lds;
     int64_t check_blocks;
     bool use_graph;
+    bool pair;                      // some instance has pair-disjunction templates
 };
 
 fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,

@@ -203,8 +203,33 @@ static fsmt_status check_expr(const ConView &cv, int n_lits, int c) {
 
 struct Template {
     int n_nodes = 0, n_slots = 0, n_bslots = 0, root = 0;
+    int pair_l = 0;   // > 0: pair disjunction with this many XOR pairs (closed-form evaluation)
     std::vector<Node> nodes;
 };
+
+// Pair disjunction: the EXPR program OR_i (l_{2i} XOR l_{2i+1}) OR l_{2L} OR ... OR
+// l_{2L+T-1}, written as [0 1 XOR (2i 2i+1 XOR OR)* (t OR)*], every literal positive and on
+// its own slot in literal order, the 2L pair literals Booleans and the T others atoms.
+// Returns L, or 0 when the constraint is not of this form.
+static int pair_family(const ConView &cv, int n_lits) {
+    if (cv.kind != FSMT_EXPR || (int)cv.ids.size() != n_lits) return 0;
+    for (int t = 0; t < n_lits; ++t)
+        if (cv.lit_slot[t] != t || cv.lit_neg[t]) return 0;
+    auto op = [&](int64_t i) { return i < cv.n_ops ? cv.ops[i] : INT32_MIN; };
+    if (!(op(0) == 0 && op(1) == 1 && op(2) == FSMT_X_XOR)) return 0;
+    int64_t q = 3;
+    int L = 1, T = 0;
+    while (op(q) == 2 * L && op(q + 1) == 2 * L + 1 && op(q + 2) == FSMT_X_XOR && op(q + 3) == FSMT_X_OR) {
+        q += 4;
+        ++L;
+    }
+    while (op(q) == 2 * L + T && op(q + 1) == FSMT_X_OR) {
+        q += 2;
+        ++T;
+    }
+    if (q != cv.n_ops || 2 * L + T != n_lits || cv.n_bslots != 2 * L) return 0;
+    return (L <= kPairMaxL && T <= kPairMaxT) ? L : 0;
+}
 
 // Levelize: nodes reachable from the root sorted by (level, id); root first.
 static fsmt_status emit_template(const Robdd &B, uint32_t root, const ConView &cv, int max_nodes,
@@ -393,6 +418,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             Template T;
             fsmt_status rc = emit_template(B, root, cv, max_nodes, T);
             if (rc) return set_error(rc, "constraint %d: %s", c, last_error());
+            if (T.n_nodes > 0) T.pair_l = pair_family(cv, L);
             if (T.n_slots > 65535) return set_error(FSMT_ELIMIT, "constraint %d: support too large", c);
             t_id = (int)tpls.size();
             tpls.push_back(std::move(T));
@@ -431,7 +457,8 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     std::vector<int32_t> lev;   // level starts: nodes are sorted by slot, so each level is a range
     for (int t = 0; t < T; ++t) {
         const Template &tp = tpls[t];
-        tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, (int32_t)lev.size(), {0, 0}};
+        tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, (int32_t)lev.size(),
+                           {tp.pair_l, 0}};
         int v = 0;
         for (int sl = 0; sl <= tp.n_slots; ++sl) {
             while (v < tp.n_nodes && tp.nodes[v].slot < sl) ++v;
@@ -441,7 +468,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         h->max_nodes = std::max(h->max_nodes, tp.n_nodes);
         h->max_slots = std::max(h->max_slots, tp.n_slots);
         if (members[t].empty()) continue;
-        if (big_diagram(tp.n_nodes, tp.n_slots)) {
+        if (tp.pair_l > 0) {
+            h->n_pair += (int64_t)members[t].size();   // closed form: no message store, never big
+        } else if (big_diagram(tp.n_nodes, tp.n_slots)) {
             h->big_max_nodes = std::max(h->big_max_nodes, tp.n_nodes);
             h->big_max_slots = std::max(h->big_max_slots, tp.n_slots);
         } else {
@@ -457,9 +486,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         const int npos = (nc + 63) / 64 * 64;
         const int ns = tpls[t].n_slots;
         const TplInfo &ti = tinfo[t];
-        const int big = big_diagram(ti.n_nodes, ti.n_slots) ? 1 : 0;
+        const int big = (ti.pad[0] == 0 && big_diagram(ti.n_nodes, ti.n_slots)) ? 1 : 0;
         BucketInfo bi{t, bstart.back(), npos, nc, (int64_t)sup.size(), -1, ti.node_off, ti.n_nodes, ti.n_slots,
-                      ti.n_bslots, ti.root, ti.lev_off, big, 0};
+                      ti.n_bslots, ti.root, ti.lev_off, big, ti.pad[0]};
         const int b_id = (int)buckets.size();
         sup.resize(sup.size() + (size_t)ns * npos, 0);
         for (int i = 0; i < npos; ++i) {
@@ -716,6 +745,7 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->max_slots = h->max_slots;
     s->n_big = h->n_big;
     s->n_hs_colors = h->n_hs_colors;
+    s->n_pair = (int32_t)h->n_pair;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

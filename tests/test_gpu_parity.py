@@ -449,6 +449,18 @@ def test_paper_suite_cop_parity(fam, A, B, R):
         _compare(p, a, b, kap, w=w)
 
 
+@pytest.mark.parametrize("fam,A,B,R", [("sched", 16, 2, 100), ("place", 2, 4, 70)])
+def test_paper_suite_many_restarts(fam, A, B, R):
+    """More than 64 restarts (lanes are restarts of one constraint, one wave per 64): the
+    closed-form pair path and the generic path against the oracle, rows and columns layout."""
+    p = _paper_instance(fam, A, B)
+    a, b = W.initial_points(p, R, 15, A, B)
+    ell = p.meta.get("mean_duration", p.meta.get("mean_side"))
+    for kap in (1.0 / ell, 8.0 / ell):
+        _compare(p, a, b, kap)
+        _compare(p, a, b, kap, layout="cols")
+
+
 @pytest.mark.parametrize("R,kap", [(1, 2.0), (2, 20.0)])
 def test_paper_placement_large_register_store(R, kap):
     """32 macros x 8 layers: 8 index bits per module pair, 28-node / 20-slot diagrams in the

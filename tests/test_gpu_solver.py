@@ -210,7 +210,9 @@ def test_autograd_function_matches_reverse_sweep():
     np.testing.assert_allclose(b.grad.cpu().numpy(), g * o["grad_b"], rtol=1e-4, atol=1e-5 * np.abs(o["grad_b"]).max())
     with torch.no_grad():
         U2 = S.cop_objective(a, b, h, 0.2, w)
-    np.testing.assert_allclose(U2.cpu().numpy(), U.detach().cpu().numpy(), rtol=1e-6)
+    # forward-only and forward + reverse calls sum the same per-constraint values in a
+    # different order (float atomics over ~180 wave partials): the objective tolerance
+    assert_objective(U2.cpu().numpy(), U.detach().cpu().numpy().astype(np.float64), p.n_cons)
 
 
 def test_solver_rejects_bad_options():

@@ -266,3 +266,26 @@ def test_par2_scoring():
     assert [r.score(20.0) for r in rs] == [1.5, 40.0, 40.0]
     assert par2(rs, 20.0) == pytest.approx(81.5 / 3)
     assert par2([], 20.0) == 0.0
+
+
+def test_pair_disjunctions_are_recognized():
+    """Non-overlap constraints of both encodings, OR_i (x_2i XOR x_2i+1) OR atoms, are marked
+    for the closed-form sweep; the same program with a negated literal, a different
+    connective, or other workloads are not."""
+    import dataclasses
+    host = fsmt.FSMT_HOST_ONLY
+    p = sched(16, 2)
+    assert fsmt.xbdd_info(fsmt.xbdd_compile(p, device=host))["n_pair"] == p.meta["n_pairs"]
+    q = place(4, 4)
+    assert fsmt.xbdd_info(fsmt.xbdd_compile(q, device=host))["n_pair"] == q.meta["n_pairs"]
+    for cfg in (2, 3):
+        assert fsmt.xbdd_info(fsmt.xbdd_compile(W.make_config(cfg), device=host))["n_pair"] == 0
+    nd = p.meta["n_deps"]
+    lit = p.con_lit.copy()
+    lit[p.con_ptr[nd]] |= 1                      # negate the first literal of the first pair
+    assert fsmt.xbdd_info(fsmt.xbdd_compile(dataclasses.replace(p, con_lit=lit), device=host))["n_pair"] == \
+        p.meta["n_pairs"] - 1
+    ops = p.expr_ops.copy()
+    ops[p.expr_ptr[nd] + 2] = -1                 # XOR -> AND in the first pair constraint
+    assert fsmt.xbdd_info(fsmt.xbdd_compile(dataclasses.replace(p, expr_ops=ops), device=host))["n_pair"] == \
+        p.meta["n_pairs"] - 1
