@@ -13,9 +13,12 @@ public; the generator is in workloads/scheduling.py).
   before the timed region; no early exit (eps = 0, no stop on SAT) so the work is fixed.
 * time_to_sat: wall time until a SAT verdict, batched fused (64 restarts in one launch)
   against the plain per-call path (one restart at a time, separate launches per step),
-  same hyperparameters, median and PAR-2 over instance seeds.
+  same hyperparameters, median and PAR-2 over instance seeds; time_to_sat_index_encoding:
+  the same comparison on the paper's scheduling encoding (16 workers x 32 jobs), where a
+  single restart rarely reaches SAT.
 * roofline: the solver kernel's duration from HIP events on its stream; algorithmic
-  FLOP and byte counts per launch (model in the design doc).
+  FLOP and byte counts per launch (the per-eval model in algorithmic_cost and
+  flops_per_pass / bytes_per_pass below).
 * cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread);
   cpu_baseline_all_cores: the same on up to 16 host threads.
 * paper_protocol: the paper's gradient-timing protocol (Supplementary Note "Gradient
