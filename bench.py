@@ -59,6 +59,11 @@ ETA_A, ETA_B, EPS = 0.5, 5.0, 1e-2
 LEVELS = 40
 
 
+def log(msg: str) -> None:
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +152,7 @@ def main():
     if args.configs_mode:
         print(json.dumps(other_configs(args, fsmt, S)))
         return
+    log("compiling scheduling 200 x 10")
     p = W.make_config(2)
     R = W.RESTARTS[2]
     ell = p.meta["mean_duration"]
@@ -235,14 +241,19 @@ def main():
                      "flop_per_launch": fl, "bytes_per_launch": by,
                      "hbm_achieved_gbs": ach_gbs, "hbm_frac": ach_gbs / PEAK_HBM_GBS},
     }
+    log(f"timed launch: {levels} levels, {value:.3e} constraint-evals/s")
     if not args.no_tts:
         out["time_to_sat"] = time_to_sat(args, fsmt, S, W, st)
+        log("time-to-SAT on scheduling 200 x 10 done")
         out["time_to_sat_index_encoding"] = time_to_sat_hard(args, fsmt, S, W, st)
+        log("time-to-SAT on the index encoding done")
     if not args.no_protocol:
         out["paper_protocol"] = paper_protocol(fsmt, W, st)
+        log("gradient-timing protocol done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a0, b0, kappas[0])
         out["cpu_baseline_all_cores"] = cpu_baseline(p, a0, b0, kappas[0], threads=min(16, os.cpu_count() or 1))
+        log("CPU baselines done")
     print(json.dumps(out))
 
 
@@ -286,6 +297,7 @@ def time_to_sat(args, fsmt, S, W, st):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             S.solve_batched([h], [state], cfg, stream=st)
+            torch.cuda.synchronize()          # the solver runs on its own stream
             ver = state.verdict.cpu().numpy()
             elapsed += time.perf_counter() - t0
             if ver.max() == 1:
@@ -310,6 +322,7 @@ def time_to_sat(args, fsmt, S, W, st):
             r += 1
         res["plain_s"].append(tp)
         res["plain_restarts"].append(r + 1)
+        log(f"time-to-SAT seed {seed}: batched {tb}, plain {tp}")
 
     def par2(ts):
         return float(np.mean([t if t is not None else 2 * cap for t in ts]))
@@ -347,6 +360,7 @@ def time_to_sat_hard(args, fsmt, S, W, st, cap=15.0):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             S.solve_batched([h], [state], cfg, stream=st)
+            torch.cuda.synchronize()          # the solver runs on its own stream
             ver = state.verdict.cpu().numpy()
             elapsed += time.perf_counter() - t0
             att += 1
@@ -370,6 +384,7 @@ def time_to_sat_hard(args, fsmt, S, W, st, cap=15.0):
                 break
         res["plain_s"].append(tp)
         res["plain_restarts"].append(r)
+        log(f"time-to-SAT index encoding instance {k}: batched {tb}, plain {tp}")
         h.free()
     sc = lambda ts: [t if t is not None else 2 * cap for t in ts]  # noqa: E731
     return {"workload": "paper's scheduling encoding, 16 workers x 32 jobs (instances 0 and 1)",

@@ -60,6 +60,8 @@ def run_instance(problem, cfg: SolveConfig, restarts: int, time_limit: float,
         for end in range(chunk_levels, len(kap) + chunk_levels, chunk_levels):
             sub = dataclasses.replace(cfg, kappas=kap[:min(end, len(kap))])
             solve_batched([h], [st], sub, stream=stream)
+            if stream is not None:
+                torch.cuda.synchronize()            # the solver ran on another stream
             ver = st.verdict.cpu().numpy()          # synchronizes with the solver
             nu = st.n_unsat.cpu().numpy()
             if np.any(nu >= 0):

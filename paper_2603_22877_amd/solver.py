@@ -115,7 +115,18 @@ class PlainSolver:
         self.ver = torch.zeros(R, dtype=torch.int32, device=dev)
 
     def run(self, a0, b0, cfg: SolveConfig, stream=None):
-        """Alg. CLS with Annealing for the R points of a0, b0; returns the trace summary."""
+        """Alg. CLS with Annealing for the R points of a0, b0; returns the trace summary.
+
+        With a torch stream the host-side reads (gradient-map norm, verdict) are ordered
+        after the launches on that stream.
+        """
+        import torch
+        if isinstance(stream, torch.cuda.Stream):
+            with torch.cuda.stream(stream):
+                return self._run(a0, b0, cfg, stream)
+        return self._run(a0, b0, cfg, stream)
+
+    def _run(self, a0, b0, cfg: SolveConfig, stream=None):
         import torch
         h = self.h
         a = torch.as_tensor(np.ascontiguousarray(a0, np.float32), device=self.dev).reshape(self.R, h.n_bool).clone()
