@@ -287,7 +287,8 @@ fsmt_status select_device(const fsmt_xbdd *h) {
 
 HalfSpaces halfspaces_of(const fsmt_xbdd *h) {
     return HalfSpaces{as_cptr(h->d.hs_ptr), as_cptr(h->d.hs_var), as_cptr(h->d.hs_coef), as_cptr(h->d.hs_rhs),
-                      as_cptr(h->d.hs_inv), as_cptr(h->d.hs_cstart), h->n_hs, h->hs_nnz, h->n_hs_colors, 0};
+                      as_cptr(h->d.hs_inv), as_cptr(h->d.hs_cstart), h->n_hs, h->hs_nnz, h->n_hs_colors,
+                      h->hs_separable};
 }
 
 static fsmt_status launch_status(const char *what) {

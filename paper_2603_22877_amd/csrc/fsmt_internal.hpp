@@ -44,6 +44,9 @@ constexpr int kLargeMaxNodes = 29, kLargeMaxSlots = 24;
 // differ, or one of T atoms) are evaluated in closed form (see pair_eval) up to these sizes;
 // their templates carry L in TplInfo::pad[0] / BucketInfo::pad (0: generic diagram).
 constexpr int kPairMaxL = 10, kPairMaxT = 4;
+// Unit-atom half-spaces that share no variable, each over at most this many distinct
+// variables, are projected onto in closed form (project_dykstra) instead of by sweeps.
+constexpr int kSeparableRowMax = 16;
 inline bool big_diagram(int n_nodes, int n_slots) {
     const int64_t ss = n_slots > 1 ? n_slots : 1;
     return (2 * ((int64_t)n_nodes + 2) + 4 * ss) * 64 * 4 > kBigDiagramBytes;
@@ -122,6 +125,7 @@ struct fsmt_xbdd {
     int n_big = 0;                                  // constraints in big buckets
     int64_t total_nodes = 0, nnz = 0, table_bytes = 0;
     int n_box_units = 0, n_hs = 0, hs_nnz = 0, n_hs_colors = 0;
+    int hs_separable = 0;   // one colour class, rows of at most kSeparableRowMax distinct variables
     int64_t n_pair = 0;               // constraints evaluated as pair disjunctions (closed form)
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record

@@ -653,6 +653,16 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
 
     h->n_box_units = h_box_units;
     h->n_hs_colors = (int)hs_cstart.size() - 1;
+    // half-spaces on disjoint variables, each over a few distinct variables: the projection
+    // separates into one exact problem per half-space (the kernels' closed form)
+    h->hs_separable = h->n_hs_colors == 1;
+    for (size_t t = 0; h->hs_separable && t + 1 < hs_ptr.size(); ++t) {
+        const int e0 = hs_ptr[t], e1 = hs_ptr[t + 1];
+        if (e1 - e0 > kSeparableRowMax) h->hs_separable = 0;
+        for (int e = e0; e < e1 && h->hs_separable; ++e)
+            for (int f = e0; f < e; ++f)
+                if (hs_var[f] == hs_var[e]) h->hs_separable = 0;
+    }
     h->n_big = (int)big_pos.size();
     h->n_hs = (int)hs_rhs.size();
     h->hs_nnz = (int)hs_var.size();
@@ -746,6 +756,8 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->n_big = h->n_big;
     s->n_hs_colors = h->n_hs_colors;
     s->n_pair = (int32_t)h->n_pair;
+    s->hs_separable = h->hs_separable;
+    s->reserved = 0;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

@@ -195,6 +195,37 @@ def test_pgd_step_matches_oracle(projection):
                 assert (ch["sat_bits"][r, c >> 5] >> (c & 31)) & 1
 
 
+def test_pgd_step_dykstra_matches_oracle():
+    """Half-spaces that share variables (chained job dependencies of the paper's scheduling
+    encoding): Dykstra's sweeps over colour classes in FP32 against the FP64 oracle run to
+    convergence (the test above takes the closed form: config 2's precedences are disjoint)."""
+    from workloads.paper_suite import make_paper_scheduling
+    p = make_paper_scheduling(16, 3, W.seed_seq(8, 16, 3, 0), dep_prob=0.6)
+    h = fsmt.xbdd_compile(p)
+    info = fsmt.xbdd_info(h)
+    assert info["n_hs_colors"] > 1 and info["hs_separable"] == 0
+    R = 8
+    rng = np.random.default_rng(11)
+    lo, hi = p.real_lo.astype(np.float64), p.real_hi.astype(np.float64)
+    a = rng.uniform(-1, 1, (R, p.n_bool)).astype(np.float32)
+    b = (lo + (hi - lo) * rng.uniform(size=(R, p.n_real))).astype(np.float32)
+    ga = rng.normal(size=a.shape).astype(np.float32)
+    gb = (rng.normal(size=b.shape) * p.meta["mean_duration"]).astype(np.float32)
+    ta, tb, tga, tgb = T(a), T(b), T(ga), T(gb)
+    gsq = torch.zeros(R, device=dev())
+    fsmt.pgd_step(h, ta, tb, tga, tgb, 0.25, 1.0, gsq)
+    o = oracle.pgd(p, a, b, ga, gb, 0.25, 1.0, unit_proj=True)
+    assert o["n_halfspaces"] == info["n_halfspaces"] > 0
+    nb = tb.cpu().numpy()
+    assert np.any(np.abs(o["b"] - np.clip(b - gb, lo, hi)) > 1e-3)   # the half-spaces moved points
+    err = np.abs(nb - o["b"]) / np.maximum(1, np.abs(o["b"]))
+    print(f"Dykstra projection: {info['n_halfspaces']} half-spaces in {info['n_hs_colors']} classes, "
+          f"max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-4, err.max()
+    # the sweeps end with the box step: inside the box the kernel holds (float32 bounds)
+    assert np.all((nb >= lo.astype(np.float32)) & (nb <= hi.astype(np.float32)))
+
+
 def _check_gpu(p, h, a, b):
     R = a.shape[0]
     nw = (p.n_cons + 31) // 32

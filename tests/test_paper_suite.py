@@ -256,6 +256,18 @@ def test_halfspace_colour_classes(make):
     lo = max(deg.values())
     hi = 1 + max(sum(deg[j] - 1 for j in v) for v in hs)
     assert lo <= info["n_hs_colors"] <= hi
+    # half-spaces that share a variable are projected onto by Dykstra's sweeps
+    assert lo > 1 and info["hs_separable"] == 0
+
+
+def test_separable_halfspaces_flag():
+    """The closed-form projection is chosen exactly when no two half-spaces share a
+    variable (one colour class) and each has at most 16 distinct variables."""
+    p = W.make_config(2)      # 5 precedences on distinct jobs among 200
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    assert info["n_halfspaces"] == 5 and info["n_hs_colors"] == 1 and info["hs_separable"] == 1
+    box = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY, projection=fsmt.FSMT_PROJ_BOX))
+    assert box["n_halfspaces"] == 0 and box["hs_separable"] == 0
 
 
 def test_par2_scoring():
