@@ -124,10 +124,10 @@ typedef struct {
                                   the projection handles a class's members in parallel) */
     int32_t n_pair;            /* constraints of the form OR_i (x_2i XOR x_2i+1) OR atoms, whose
                                   forward and reverse sweeps run in closed form */
-    int32_t hs_separable;      /* 1: one colour class and at most 16 distinct variables per
+    int32_t hs_separable;      /* 1: one colour class and at most 4 distinct variables per
                                   half-space; the projection onto D (Prop. "qp") is then solved
                                   exactly per half-space instead of by Dykstra sweeps */
-    int32_t reserved;
+    int32_t reserved;          /* set to 0 */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

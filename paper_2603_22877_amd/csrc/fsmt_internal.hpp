@@ -46,7 +46,7 @@ constexpr int kLargeMaxNodes = 29, kLargeMaxSlots = 24;
 constexpr int kPairMaxL = 10, kPairMaxT = 4;
 // Unit-atom half-spaces that share no variable, each over at most this many distinct
 // variables, are projected onto in closed form (project_dykstra) instead of by sweeps.
-constexpr int kSeparableRowMax = 16;
+constexpr int kSeparableRowMax = 4;
 inline bool big_diagram(int n_nodes, int n_slots) {
     const int64_t ss = n_slots > 1 ? n_slots : 1;
     return (2 * ((int64_t)n_nodes + 2) + 4 * ss) * 64 * 4 > kBigDiagramBytes;

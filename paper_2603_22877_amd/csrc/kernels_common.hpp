@@ -103,22 +103,83 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// a.clip(y - lam a) - r over half-space t's variables (clip to each variable's box)
-__device__ __forceinline__ float hs_excess(const HalfSpaces &hs, int t, const float *y, cptr<float> lo,
-                                           cptr<float> hi, float lam) {
-    float g = -hs.rhs[t];
-    for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) {
-        const int j = hs.var[e];
-        const float z = y[j] - lam * hs.coef[e];
-        g += hs.coef[e] * (z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z));
+__device__ __forceinline__ float clip_to(float z, float l, float h) { return z < l ? l : (z > h ? h : z); }
+
+// Projection onto the box and half-spaces that share no variable, each over at most
+// kSeparableRowMax distinct variables (hs.separable). The problem separates into one
+// projection per half-space onto {x in its variables' box : a.x <= r}; the other variables
+// are only clipped. By the KKT conditions that projection is clip(y - lam a) with lam >= 0
+// the root of g(lam) = a.clip(y - lam a) - r when g(0) > 0. g does not increase and is
+// linear between its breakpoints (where a coordinate reaches a bound), so the root lies on
+// the segment between the last breakpoint with g > 0 and the first with g <= 0. If g stays
+// positive the half-space misses the box; its point of least excess (every coordinate at
+// the bound minimizing a.x) is taken. One lane per half-space, its row in registers.
+__device__ __forceinline__ void project_separable(float *y, float *pb, cptr<float> lo, cptr<float> hi, int m,
+                                                  const HalfSpaces &hs) {
+    constexpr int K = kSeparableRowMax;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = clip_to(y[j], lo[j], hi[j]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < hs.n; t += blockDim.x) {
+        const int e0 = hs.ptr[t], ne = hs.ptr[t + 1] - e0;
+        const float r = hs.rhs[t];
+        int jv[K];
+        float av[K], yv[K], lv[K], hv[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            jv[q] = 0;
+            av[q] = 0.0f;
+            if (q < ne) {
+                jv[q] = hs.var[e0 + q];
+                av[q] = hs.coef[e0 + q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            yv[q] = lv[q] = hv[q] = 0.0f;   // padding: a = 0 adds nothing to g
+            if (q < ne) {
+                yv[q] = y[jv[q]];
+                lv[q] = lo[jv[q]];
+                hv[q] = hi[jv[q]];
+            }
+        }
+        auto excess = [&](float lam) {
+            float g = -r;
+#pragma unroll
+            for (int q = 0; q < K; ++q) g += av[q] * clip_to(yv[q] - lam * av[q], lv[q], hv[q]);
+            return g;
+        };
+        const float g0 = excess(0.0f);
+        if (!(g0 > 0.0f)) continue;
+        float L = 0.0f, gL = g0, U = INFINITY, gU = 0.0f;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (q >= ne || av[q] == 0.0f) continue;
+            for (int s = 0; s < 2; ++s) {
+                const float bp = (yv[q] - (s ? hv[q] : lv[q])) / av[q];
+                if (!(bp > 0.0f)) continue;
+                const float g = excess(bp);
+                if (g > 0.0f) {
+                    if (bp > L) { L = bp; gL = g; }
+                } else if (bp < U) {
+                    U = bp;
+                    gU = g;
+                }
+            }
+        }
+        const float lam = U == INFINITY ? L : L + gL * ((U - L) / (gL - gU));
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q < ne) pb[jv[q]] = clip_to(yv[q] - lam * av[q], lv[q], hv[q]);
     }
-    return g;
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = pb[j];
+    __syncthreads();
 }
 
 // Euclidean projection of y[0..m) (LDS) onto [lo, hi] intersected with the half-spaces
-// (Prop. "qp"). If the clamped point already satisfies every half-space it is the
-// projection. Otherwise, when the half-spaces share no variable and each has few variables
-// (hs.separable), each one is solved in closed form (below); else Dykstra's alternating
+// (Prop. "qp"). Half-spaces that share no variable and have few variables each
+// (hs.separable) are solved in closed form (project_separable). Otherwise: if the clamped
+// point already satisfies every half-space it is the projection; else Dykstra's alternating
 // projections run from y (the colour classes of half-spaces in order, then the box, per
 // sweep; increments pb[m], ph[nnz] in LDS) until a sweep moves no coordinate by more than
 // 4e-7 (1 + |y|), or 256 sweeps. Projecting onto a class is projecting onto each member
@@ -127,6 +188,10 @@ __device__ __forceinline__ float hs_excess(const HalfSpaces &hs, int t, const fl
 // block barriers. All threads of the block must call it.
 __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, cptr<float> lo, cptr<float> hi,
                                                 int m, const HalfSpaces &hs) {
+    if (hs.separable) {
+        project_separable(y, pb, lo, hi, m, hs);
+        return;
+    }
     for (int j = threadIdx.x; j < m; j += blockDim.x) pb[j] = y[j] < lo[j] ? lo[j] : (y[j] > hi[j] ? hi[j] : y[j]);
     __syncthreads();
     int violated = 0;
@@ -136,47 +201,6 @@ __device__ __forceinline__ void project_dykstra(float *y, float *pb, float *ph, 
         violated |= v > 0.0f ? 1 : 0;
     }
     if (!__syncthreads_or(violated)) {
-        for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = pb[j];
-        __syncthreads();
-        return;
-    }
-    if (hs.separable) {
-        // Half-spaces on disjoint variables: the problem separates into one projection per
-        // half-space onto {x in its variables' box : a.x <= r} (the other variables are only
-        // clipped, already in pb). By the KKT conditions that projection is clip(y - lam a)
-        // with lam >= 0 the root of g(lam) = a.clip(y - lam a) - r when g(0) > 0. g does not
-        // increase and is linear between its breakpoints (where a coordinate reaches a
-        // bound), so the root lies on the segment between the last breakpoint with g > 0 and
-        // the first with g <= 0. If g stays positive the half-space misses the box; its
-        // point of least excess (every coordinate at the bound minimizing a.x) is taken.
-        for (int t = threadIdx.x; t < hs.n; t += blockDim.x) {
-            const float g0 = hs_excess(hs, t, y, lo, hi, 0.0f);
-            if (!(g0 > 0.0f)) continue;
-            float L = 0.0f, gL = g0, U = INFINITY, gU = 0.0f;
-            for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) {
-                const float a = hs.coef[e];
-                if (a == 0.0f) continue;
-                const int j = hs.var[e];
-                for (int s = 0; s < 2; ++s) {
-                    const float bp = (y[j] - (s ? hi[j] : lo[j])) / a;
-                    if (!(bp > 0.0f)) continue;
-                    const float g = hs_excess(hs, t, y, lo, hi, bp);
-                    if (g > 0.0f) {
-                        if (bp > L) { L = bp; gL = g; }
-                    } else if (bp < U) {
-                        U = bp;
-                        gU = g;
-                    }
-                }
-            }
-            const float lam = U == INFINITY ? L : L + gL * ((U - L) / (gL - gU));
-            for (int e = hs.ptr[t]; e < hs.ptr[t + 1]; ++e) {
-                const int j = hs.var[e];
-                const float z = y[j] - lam * hs.coef[e];
-                pb[j] = z < lo[j] ? lo[j] : (z > hi[j] ? hi[j] : z);
-            }
-        }
-        __syncthreads();
         for (int j = threadIdx.x; j < m; j += blockDim.x) y[j] = pb[j];
         __syncthreads();
         return;

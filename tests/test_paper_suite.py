@@ -262,7 +262,7 @@ def test_halfspace_colour_classes(make):
 
 def test_separable_halfspaces_flag():
     """The closed-form projection is chosen exactly when no two half-spaces share a
-    variable (one colour class) and each has at most 16 distinct variables."""
+    variable (one colour class) and each has at most 4 distinct variables."""
     p = W.make_config(2)      # 5 precedences on distinct jobs among 200
     info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
     assert info["n_halfspaces"] == 5 and info["n_hs_colors"] == 1 and info["hs_separable"] == 1
