@@ -81,6 +81,7 @@ __device__ __forceinline__ int32_t fetch(gptr<int32_t> p) {
 // false on abort.
 constexpr unsigned kSpinLimit = 1u << 22;
 
+template <bool kNoPoll>
 __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, int32_t *abort_flag) {
     int32_t *bar = (int32_t *)bar_g;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -88,21 +89,68 @@ __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, in
     __syncthreads();
     int ok = 1;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
-            if (++spins > kSpinLimit) {
-                atomicExch(abort_flag, 1);
-                ok = 0;
-                break;
+        auto wait_all = [&]() {
+            unsigned spins = 0;
+            while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+                if (++spins > kSpinLimit) {
+                    atomicExch(abort_flag, 1);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            __builtin_amdgcn_s_sleep(2);
+        };
+        if constexpr (kNoPoll) {
+            // the last to arrive sees the full count in the add's own result and does not
+            // poll (kept to the kernels whose registers leave room for it)
+            if (__hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 < target) wait_all();
+        } else {
+            __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wait_all();
         }
     }
     const bool all = __syncthreads_and(ok) != 0;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return all;
+}
+
+// Sum of the cluster's k partial gradients into g[0..nm) in rank order (every rank gets the
+// same bits); returns the sum of the partial objectives.
+__device__ __forceinline__ float read_partials(float *g, gptr<float> buf, int64_t pstride, int nm, int k) {
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
+        float s = 0.0f;
+        for (int q = 0; q < k; ++q) s += fetch(buf + (int64_t)q * pstride + i);
+        g[i] = s;
+    }
+    float os = 0.0f;
+    for (int q = 0; q < k; ++q) os += fetch(buf + (int64_t)q * pstride + nm);
+    return os;
+}
+
+// The same for k = 2 with every load of a thread in flight before the first sum: one round
+// trip to the coherence point instead of one per element (same sums, same order).
+__device__ __forceinline__ float read_partials2(float *g, gptr<float> buf, int64_t pstride, int nm) {
+    constexpr int kB = 4;
+    const float o0 = fetch(buf + nm), o1 = fetch(buf + pstride + nm);
+    for (int i0 = threadIdx.x; i0 < nm; i0 += kB * blockDim.x) {
+        float v0[kB], v1[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            v0[u] = v1[u] = 0.0f;
+            if (i < nm) {
+                v0[u] = fetch(buf + i);
+                v1[u] = fetch(buf + pstride + i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < nm) g[i] = (0.0f + v0[u]) + v1[u];
+        }
+    }
+    return (0.0f + o0) + o1;
 }
 
 // Waves per workgroup of the solver kernel for each message variant: register-resident
@@ -188,17 +236,16 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 for (int i = threadIdx.x; i < n + m; i += blockDim.x) publish(mine + i, ga[i]);
                 if (threadIdx.x == 0) publish(mine + n + m, op);
                 bar_target += k;
-                if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
+                if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag)) {
                     aborted = true;
                     break;
                 }
-                for (int i = threadIdx.x; i < n + m; i += blockDim.x) {
-                    float s = 0.0f;
-                    for (int q = 0; q < k; ++q) s += fetch(buf + (int64_t)q * pstride + i);
-                    ga[i] = s;
+                float os;
+                if constexpr (V == kMsgSmall) {
+                    os = k == 2 ? read_partials2(ga, buf, pstride, n + m) : read_partials(ga, buf, pstride, n + m, k);
+                } else {
+                    os = read_partials(ga, buf, pstride, n + m, k);
                 }
-                float os = 0.0f;
-                for (int q = 0; q < k; ++q) os += fetch(buf + (int64_t)q * pstride + n + m);
                 oacc = threadIdx.x == 0 ? os : 0.0f;
             }
             __syncthreads();
@@ -280,7 +327,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
         }
         if (kCluster) {
             bar_target += k;
-            if (!cluster_sync(I.bar + r, bar_target, abort_flag)) {
+            if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag)) {
                 aborted = true;
                 break;
             }
