@@ -47,7 +47,8 @@ enum {
     FSMT_ENOMEM = -2,       /* host or device allocation failed */
     FSMT_EUNSUPPORTED = -3, /* valid input the library does not handle ("=" atoms, ...) */
     FSMT_ELIMIT = -4,       /* a size limit was exceeded (diagram nodes, support size) */
-    FSMT_EHIP = -5          /* a HIP runtime call failed */
+    FSMT_EHIP = -5,         /* a HIP runtime call failed */
+    FSMT_EABORTED = -6      /* a solver call ended early (see fsmt_solve_status) */
 };
 
 /* atom comparison operators */
@@ -209,7 +210,9 @@ fsmt_status cop_backward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double ka
  * half-spaces q.b <= q0 - delta of multi-variable unit atoms (delta = 1e-6 (|q0| +
  * sum_j |q_j| max(|lo_j|, |hi_j|)) keeps the rounded point on the satisfied side). The
  * intersection is projected by Dykstra's alternating projections (at most 256 sweeps, until
- * a sweep moves no coordinate by more than 1e-7 (1 + |b|));
+ * a sweep moves no coordinate by more than 4e-7 (1 + |b|)); when no two half-spaces
+ * share a variable and each has at most 4 distinct variables, the projection separates
+ * into one closed-form projection per half-space instead (exact up to rounding);
  * and gmap_sq[r] = ||g||^2 of the gradient map g = ((a-a+)/eta_a, (b-b+)/eta_b)
  * (Eq. "grad_map", "critical"); gmap_sq may be NULL. grad_a / grad_b are zeroed after use
  * (so the next cop_backward can run with FSMT_ACCUMULATE). NaN inputs stay NaN.
@@ -260,7 +263,12 @@ typedef struct {
                                  same instance stops at its next level boundary */
     int32_t schedule;         /* 0 = automatic, 1 = persistent, 2 = grid (see fsmt_solve_batched) */
     int32_t cluster;          /* persistent schedule: workgroups per restart (0 = automatic) */
-    int32_t reserved[4];
+    int32_t level_begin;      /* grid schedule: levels below this are complete for every restart
+                                 of the call (the caller's word); each restart then runs at most
+                                 n_levels - level_begin levels in this call (0: no promise) */
+    int32_t spin_limit;       /* polls of a cluster barrier before it gives up (0 = 2^22); a small
+                                 value makes an incomplete cluster end the call early */
+    int32_t reserved[2];      /* set to 0 */
 } fsmt_solve_opts;
 
 /* Per-instance solver state, device memory owned by the caller ([R] rows each). The
@@ -280,21 +288,45 @@ typedef struct {
 } fsmt_solve_state;
 
 /*
- * Run the annealed PGD solver for n_inst instances at once, each with its own R restarts,
- * fusing forward, reverse sweep, projection, check and ERWA on the device in one
- * persistent launch (one workgroup per restart; its state, gradient and projection work
- * arrays stay in LDS). For every level t from level_done[r] to n_levels-1 with
- * kappa_t = kappas[t]: up to steps_per_level PGD steps (stopping early once
- * ||g||^2 <= eps^2), then rounding + exact check and the ERWA update of Alg. "CLS with
- * Annealing" (h = rho h + [violated]; every tau levels w *= gamma^h, h = 1, then optional
- * renormalization of w to sum n_cons). A restart whose check reports no violated
- * constraint is SAT (Thm. "Soundness"). Asynchronous on the stream. Errors:
- * FSMT_EUNSUPPORTED when a restart's state does not fit in LDS, FSMT_ELIMIT for more than
- * 128 levels, FSMT_EINVAL for bad shapes or options.
+ * Run the annealed PGD solver for n_inst instances at once, each with its own R restarts
+ * (Alg. "CLS with Annealing" around the PGD loop of Alg. "FourierSMT"), fusing forward,
+ * reverse sweep, projection, check and ERWA on the device. For every restart and every level
+ * t from level_done[r] to n_levels-1 with kappa_t = kappas[t]: projected gradient steps while
+ * the gradient map of the last step has ||g||^2 > eps^2 (each restart on its own; at least
+ * one and at most steps_per_level steps), then rounding + exact check and the ERWA update
+ * (h = rho h + [violated]; every tau levels w *= gamma^h, h = 1, then optional
+ * renormalization of w to sum n_cons). A restart whose check reports no violated constraint
+ * is SAT (Thm. "Soundness"). At the end of every level a restart's a, b, level_done,
+ * steps_done, n_unsat, obj and verdict are written together.
+ *
+ * Schedules (opts->schedule; 0 picks one per instance from a cost model): persistent, one
+ * workgroup (or a cluster of `cluster` co-resident workgroups) per restart with the state
+ * in LDS, one launch; grid, one captured graph of grid-wide kernels replayed per level, for
+ * states that do not fit in LDS, big diagrams, or too few restarts to fill the device. A
+ * batch may mix both (they run concurrently). The grid schedule uses grad_a / grad_b of the
+ * state as work arrays when given (else its own).
+ *
+ * Asynchronous on the stream: the call enqueues work and returns without waiting for the
+ * device. A cluster whose workgroups were not all resident gives up at a bounded barrier
+ * wait (spin_limit): every restart of that launch that was still running then ends with
+ * verdict = -2 and the state of its last completed level; fsmt_solve_status reports it.
+ * Errors (before anything is launched): FSMT_EINVAL for bad shapes or options, FSMT_ELIMIT
+ * for more than 128 levels or diagrams beyond the LDS bounds, FSMT_EUNSUPPORTED when the
+ * persistent schedule is asked for but a state does not fit in LDS, an instance has big
+ * diagrams, or a forced cluster size cannot be co-resident.
  */
 fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst,
                                const fsmt_solve_opts *opts, const fsmt_solve_state *states,
                                void *stream);
+
+/*
+ * Outcome of the solver calls enqueued on the stream: synchronizes the stream, then reads
+ * every restart's verdict. Returns FSMT_EABORTED (with the instance and restart in
+ * fsmt_last_error) if a restart ended with verdict -2, i.e. a call gave up early; the
+ * state then holds that restart's last completed level and a new call resumes from there.
+ * FSMT_OK otherwise. FSMT_EHIP if the device reported an error.
+ */
+fsmt_status fsmt_solve_status(const fsmt_solve_state *states, int32_t n_inst, void *stream);
 
 #ifdef __cplusplus
 }

@@ -5,8 +5,9 @@ package; the library never imports it. The arithmetic lives in ``fsmt_oracle.c``
 FP64, compiled with gcc, no FMA contraction) and, for the tiny brute-force pins, in
 ``brute.py`` (pure Python / numpy). Paper references are given per function in the C file.
 
-Parity unpinned: the annealing driver ``anneal`` (Alg. "CLS with Annealing") has no printed
-trace in the paper; it is pinned only by replaying its steps from identical inputs.
+The annealing driver ``anneal`` (Alg. "CLS with Annealing") has no printed trace in the
+paper; it is pinned by a by-hand replay of the Fig. 2 toy (closed-form gradients, two
+restarts that stop at different steps) and, against the library, level by level.
 """
 from __future__ import annotations
 
@@ -227,14 +228,73 @@ def variable_probs(prob, a, b, kappa: float) -> np.ndarray:
     return np.concatenate([(1.0 - np.asarray(a, np.float32).astype(np.float64)) / 2.0, p_atoms])
 
 
-def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float = 1e-2,
-           rho=0.5, gamma=2.0, tau=1, normalize=True, w0=None, unit_proj=True):
-    """Alg. "CLS with Annealing" literally, with the PGD of Alg. "FourierSMT" inside.
+def anneal_level(prob, a, b, w, h, kappa: float, t: int, eta_a, eta_b, steps_per_level: int,
+                 eps: float = 1e-2, rho=0.5, gamma=2.0, tau=1, normalize=True, unit_proj=True,
+                 active=None):
+    """One annealing level t (1-based) of Alg. "CLS with Annealing" for each restart r with
+    active[r] (all when None), every restart on its own:
 
-    Per level t (kappa_t): up to ``steps_per_level`` projected-gradient steps on U (stop
-    early once ||g||^2 <= eps^2), then rounding, exact check and the ERWA update. The
-    iterates are kept in float32 between steps (as the library stores them). Returns the
-    per-level trace. Parity unpinned (no printed trace in the paper).
+    * ProjGradDesc at kappa (Alg. "FourierSMT"): projected-gradient steps on U
+      (Eq. "pg1"/"pg2"), at most ``steps_per_level``; the loop's test is taken on the
+      gradient map of the step just made, so a restart stops once a step had
+      ||g||^2 <= eps^2 (Eq. "critical"; eps <= 0: never) while the others go on. Iterates
+      are stored in float32 between steps, as the library stores them.
+    * rounding x = sgn(a), exact check, ERWA update of h and w (float64 rows of [R][C]).
+
+    a, b (float32 [R][n], [R][m]), w, h are updated in place for the active rows only.
+    The stop test compares the step's ||g||^2, rounded to float32, with eps^2 in float32:
+    the library takes that decision in float32, and a decision must be taken in the same
+    precision on both sides.
+    Returns dict(n_unsat [R] (-1 for inactive rows), verdict [R], steps [R], sat_bits,
+    gsq [R] (||g||^2 of each restart's last step, float64)).
+    """
+    op = _as(prob)
+    R = a.shape[0]
+    act = np.ones(R, bool) if active is None else np.asarray(active, bool).copy()
+    steps = np.zeros(R, np.int64)
+    last_gsq = np.full(R, np.nan)
+    eps2 = np.float32(eps) * np.float32(eps)
+    stepping = act.copy()
+    for _ in range(steps_per_level):
+        idx = np.nonzero(stepping)[0]
+        if idx.size == 0:
+            break
+        o = objective(op, a[idx], b[idx], kappa, w=w[idx], per_constraint=False)
+        st = pgd(op, a[idx], b[idx], o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32),
+                 eta_a, eta_b, unit_proj)
+        a[idx] = st["a"].astype(np.float32)
+        b[idx] = st["b"].astype(np.float32)
+        steps[idx] += 1
+        last_gsq[idx] = st["gsq"]
+        if eps > 0:
+            stepping[idx[st["gsq"].astype(np.float32) <= eps2]] = False
+    n_unsat = np.full(R, -1, np.int64)
+    verdict = np.zeros(R, np.int32)
+    nw = (op.C + 31) // 32
+    bits = np.zeros((R, nw), np.uint32)
+    idx = np.nonzero(act)[0]
+    if idx.size:
+        ch = check(op, a[idx], b[idx])
+        hh, ww = h[idx].copy(), w[idx].copy()
+        erwa(ch["sat_bits"], op.C, t, hh, ww, rho, gamma, tau, normalize)
+        h[idx], w[idx] = hh, ww
+        n_unsat[idx] = ch["n_unsat"]
+        verdict[idx] = ch["verdict"]
+        bits[idx] = ch["sat_bits"]
+    return dict(n_unsat=n_unsat, verdict=verdict, steps=steps, sat_bits=bits, gsq=last_gsq)
+
+
+def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float = 1e-2,
+           rho=0.5, gamma=2.0, tau=1, normalize=True, w0=None, unit_proj=True, stop_on_sat: int = 1):
+    """Alg. "CLS with Annealing" literally, with the PGD of Alg. "FourierSMT" inside, for R
+    independent restarts (the rows of a0, b0), each running its own loop.
+
+    h starts at 0 and w at w0 (1 by default). Per level t = 1..T (kappa_t): ``anneal_level``.
+    With stop_on_sat = 1 a restart whose check passes is SAT and runs no further level
+    (returns SAT); with 0 every restart runs every level (fixed work). Returns the per-level
+    trace: n_unsat per restart (-1 once a restart has stopped), the iterates and weights after
+    the level, and the steps each restart took. Parity unpinned by the paper (no printed
+    trace); pinned by a by-hand replay of the Fig. 2 toy and level-by-level GPU replays.
     """
     op = _as(prob)
     a = _f32(a0, (-1, op.n)).copy()
@@ -245,19 +305,13 @@ def anneal(prob, a0, b0, kappas, eta_a, eta_b, steps_per_level: int, eps: float 
     trace = []
     done = np.zeros(R, bool)
     for t, kap in enumerate(kappas, start=1):
-        for _ in range(steps_per_level):
-            o = objective(op, a, b, kap, w=w, per_constraint=False)
-            st = pgd(op, a, b, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32),
-                     eta_a, eta_b, unit_proj)
-            a = np.where(done[:, None], a, st["a"].astype(np.float32))
-            b = np.where(done[:, None], b, st["b"].astype(np.float32))
-            if np.all((st["gsq"] <= eps * eps) | done):
-                break
-        ch = check(op, a, b)
-        erwa(ch["sat_bits"], op.C, t, h, w, rho, gamma, tau, normalize)
-        done |= ch["verdict"] == 1
-        trace.append(dict(level=t, kappa=kap, n_unsat=ch["n_unsat"].copy(), a=a.copy(),
-                          b=b.copy(), w=w.copy()))
-        if np.all(done):
+        act = ~done if stop_on_sat else np.ones(R, bool)
+        lv = anneal_level(op, a, b, w, h, kap, t, eta_a, eta_b, steps_per_level, eps, rho, gamma,
+                          tau, normalize, unit_proj, active=act)
+        if stop_on_sat:
+            done |= lv["verdict"] == 1
+        trace.append(dict(level=t, kappa=kap, n_unsat=lv["n_unsat"].copy(), steps=lv["steps"].copy(),
+                          verdict=lv["verdict"].copy(), a=a.copy(), b=b.copy(), w=w.copy(), h=h.copy()))
+        if stop_on_sat and np.all(done):
             break
     return trace

@@ -17,7 +17,7 @@ from ._abi import (FSMT_ACCUMULATE, FSMT_HOST_ONLY, FSMT_MSG_AUTO, FSMT_MSG_LDS,
                    FSMT_PROJ_UNIT, FsmtError)
 
 __all__ = ["XBDD", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram", "cop_forward",
-           "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "FsmtError",
+           "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "fsmt_solve_status", "FsmtError",
            "FSMT_ACCUMULATE", "FSMT_HOST_ONLY", "view", "lib"]
 
 
@@ -177,3 +177,10 @@ def fsmt_solve_batched(handles, opts: _abi.SolveOpts, states, stream=None):
     sarr = (_abi.SolveState * n)(*states)
     _abi.check(lib().fsmt_solve_batched(ct.cast(harr, ct.c_void_p), n, ct.byref(opts),
                                         ct.cast(sarr, ct.c_void_p), _stream(stream)))
+
+
+def fsmt_solve_status(states, stream=None):
+    """Synchronize the stream and raise FsmtError(FSMT_EABORTED) if a solver call gave up."""
+    n = len(states)
+    sarr = (_abi.SolveState * n)(*states)
+    _abi.check(lib().fsmt_solve_status(ct.cast(sarr, ct.c_void_p), n, _stream(stream)))

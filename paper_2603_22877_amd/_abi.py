@@ -7,7 +7,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfsmt.so")
 
-FSMT_OK, FSMT_EINVAL, FSMT_ENOMEM, FSMT_EUNSUPPORTED, FSMT_ELIMIT, FSMT_EHIP = 0, -1, -2, -3, -4, -5
+FSMT_OK, FSMT_EINVAL, FSMT_ENOMEM, FSMT_EUNSUPPORTED, FSMT_ELIMIT, FSMT_EHIP, FSMT_EABORTED = (
+    0, -1, -2, -3, -4, -5, -6)
 FSMT_HOST_ONLY = -2
 FSMT_PROJ_UNIT, FSMT_PROJ_BOX = 0, 1
 FSMT_MSG_AUTO, FSMT_MSG_LDS = 0, 1
@@ -15,7 +16,7 @@ FSMT_ACCUMULATE = 1
 
 EXPORTED = ["fsmt_last_error", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram",
             "cop_forward", "cop_backward", "pgd_step", "round_and_check", "erwa_update",
-            "fsmt_solve_batched"]
+            "fsmt_solve_batched", "fsmt_solve_status"]
 
 
 class Problem(ct.Structure):
@@ -51,7 +52,8 @@ class SolveOpts(ct.Structure):
                 ("eta_a", ct.c_float), ("eta_b", ct.c_float), ("eps", ct.c_float),
                 ("rho", ct.c_float), ("gamma", ct.c_float), ("tau", ct.c_int32),
                 ("normalize", ct.c_int32), ("stop_on_sat", ct.c_int32), ("schedule", ct.c_int32),
-                ("cluster", ct.c_int32), ("reserved", ct.c_int32 * 4)]
+                ("cluster", ct.c_int32), ("level_begin", ct.c_int32), ("spin_limit", ct.c_int32),
+                ("reserved", ct.c_int32 * 2)]
 
 
 class SolveState(ct.Structure):
@@ -95,6 +97,8 @@ def load() -> ct.CDLL:
     L.erwa_update.restype = i32
     L.fsmt_solve_batched.argtypes = [vp, i32, ct.POINTER(SolveOpts), vp, vp]
     L.fsmt_solve_batched.restype = i32
+    L.fsmt_solve_status.argtypes = [vp, i32, vp]
+    L.fsmt_solve_status.restype = i32
     _lib = L
     return L
 

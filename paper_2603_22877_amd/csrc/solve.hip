@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "eval_task.hpp"
@@ -43,7 +44,7 @@ struct SolveParams {
     float eta_a, eta_b, eps2, rho, gamma;
     int32_t state_floats;   // LDS floats reserved for state (max over instances)
     int32_t waves;
-    int32_t pad;
+    uint32_t spin_limit;    // polls of a cluster barrier before it gives up
     double kappas[kMaxLevels];
 };
 
@@ -82,7 +83,8 @@ __device__ __forceinline__ int32_t fetch(gptr<int32_t> p) {
 constexpr unsigned kSpinLimit = 1u << 22;
 
 template <bool kNoPoll>
-__device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, int32_t *abort_flag) {
+__device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, int32_t *abort_flag,
+                                             unsigned spin_limit) {
     int32_t *bar = (int32_t *)bar_g;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);   // this thread's published stores have completed
@@ -93,7 +95,7 @@ __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, in
             unsigned spins = 0;
             while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
-                if (++spins > kSpinLimit) {
+                if (++spins > spin_limit) {
                     atomicExch(abort_flag, 1);
                     ok = 0;
                     break;
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
     }
     int level = I.level_done[r];
     int steps_done = I.steps_done[r];
-    int verdict = I.verdict[r];
+    int verdict = I.verdict[r] == 1 ? 1 : 0;   // -2 (an earlier call gave up) resumes as not SAT
     int n_unsat = I.n_unsat[r];
     float obj = I.obj[r];
     bool aborted = false;
@@ -236,7 +238,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                 for (int i = threadIdx.x; i < n + m; i += blockDim.x) publish(mine + i, ga[i]);
                 if (threadIdx.x == 0) publish(mine + n + m, op);
                 bar_target += k;
-                if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag)) {
+                if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag, P.spin_limit)) {
                     aborted = true;
                     break;
                 }
@@ -320,6 +322,18 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             }
             if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
             stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
+            // the level is complete: its point and counters go to memory together with the
+            // weights just written, so a call that ends early (a cluster that gives up
+            // below) leaves a state that a later call resumes consistently
+            for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
+            for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
+            if (threadIdx.x == 0) {
+                I.level_done[r] = level + 1;
+                I.steps_done[r] = steps_done;
+                I.n_unsat[r] = n_unsat;
+                I.obj[r] = obj;
+                I.verdict[r] = n_unsat == 0 ? 1 : verdict;
+            }
             if (kCluster && threadIdx.x == 0) {
                 publish(I.ctl + 4 * r + 2 * lpar, n_unsat);
                 publish(I.ctl + 4 * r + 2 * lpar + 1, stop);
@@ -327,7 +341,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
         }
         if (kCluster) {
             bar_target += k;
-            if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag)) {
+            if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag, P.spin_limit)) {
                 aborted = true;
                 break;
             }
@@ -340,19 +354,9 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
         if (stop) break;
         __syncthreads();
     }
-    __syncthreads();
-    if (rank != 0) return;
-    if (!aborted) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
-        for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
-    }
-    if (threadIdx.x == 0) {
-        I.level_done[r] = level;
-        I.steps_done[r] = steps_done;
-        I.verdict[r] = aborted ? -2 : verdict;
-        I.n_unsat[r] = n_unsat;
-        I.obj[r] = obj;
-    }
+    // every completed level was written back at its end; an aborted restart only marks its
+    // verdict (its state is that of its last completed level)
+    if (aborted && rank == 0 && threadIdx.x == 0) I.verdict[r] = -2;
 }
 
 static fsmt_status launch_status(const char *what) {
@@ -377,24 +381,35 @@ static const void *solve_kernel_fn(int msg, bool cl, bool pair) {
     return pair ? solve_kernel_fn_p<true>(msg, cl) : solve_kernel_fn_p<false>(msg, cl);
 }
 
+// Dynamic LDS a persistent workgroup may take: the device's per-block maximum (opted into
+// for every solver kernel) less the largest static LDS of those kernels (the block
+// reductions' partial sums).
 static int lds_budget_bytes() {
     static int budget = -1;
     if (budget < 0) {
-        budget = 65536;
+        int b = 65536;
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > budget)
-            budget = v;
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > b)
+            b = v;
         std::vector<const void *> fns;
         for (int msg : {kMsgLds, kMsgSmall, kMsgMedium, kMsgLarge})
             for (int cl = 0; cl < 2; ++cl)
                 for (int pair = 0; pair < 2; ++pair) fns.push_back(solve_kernel_fn(msg, cl != 0, pair != 0));
+        size_t static_lds = 0;
         for (const void *f : fns) {
-            if (budget > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, budget) != hipSuccess) {
+            hipFuncAttributes fa{};
+            if (hipFuncGetAttributes(&fa, f) == hipSuccess) static_lds = std::max(static_lds, (size_t)fa.sharedSizeBytes);
+            else (void)hipGetLastError();
+        }
+        const int dyn = b - (int)static_lds;
+        for (const void *f : fns) {
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
                 (void)hipGetLastError();
-                budget = 65536;
+                b = 65536;
             }
         }
+        budget = b - (int)static_lds;
     }
     return budget;
 }
@@ -410,6 +425,65 @@ static size_t state_floats_of(const fsmt_xbdd *h) {
     if (h->n_hs) f += (size_t)h->n_real + (size_t)h->hs_nnz;
     return (f + 63) / 64 * 64;
 }
+
+// ---- per-device resources kept for the life of the process
+// A stream for the grid part of a mixed batch, a stream to capture level graphs on, the
+// fork/join events, and instantiated level graphs waiting for their last launch to finish
+// before they are destroyed (checked without blocking at the next call).
+constexpr int kMaxDevices = 64;
+struct DeviceRes {
+    bool init = false;
+    hipStream_t fork = nullptr, cap = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<GraphRetired> retired;
+};
+static std::mutex g_res_mutex;
+static DeviceRes g_res[kMaxDevices];
+
+// Called with g_res_mutex held and `device` current.
+static fsmt_status device_res(int device, DeviceRes **out) {
+    if (device < 0 || device >= kMaxDevices) return set_error(FSMT_EINVAL, "device %d out of range", device);
+    DeviceRes &R = g_res[device];
+    if (!R.init) {
+        if (hipStreamCreateWithFlags(&R.fork, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&R.ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&R.ev_join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FSMT_EHIP, "solver stream / event creation failed on device %d", device);
+        }
+        R.init = true;
+    }
+    reap_retired(R.retired);
+    *out = &R;
+    return FSMT_OK;
+}
+
+// Device memory of one call: either allocated stream-ordered on the call's stream (and
+// freed the same way after the kernels), or carved from a fixed buffer (the allocation-free
+// entry point).
+struct CallScratch {
+    char *fixed = nullptr;     // base of the fixed buffer, or null
+    size_t cap = 0, used = 0;
+    fsmt_status get(size_t bytes, hipStream_t st, void **out) {
+        bytes = (bytes + 255) / 256 * 256;
+        if (fixed) {
+            if (used + bytes > cap)
+                return set_error(FSMT_ELIMIT, "the call needs more than the %zu bytes of the fixed solver scratch", cap);
+            *out = fixed + used;
+            used += bytes;
+            return FSMT_OK;
+        }
+        if (hipMallocAsync(out, bytes, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FSMT_ENOMEM, "solver scratch allocation (%zu bytes) failed", bytes);
+        }
+        return FSMT_OK;
+    }
+    void put(void *p, hipStream_t st) const {
+        if (!fixed && p) (void)hipFreeAsync(p, st);
+    }
+};
 
 }  // namespace fsmt
 
@@ -438,8 +512,44 @@ static bool prefer_grid(const fsmt_xbdd *h, int R, int64_t R_batch, int waves_a,
     return t_b < t_a;
 }
 
-extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
-                                          const fsmt_solve_state *states, void *stream) {
+// Geometry of one persistent launch over a set of instances.
+struct PersistentGeom {
+    int msg = kMsgSmall, waves = 0, maxn = 0, maxs = 1;
+    size_t state_f = 0, wave_bytes = 0, lds = 0;
+    bool pair = false;
+};
+
+static PersistentGeom persistent_geom(const fsmt_xbdd *const *insts, const std::vector<int> &ids, size_t budget) {
+    PersistentGeom G;
+    bool lds_only = false, all_inline = true;
+    for (int i : ids) {
+        const fsmt_xbdd *h = insts[i];
+        G.state_f = std::max(G.state_f, state_floats_of(h));
+        G.maxn = std::max(G.maxn, h->small_max_nodes);
+        G.maxs = std::max(G.maxs, h->small_max_slots);
+        lds_only = lds_only || lds_store(h);
+        all_inline = all_inline && h->all_inline;
+        G.pair = G.pair || h->n_pair > 0;
+    }
+    G.msg = msg_variant(G.maxn, G.maxs, lds_only, all_inline);
+    G.wave_bytes = G.msg == kMsgLds ? WaveScratch::bytes(G.maxn + 2, G.maxs) : 0;
+    const size_t state_bytes = G.state_f * sizeof(float);
+    if (state_bytes > budget) {
+        G.waves = 0;
+    } else if (G.wave_bytes) {
+        G.waves = (int)std::min<size_t>(16, (budget - state_bytes) / G.wave_bytes);
+    } else {
+        G.waves = solve_waves(G.msg);
+    }
+    G.lds = state_bytes + (size_t)G.waves * G.wave_bytes;
+    return G;
+}
+
+namespace fsmt {
+
+fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
+                       const fsmt_solve_state *states, void *stream, void *fixed, size_t fixed_cap) {
+    const bool fixed_scratch = fixed != nullptr;
     clear_error();
     if (!insts || !opts || !states || n_inst <= 0) return set_error(FSMT_EINVAL, "null argument or no instance");
     const fsmt_solve_opts &O = *opts;
@@ -451,6 +561,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     if (!(O.gamma > 0.0f) || !(O.rho >= 0.0f)) return set_error(FSMT_EINVAL, "bad ERWA parameters");
     if (O.schedule < 0 || O.schedule > 2) return set_error(FSMT_EINVAL, "schedule %d unknown", O.schedule);
     if (O.stop_on_sat < 0 || O.stop_on_sat > 2) return set_error(FSMT_EINVAL, "stop_on_sat must be 0, 1 or 2");
+    if (O.level_begin < 0) return set_error(FSMT_EINVAL, "level_begin < 0");
+    if (O.spin_limit < 0) return set_error(FSMT_EINVAL, "spin_limit < 0");
+    if (fixed_scratch && O.schedule == 2) return set_error(FSMT_EUNSUPPORTED, "the allocation-free call runs the persistent schedule only");
     for (int t = 0; t < O.n_levels; ++t)
         if (!(O.kappas[t] >= 0.0)) return set_error(FSMT_EINVAL, "kappa[%d] must be in [0, +inf]", t);
 
@@ -479,7 +592,16 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         }
     }
 
-    // ---- persistent-schedule geometry (max over its instances) and schedule choice
+    // the device's streams, events and retired graphs serve the grid schedule and mixed
+    // batches; the allocation-free call runs neither and creates nothing
+    std::lock_guard<std::mutex> lock(g_res_mutex);
+    DeviceRes *res = nullptr;
+    if (!fixed_scratch && (rc = device_res(device, &res))) return rc;
+    CallScratch scratch;
+    scratch.fixed = (char *)fixed;
+    scratch.cap = fixed_cap;
+
+    // ---- schedule choice per instance
     const size_t budget = (size_t)lds_budget_bytes();
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
@@ -488,35 +610,46 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
     for (int i = 0; i < n_inst; ++i) r_batch += states[i].a.rows;
     for (int i = 0; i < n_inst; ++i) {
         const fsmt_xbdd *h = insts[i];
-        const int mv = msg_variant(h->small_max_nodes, h->small_max_slots, lds_store(h), h->all_inline);
-        const size_t wb = mv == kMsgLds ? WaveScratch::bytes(h->small_max_nodes + 2, std::max(h->small_max_slots, 1)) : 0;
-        const size_t sb = state_floats_of(h) * sizeof(float);
-        const bool fits = sb + wb <= budget;
-        const int waves = !fits ? 0 : wb ? (int)std::min<size_t>(16, (budget - sb) / wb) : solve_waves(mv);
-        if (O.schedule == 1 && !fits)
+        const PersistentGeom G = persistent_geom(insts, std::vector<int>{i}, budget);
+        const bool fits = G.waves > 0;
+        if ((O.schedule == 1 || fixed_scratch) && !fits)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: restart state (%zu B) does not fit the persistent "
-                             "schedule's LDS (%zu B)", i, sb, budget);
+                             "schedule's LDS (%zu B)", i, G.state_f * sizeof(float), budget);
         // big diagrams are evaluated level by level by their own kernel, in the grid schedule
-        if (O.schedule == 1 && h->n_big > 0)
+        if ((O.schedule == 1 || fixed_scratch) && h->n_big > 0)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: %d big diagrams need the grid schedule", i, h->n_big);
         use_grid[i] = O.schedule == 2 || !fits || h->n_big > 0 ||
-                      (O.schedule == 0 && prefer_grid(h, states[i].a.rows, r_batch, waves, n_cu));
+                      (O.schedule == 0 && !fixed_scratch && prefer_grid(h, states[i].a.rows, r_batch, G.waves, n_cu));
     }
-
-    hipStream_t st = (hipStream_t)stream;
     std::vector<int> ia, ib;
     for (int i = 0; i < n_inst; ++i) (use_grid[i] ? ib : ia).push_back(i);
+    // the persistent launch takes the largest state and message store of its instances: while
+    // that leaves no room for a wave, the instance with the largest state goes to the grid
+    // schedule (the persistent schedule only when it was asked for)
+    PersistentGeom G;
+    while (!ia.empty()) {
+        G = persistent_geom(insts, ia, budget);
+        if (G.waves > 0) break;
+        if (O.schedule == 1 || fixed_scratch)
+            return set_error(FSMT_EUNSUPPORTED, "the instances' combined restart state and message store do not fit "
+                             "one persistent workgroup's LDS (%zu B)", budget);
+        auto big = std::max_element(ia.begin(), ia.end(), [&](int x, int y) {
+            return state_floats_of(insts[x]) < state_floats_of(insts[y]);
+        });
+        ib.push_back(*big);
+        ia.erase(big);
+    }
+    std::sort(ib.begin(), ib.end());
 
-    // the grid part runs on a forked stream, concurrently with the persistent launch
+    hipStream_t st = (hipStream_t)stream;
+    // the grid part runs on the device's fork stream, concurrently with the persistent launch
     hipStream_t gst = st;
-    hipEvent_t fork = nullptr, join = nullptr;
     if (!ia.empty() && !ib.empty()) {
-        if (hipStreamCreateWithFlags(&gst, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
-            return set_error(FSMT_EHIP, "stream / event creation failed");
-        (void)hipEventRecord(fork, st);
-        (void)hipStreamWaitEvent(gst, fork, 0);
+        gst = res->fork;
+        if (hipEventRecord(res->ev_fork, st) != hipSuccess || hipStreamWaitEvent(gst, res->ev_fork, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FSMT_EHIP, "stream fork failed");
+        }
     }
 
     rc = FSMT_OK;
@@ -534,33 +667,17 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         P.eps2 = O.eps > 0.0f ? O.eps * O.eps : -1.0f;
         P.rho = O.rho;
         P.gamma = O.gamma;
+        P.spin_limit = O.spin_limit > 0 ? (uint32_t)O.spin_limit : kSpinLimit;
         for (int t = 0; t < O.n_levels; ++t) P.kappas[t] = O.kappas[t];
         std::vector<InstDesc> desc(ia.size());
-        size_t state_f = 0;
-        int maxn = 0, maxs = 1;
         int64_t total_r = 0, min_tasks = INT64_MAX, part_floats = 0;
-        for (size_t q = 0; q < ia.size(); ++q) {
-            const fsmt_xbdd *h = insts[ia[q]];
-            state_f = std::max(state_f, state_floats_of(h));
-            maxn = std::max(maxn, h->small_max_nodes);
-            maxs = std::max(maxs, h->small_max_slots);
-            total_r += states[ia[q]].a.rows;
-            min_tasks = std::min<int64_t>(min_tasks, h->n_pos / 64);
+        for (int i : ia) {
+            total_r += states[i].a.rows;
+            min_tasks = std::min<int64_t>(min_tasks, insts[i]->n_pos / 64);
         }
-        bool lds_only = false, all_inline = true;
-        for (size_t q = 0; q < ia.size(); ++q) {
-            lds_only = lds_only || lds_store(insts[ia[q]]);
-            all_inline = all_inline && insts[ia[q]]->all_inline;
-        }
-        const int msg = msg_variant(maxn, maxs, lds_only, all_inline);
-        const size_t wave_bytes = msg == kMsgLds ? WaveScratch::bytes(maxn + 2, maxs) : 0;
-        const size_t state_bytes = state_f * sizeof(float);
-        const int waves = wave_bytes ? (int)std::min<size_t>(16, (budget - state_bytes) / wave_bytes) : solve_waves(msg);
-        const size_t lds = state_bytes + (size_t)waves * wave_bytes;
-        // the cluster kernels (k workgroups per restart) have their own resource use
-        bool pair = false;
-        for (size_t q = 0; q < ia.size(); ++q) pair = pair || insts[ia[q]]->n_pair > 0;
-        auto kernel_of = [&](bool cl) -> const void * { return solve_kernel_fn(msg, cl, pair); };
+        const int msg = G.msg, waves = G.waves;
+        const size_t lds = G.lds;
+        auto kernel_of = [&](bool cl) -> const void * { return solve_kernel_fn(msg, cl, G.pair); };
         auto resident_of = [&](bool cl) -> int64_t {
             int occ = 1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel_of(cl), 64 * waves, lds) != hipSuccess) {
@@ -582,10 +699,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             // (182 tasks per restart, 8 waves), 16 restarts: 306 us at k = 1, 163 at 2, 89 at
             // 4, 59 at 8; config 2 (66 tasks, 16 waves), 64 restarts: 22.8 us at k = 1,
             // 21.9 at 2, 22.9 at 4.
-            const int64_t res = resident_of(true);
-            while (k < 16 && min_tasks >= (int64_t)2 * (2 * k) * waves && total_r * 2 * k <= res) k *= 2;
+            const int64_t resd = resident_of(true);
+            while (k < 16 && min_tasks >= (int64_t)2 * (2 * k) * waves && total_r * 2 * k <= resd) k *= 2;
         }
-        const bool cl = k > 1;
         int64_t wg = 0;
         for (size_t q = 0; q < ia.size(); ++q) {
             const fsmt_xbdd *h = insts[ia[q]];
@@ -612,9 +728,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
             if (k > 1) part_floats += (int64_t)d.R * 2 * k * ((int64_t)h->n_bool + h->n_real + 1);
         }
         if (wg > INT32_MAX) return set_error(FSMT_ELIMIT, "too many restarts");
-        P.lds_nodes = maxn;
-        P.lds_slots = maxs;
-        P.state_floats = (int32_t)state_f;
+        P.lds_nodes = G.maxn;
+        P.lds_slots = G.maxs;
+        P.state_floats = (int32_t)G.state_f;
         P.waves = waves;
         // scratch: descriptors | stop flags [n] | abort flag | barriers [R] | level results [2][2R] | partials [2]
         void *dbuf = nullptr;
@@ -622,10 +738,8 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         const size_t off_flag = (desc_bytes + 255) / 256 * 256;
         const size_t n_int = desc.size() + 1 + 5 * (size_t)total_r;
         const size_t off_part = off_flag + (n_int * sizeof(int32_t) + 255) / 256 * 256;
-        if (hipMallocAsync(&dbuf, off_part + sizeof(float) * (size_t)part_floats + 256, st) != hipSuccess) {
-            (void)hipGetLastError();
-            rc = set_error(FSMT_ENOMEM, "descriptor allocation failed");
-        } else {
+        rc = scratch.get(off_part + sizeof(float) * (size_t)part_floats, st, &dbuf);
+        if (!rc) {
             int32_t *ints = (int32_t *)((char *)dbuf + off_flag);
             int32_t *flags = ints, *abort_flag = ints + desc.size(), *bar = abort_flag + 1, *ctl = bar + total_r;
             float *part = (float *)((char *)dbuf + off_part);
@@ -637,8 +751,11 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                 rb += d.R;
                 if (k > 1) pb += (int64_t)d.R * 2 * k * ((int64_t)d.T.n_bool + d.T.n_real + 1);
             }
+            // flags, barriers and level results start at zero (a fill kernel, not a memset:
+            // the call may be captured into a graph); the partials are written before read
             if (hipMemcpyAsync(dbuf, desc.data(), desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
                 fill_i32(ints, (int64_t)n_int, 0, st) != FSMT_OK) {
+                (void)hipGetLastError();
                 rc = set_error(FSMT_EHIP, "descriptor upload failed");
             } else {
                 const dim3 g((unsigned)wg), b(64 * waves);
@@ -648,7 +765,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                 rc = le != hipSuccess ? set_error(FSMT_EHIP, "solver kernel: %s", hipGetErrorString(le))
                                       : launch_status("solver kernel");
             }
-            (void)hipFreeAsync(dbuf, st);
+            scratch.put(dbuf, st);
         }
     }
 
@@ -731,12 +848,9 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
         const size_t off_obj = off_stp + (sizeof(int32_t) * total_r + 255) / 256 * 256;
         const size_t off_flg = off_obj + (sizeof(float) * total_r + 255) / 256 * 256;
         const size_t off_grd = off_flg + (sizeof(int32_t) * gi.size() + 255) / 256 * 256;
-        const size_t total = off_grd + sizeof(float) * (size_t)scratch_floats + 256;
+        const size_t total = off_grd + sizeof(float) * (size_t)scratch_floats;
         void *buf = nullptr;
-        if (!rc && hipMallocAsync(&buf, total, gst) != hipSuccess) {
-            (void)hipGetLastError();
-            rc = set_error(FSMT_ENOMEM, "grid schedule scratch allocation failed");
-        }
+        if (!rc) rc = scratch.get(total, gst, &buf);
         if (!rc) {
             char *base = (char *)buf;
             float *grd = (float *)(base + off_grd);
@@ -776,6 +890,7 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                                                   hipMemcpyHostToDevice, gst) != hipSuccess) ||
                 fill_i32(S.stop_flags, (int64_t)gi.size(), 0, gst) != FSMT_OK ||
                 fill_f32((float *)(base + off_grd), scratch_floats, 0.0f, gst) != FSMT_OK) {
+                (void)hipGetLastError();
                 rc = set_error(FSMT_EHIP, "grid schedule upload failed");
             } else {
                 GridPlan plan{};
@@ -795,36 +910,53 @@ extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t
                 plan.use_graph = true;
                 plan.pair = false;
                 for (size_t q = 0; q < ib.size(); ++q) plan.pair = plan.pair || insts[ib[q]]->n_pair > 0;
-                // replay only the levels some restart still has to run: a call that resumes a
-                // schedule (level_done > 0) would otherwise replay every finished level as
-                // launches with nothing to do
-                int first = O.n_levels;
-                for (size_t q = 0; q < ib.size() && !rc; ++q) {
-                    const fsmt_solve_state &St = states[ib[q]];
-                    const int R = St.a.rows;
-                    std::vector<int32_t> lv((size_t)R), vd((size_t)R);
-                    if (hipMemcpyAsync(lv.data(), St.level_done, sizeof(int32_t) * R, hipMemcpyDeviceToHost, gst) != hipSuccess ||
-                        hipMemcpyAsync(vd.data(), St.verdict, sizeof(int32_t) * R, hipMemcpyDeviceToHost, gst) != hipSuccess ||
-                        hipStreamSynchronize(gst) != hipSuccess) {
-                        rc = set_error(FSMT_EHIP, "reading level counters failed");
-                        break;
-                    }
-                    for (int r = 0; r < R; ++r)
-                        if (!(vd[r] == 1 && O.stop_on_sat != 0)) first = std::min(first, std::max(lv[r], 0));
-                }
-                if (!rc) rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, O.n_levels - first, gst);
+                // each replay of the level sequence advances every running restart by one
+                // level (the kernels read each restart's level from memory and skip finished
+                // restarts); levels below level_begin are complete by the caller's word, so
+                // they are not replayed
+                const int replays = std::max(0, O.n_levels - std::min(O.level_begin, O.n_levels));
+                rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, replays, gst, res->cap,
+                                       res->retired);
             }
-            (void)hipFreeAsync(buf, gst);
+            scratch.put(buf, gst);
         }
     }
 
-    if (join) {
-        (void)hipEventRecord(join, gst);
-        (void)hipStreamWaitEvent(st, join, 0);
-        (void)hipStreamSynchronize(gst);
-        (void)hipEventDestroy(fork);
-        (void)hipEventDestroy(join);
-        (void)hipStreamDestroy(gst);
+    if (gst != st) {
+        if (hipEventRecord(res->ev_join, gst) != hipSuccess || hipStreamWaitEvent(st, res->ev_join, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (!rc) rc = set_error(FSMT_EHIP, "stream join failed");
+        }
     }
     return rc;
+}
+
+}  // namespace fsmt
+
+extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
+                                          const fsmt_solve_state *states, void *stream) {
+    return solve_impl(insts, n_inst, opts, states, stream, nullptr, 0);
+}
+
+extern "C" fsmt_status fsmt_solve_status(const fsmt_solve_state *states, int32_t n_inst, void *stream) {
+    clear_error();
+    if (!states || n_inst <= 0) return set_error(FSMT_EINVAL, "null argument or no instance");
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        return set_error(FSMT_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < n_inst; ++i) {
+        const int R = states[i].a.rows;
+        if (R <= 0 || !states[i].verdict) return set_error(FSMT_EINVAL, "instance %d: no restarts or no verdict", i);
+        std::vector<int32_t> v((size_t)R);
+        if (hipMemcpy(v.data(), states[i].verdict, sizeof(int32_t) * R, hipMemcpyDeviceToHost) != hipSuccess) {
+            const hipError_t e = hipGetLastError();
+            return set_error(FSMT_EHIP, "reading verdicts: %s", hipGetErrorString(e));
+        }
+        for (int r = 0; r < R; ++r)
+            if (v[r] == -2)
+                return set_error(FSMT_EABORTED, "instance %d, restart %d: a cluster barrier gave up waiting; the "
+                                 "state holds its last completed level", i, r);
+    }
+    return FSMT_OK;
 }

@@ -49,7 +49,10 @@ __global__ void grid_begin_kernel(const GridInst *insts, int n_inst, GridShared 
     S.active[g] = act;
     S.stepping[g] = act;
     S.obj_acc[g] = 0.0f;
-    if (act) I.n_unsat[r] = 0;
+    if (act) {
+        I.n_unsat[r] = 0;
+        if (I.verdict[r] < 0) I.verdict[r] = 0;   // an earlier call gave up: resume as not SAT
+    }
 }
 
 // Forward + reverse sweep over every instance's (constraint, restart) lanes.
@@ -307,42 +310,67 @@ static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const Grid
     return launch_status("grid end");
 }
 
-fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
-                              int n_levels, hipStream_t st) {
-    if (n_levels <= 0 || n_inst == 0) return FSMT_OK;
-    // capture one level into a graph on a private stream, replay it once per level
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        cap = nullptr;
+void reap_retired(std::vector<GraphRetired> &list) {
+    size_t keep = 0;
+    for (size_t i = 0; i < list.size(); ++i) {
+        const hipError_t q = hipEventQuery(list[i].done);
+        if (q == hipSuccess) {
+            (void)hipGraphExecDestroy(list[i].exec);
+            (void)hipGraphDestroy(list[i].graph);
+            (void)hipEventDestroy(list[i].done);
+        } else {
+            (void)hipGetLastError();   // "not ready" is not an error of the next call
+            list[keep++] = list[i];
+        }
     }
+    list.resize(keep);
+}
+
+fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
+                              int n_levels, hipStream_t st, hipStream_t cap, std::vector<GraphRetired> &retired) {
+    if (n_levels <= 0 || n_inst == 0) return FSMT_OK;
+    // capture one level into a graph on the capture stream, replay it once per level
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    bool use_graph = cap != nullptr && P.use_graph;
+    bool use_graph = cap != nullptr && P.use_graph && n_levels > 1;
     if (use_graph && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) use_graph = false;
     if (use_graph) {
         fsmt_status rc = enqueue_level(d_insts, n_inst, S, P, cap);
         hipError_t e = hipStreamEndCapture(cap, &graph);
         if (rc || e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGetLastError();
+            if (graph) (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            exec = nullptr;
             use_graph = false;
         }
     }
     fsmt_status rc = FSMT_OK;
     for (int t = 0; t < n_levels && !rc; ++t) {
         if (use_graph) {
-            if (hipGraphLaunch(exec, st) != hipSuccess) rc = set_error(FSMT_EHIP, "hipGraphLaunch failed");
+            if (hipGraphLaunch(exec, st) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = set_error(FSMT_EHIP, "hipGraphLaunch failed");
+            }
         } else {
             rc = enqueue_level(d_insts, n_inst, S, P, st);
         }
     }
     if (exec) {
-        // the executable may be destroyed only after its launches finished
-        (void)hipStreamSynchronize(st);
-        (void)hipGraphExecDestroy(exec);
+        // the executable may be destroyed only after its launches finished: an event after
+        // them marks that point, and a later call destroys it
+        hipEvent_t done = nullptr;
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess && hipEventRecord(done, st) == hipSuccess) {
+            retired.push_back(GraphRetired{exec, graph, done});
+        } else {
+            (void)hipGetLastError();
+            if (done) (void)hipEventDestroy(done);
+            (void)hipStreamSynchronize(st);   // no event to wait on: the only safe point is now
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            if (!rc) rc = set_error(FSMT_EHIP, "event creation failed");
+        }
     }
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
     return rc;
 }
 

@@ -1,5 +1,7 @@
 // Descriptors of the grid schedule of the batched solver (see solve_grid.hip).
 #pragma once
+#include <vector>
+
 #include "eval_task.hpp"
 
 namespace fsmt {
@@ -47,7 +49,24 @@ struct GridPlan {
     bool pair;                      // some instance has pair-disjunction templates
 };
 
+// An instantiated level graph whose replays may still be running: destroyed once the event
+// recorded after its last replay has completed (checked without blocking).
+struct GraphRetired {
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    hipEvent_t done;
+};
+void reap_retired(std::vector<GraphRetired> &list);
+
+// Enqueue n_levels replays of one level's kernel sequence on st (captured into a graph on the
+// stream cap). Does not block the host: the graph joins `retired` after its launches.
 fsmt_status run_grid_schedule(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
-                              int n_levels, hipStream_t st);
+                              int n_levels, hipStream_t st, hipStream_t cap, std::vector<GraphRetired> &retired);
+
+// The batched solver (fsmt_solve_batched). fixed: null to allocate the call's device memory
+// stream-ordered, else a device buffer of fixed_cap bytes to carve it from (then only the
+// persistent schedule runs, and nothing is allocated).
+fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
+                       const fsmt_solve_state *states, void *stream, void *fixed, size_t fixed_cap);
 
 }  // namespace fsmt

@@ -18,7 +18,7 @@ from typing import Callable, List, Optional, Sequence
 import numpy as np
 
 from . import xbdd_compile
-from .solver import BatchState, SolveConfig, solve_batched
+from .solver import BatchState, SolveConfig, check_batched, solve_batched
 
 
 @dataclasses.dataclass
@@ -58,11 +58,11 @@ def run_instance(problem, cfg: SolveConfig, restarts: int, time_limit: float,
         st = BatchState(h, a0, b0)
         attempts += 1
         for end in range(chunk_levels, len(kap) + chunk_levels, chunk_levels):
-            sub = dataclasses.replace(cfg, kappas=kap[:min(end, len(kap))])
+            # every restart has finished the previous chunk's levels (or stopped)
+            sub = dataclasses.replace(cfg, kappas=kap[:min(end, len(kap))], level_begin=end - chunk_levels)
             solve_batched([h], [st], sub, stream=stream)
-            if stream is not None:
-                torch.cuda.synchronize()            # the solver ran on another stream
-            ver = st.verdict.cpu().numpy()          # synchronizes with the solver
+            check_batched([st], stream=stream)      # waits; raises if the call gave up early
+            ver = st.verdict.cpu().numpy()
             nu = st.n_unsat.cpu().numpy()
             if np.any(nu >= 0):
                 best = min(best, int(nu[nu >= 0].min()))

@@ -20,8 +20,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from . import (XBDD, cop_backward, cop_forward, erwa_update, fsmt_solve_batched, pgd_step,
-               round_and_check)
+from . import (XBDD, cop_backward, cop_forward, erwa_update, fsmt_solve_batched, fsmt_solve_status,
+               pgd_step, round_and_check)
 
 
 def kappa_schedule(ell: float, levels: int = 40, kmax: float = 4.0) -> List[float]:
@@ -42,6 +42,8 @@ class SolveConfig:
     stop_on_sat: int = 2
     schedule: int = 0        # 0 automatic, 1 persistent, 2 grid
     cluster: int = 0         # persistent schedule: workgroups per restart (0 automatic)
+    level_begin: int = 0     # grid schedule: levels below this are complete for every restart
+    spin_limit: int = 0      # cluster barrier polls before giving up (0: the library default)
 
     def abi(self):
         kap = (ct.c_double * max(1, len(self.kappas)))(*self.kappas)
@@ -55,6 +57,8 @@ class SolveConfig:
         o.stop_on_sat = int(self.stop_on_sat)
         o.schedule = int(self.schedule)
         o.cluster = int(self.cluster)
+        o.level_begin = int(self.level_begin)
+        o.spin_limit = int(self.spin_limit)
         return o, kap
 
 
@@ -92,16 +96,26 @@ class BatchState:
 
 
 def solve_batched(handles: Sequence[XBDD], states: Sequence[BatchState], cfg: SolveConfig, stream=None):
+    """Enqueue one fused solver call (asynchronous; see ``check_batched``)."""
     o, keep = cfg.abi()
     fsmt_solve_batched(list(handles), o, [s.abi() for s in states], stream=stream)
     del keep
 
 
+def check_batched(states: Sequence[BatchState], stream=None):
+    """Wait for the stream and raise FsmtError (FSMT_EABORTED) if a solver call gave up."""
+    fsmt_solve_status([s.abi() for s in states], stream=stream)
+
+
 class PlainSolver:
-    """Host loop of per-call launches for one instance (the plain per-instance path)."""
+    """Host loop of per-call launches for one instance and one restart (the plain
+    per-instance path): a level's steps end when the step's gradient map norm is at most
+    eps (Alg. "FourierSMT", per point)."""
 
     def __init__(self, h: XBDD, R: int = 1, device=None):
         import torch
+        if R != 1:
+            raise ValueError("the plain path runs one restart at a time")
         self.h, self.R = h, R
         dev = device or torch.device("cuda", torch.cuda.current_device())
         self.dev = dev
@@ -198,8 +212,10 @@ def time_to_sat_batched(handles, states, cfg: SolveConfig, stream=None):
     t0 = time.perf_counter()
     solve_batched(handles, states, cfg, stream=stream)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    dt = time.perf_counter() - t0
+    check_batched(states, stream=stream)
+    return dt
 
 
-__all__ = ["kappa_schedule", "SolveConfig", "BatchState", "solve_batched", "PlainSolver",
+__all__ = ["kappa_schedule", "SolveConfig", "BatchState", "solve_batched", "check_batched", "PlainSolver",
            "cop_objective", "time_to_sat_batched", "Optional"]

@@ -416,6 +416,107 @@ def test_anneal_solves_fig2_toy_to_global_minimum():
     assert tr[-1]["a"][0, 0] < 0 and tr[-1]["b"][0, 0] > 0
 
 
+def _toy_anneal_by_hand(a0, b0, kappas, eta_a, eta_b, steps, eps, rho=0.5, gamma=2.0, tau=1,
+                        stop_on_sat=1):
+    """Alg. "CLS with Annealing" on the Fig. 2 toy for one restart, from the closed forms.
+
+    Constraints c1 = (not x) XOR A and c2 = x AND A with A = (y > 0). With p = P[x True] =
+    (1 - a)/2 and pA = P[A True] = Phi(kappa b) (Eq. "sampling" for the atom -y < 0):
+    P[c1 False] = p pA + ... is p (1 - pA) + (1 - p) pA and P[c2 False] = 1 - p pA, so
+    dU/dp = w1 (1 - 2 pA) - w2 pA, dU/dpA = w1 (1 - 2 p) - w2 p, dp/da = -1/2 and
+    dpA/db = kappa exp(-(kappa b)^2 / 2) / sqrt(2 pi). Iterates are stored in float32 and
+    gradients handed to the step in float32, as the oracle does.
+    """
+    a, b = np.float32(a0), np.float32(b0)
+    w, h = np.ones(2), np.zeros(2)
+    out, done = [], False
+    for t, kap in enumerate(kappas, start=1):
+        if done:
+            out.append(dict(n_unsat=-1, steps=0, a=a, b=b, w=w.copy()))
+            continue
+        k = 0
+        for _ in range(steps):
+            p = (1.0 - float(a)) / 2.0
+            pA = 0.5 * math.erfc(-kap * float(b) / math.sqrt(2.0))
+            dUdp = w[0] * (1.0 - 2.0 * pA) - w[1] * pA
+            dUdpA = w[0] * (1.0 - 2.0 * p) - w[1] * p
+            ga = np.float32(-0.5 * dUdp)
+            gb = np.float32(dUdpA * kap * math.exp(-(kap * float(b)) ** 2 / 2.0) / math.sqrt(2.0 * math.pi))
+            a1 = min(1.0, max(-1.0, float(a) - eta_a * float(ga)))
+            b1 = min(1.0, max(-1.0, float(b) - eta_b * float(gb)))
+            gsq = ((float(a) - a1) / eta_a) ** 2 + ((float(b) - b1) / eta_b) ** 2
+            a, b = np.float32(a1), np.float32(b1)
+            k += 1
+            if eps > 0 and np.float32(gsq) <= np.float32(eps) * np.float32(eps):
+                break
+        x, A = bool(a < 0), bool(b > 0)
+        viol = np.array([(not x) == A, not (x and A)], float)   # c1 holds iff exactly one is True
+        h = rho * h + viol
+        if t % tau == 0:
+            w = w * gamma ** h
+            h = np.ones(2)
+            w = w * (2.0 / w.sum())
+        nu = int(viol.sum())
+        out.append(dict(n_unsat=nu, steps=k, a=a, b=b, w=w.copy()))
+        if stop_on_sat and nu == 0:
+            done = True
+    return out
+
+
+@pytest.mark.parametrize("stop_on_sat", [1, 0])
+def test_anneal_replays_fig2_toy_by_hand_two_restarts(stop_on_sat):
+    """Two restarts: (a, b) = (-1, 1) sits at the global minimum (its steps stop at once and,
+    with stop_on_sat, it is SAT after level 1 and runs no further level); (0.9, -0.9) starts
+    near the local minimum x = False, y <= 0 (Fig. 2) and stays there with one violated
+    constraint, its levels ending after 3, 4, 2 and 1 steps. Each restart follows its own
+    loop, as the by-hand replay does."""
+    p = W.make_fig2_toy()
+    kappas = [0.4 * t for t in range(1, 9)]
+    a0 = np.array([[-1.0], [0.9]], np.float32)
+    b0 = np.array([[1.0], [-0.9]], np.float32)
+    kw = dict(eta_a=0.5, eta_b=0.5, steps_per_level=4, eps=0.05)
+    tr = oracle.anneal(p, a0, b0, kappas, stop_on_sat=stop_on_sat, **kw)
+    hand = [_toy_anneal_by_hand(a0[r, 0], b0[r, 0], kappas, 0.5, 0.5, 4, 0.05, stop_on_sat=stop_on_sat)
+            for r in range(2)]
+    assert len(tr) == len(kappas)
+    for t, lv in enumerate(tr):
+        for r in range(2):
+            hr = hand[r][t]
+            assert lv["n_unsat"][r] == hr["n_unsat"], (t, r)
+            assert lv["steps"][r] == hr["steps"], (t, r)
+            np.testing.assert_allclose(lv["a"][r, 0], hr["a"], rtol=1e-6, atol=1e-7)
+            np.testing.assert_allclose(lv["b"][r, 0], hr["b"], rtol=1e-6, atol=1e-7)
+            np.testing.assert_allclose(lv["w"][r], hr["w"], rtol=1e-9)
+    # the restarts really took different paths: one stopped stepping at once, the other
+    # ended its levels at different step counts, some before the cap
+    assert tr[0]["steps"][0] == 1 and tr[0]["steps"][1] > 1
+    assert len({int(lv["steps"][1]) for lv in tr}) > 2 and min(int(lv["steps"][1]) for lv in tr) < 4
+    if stop_on_sat:
+        assert tr[0]["n_unsat"][0] == 0 and all(lv["n_unsat"][0] == -1 for lv in tr[1:])
+
+
+def test_anneal_restarts_are_independent():
+    """Batched restarts give exactly what each restart gives alone (Alg. "FourierSMT" is a
+    per-point loop): config 1 with 3 restarts, eps large enough that they stop at
+    different steps."""
+    p = W.make_config(1)
+    a0, b0 = W.initial_points(p, 3, 1, 5)
+    ell = p.meta["mean_duration"]
+    kap = [4.0 * t / (40 * ell) for t in (1, 2, 3)]
+    kw = dict(eta_a=0.5, eta_b=5.0, steps_per_level=6, eps=0.5)
+    tr = oracle.anneal(p, a0, b0, kap, stop_on_sat=0, **kw)
+    steps_seen = set()
+    for r in range(3):
+        one = oracle.anneal(p, a0[r:r + 1], b0[r:r + 1], kap, stop_on_sat=0, **kw)
+        for t in range(3):
+            np.testing.assert_array_equal(tr[t]["a"][r], one[t]["a"][0])
+            np.testing.assert_array_equal(tr[t]["b"][r], one[t]["b"][0])
+            np.testing.assert_array_equal(tr[t]["w"][r], one[t]["w"][0])
+            assert tr[t]["steps"][r] == one[t]["steps"][0]
+            steps_seen.add(int(tr[t]["steps"][r]))
+    assert len(steps_seen) > 1
+
+
 # ------------------------------------------------------------------ projection onto D
 def _active_set_projection(y0, G, h):
     """Exact argmin ||y - y0||^2 s.t. G y <= h by enumerating active sets (tiny problems)."""
