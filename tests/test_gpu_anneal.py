@@ -28,7 +28,7 @@ def _np(t, dtype=None):
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
-@pytest.mark.parametrize("cfg_id,R,eps", [(1, 6, 0.2), (2, 8, 0.5)])
+@pytest.mark.parametrize("cfg_id,R,eps", [(1, 6, 0.2), (2, 8, 1.5)])
 def test_anneal_levels_replay_oracle(cfg_id, R, eps, schedule):
     """Alg. "CLS with Annealing" level by level: each call runs one level (resuming at
     level_done) with ERWA on and eps > 0, and the oracle's ``anneal_level`` runs the same
