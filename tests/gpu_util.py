@@ -22,11 +22,20 @@ FLOOR_LOG = []
 
 
 def _record(kind, err, rel_tol, floor):
+    """Log (test, kind, worst ratio with the floor, worst ratio of the relative bar alone,
+    elements whose reference is (numerically) zero and that differ from it)."""
     import os
-    err, rel_tol = np.asarray(err, np.float64), np.asarray(rel_tol, np.float64)
+    err = np.atleast_1d(np.asarray(err, np.float64))
+    rel_tol = np.broadcast_to(np.asarray(rel_tol, np.float64), err.shape)
+    floor = np.broadcast_to(np.asarray(floor, np.float64), err.shape)
     with_floor = float(np.max(err / (rel_tol + floor + 1e-300))) if err.size else 0.0
-    without = float(np.max(np.where(err > 0, err / np.maximum(rel_tol, 1e-300), 0.0))) if err.size else 0.0
-    FLOOR_LOG.append((os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0], kind, with_floor, without))
+    # the relative bar alone is meaningless where the reference underflows to (almost) zero:
+    # those elements are counted apart
+    zero_ref = rel_tol <= 1e-30 * np.maximum(floor, 1e-300)
+    rel = ~zero_ref & (err > 0)
+    without = float(np.max(err[rel] / rel_tol[rel])) if rel.any() else 0.0
+    n_zero = int(np.count_nonzero(zero_ref & (err > 0)))
+    FLOOR_LOG.append((os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0], kind, with_floor, without, n_zero))
 
 
 def dev():
