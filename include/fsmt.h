@@ -320,6 +320,26 @@ fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst,
                                void *stream);
 
 /*
+ * Allocation-free variant of fsmt_solve_batched, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments, semantics and results as fsmt_solve_batched restricted to the
+ * persistent schedule (schedule 0 or 1; schedule 2 returns FSMT_EUNSUPPORTED, and so does
+ * an instance that the persistent schedule cannot take: state beyond LDS, big diagrams).
+ * The call's device memory (descriptors, stop and abort flags, cluster barriers, level
+ * results and partial gradients) is carved from a library-owned device array of
+ * FSMT_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; a call that needs more
+ * returns FSMT_ELIMIT before launching anything. The call allocates nothing (no hipMalloc,
+ * no stream-ordered allocation, no streams or events); what must start at zero is cleared
+ * by a fill kernel on the stream. Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two streams, or two host threads) race and must be serialized
+ * by the caller; calls in order on one stream are safe.
+ */
+#define FSMT_NOALLOC_SCRATCH_BYTES (8u << 20)
+fsmt_status fsmt_solve_batched_noalloc(const fsmt_xbdd *const *insts, int32_t n_inst,
+                                       const fsmt_solve_opts *opts, const fsmt_solve_state *states,
+                                       void *stream);
+
+/*
  * Outcome of the solver calls enqueued on the stream: synchronizes the stream, then reads
  * every restart's verdict. Returns FSMT_EABORTED (with the instance and restart in
  * fsmt_last_error) if a restart ended with verdict -2, i.e. a call gave up early; the

@@ -17,7 +17,7 @@ from ._abi import (FSMT_ACCUMULATE, FSMT_HOST_ONLY, FSMT_MSG_AUTO, FSMT_MSG_LDS,
                    FSMT_PROJ_UNIT, FsmtError)
 
 __all__ = ["XBDD", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram", "cop_forward",
-           "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "fsmt_solve_status", "FsmtError",
+           "cop_backward", "pgd_step", "round_and_check", "erwa_update", "fsmt_solve_batched", "fsmt_solve_batched_noalloc", "fsmt_solve_status", "FsmtError",
            "FSMT_ACCUMULATE", "FSMT_HOST_ONLY", "view", "lib"]
 
 
@@ -177,6 +177,15 @@ def fsmt_solve_batched(handles, opts: _abi.SolveOpts, states, stream=None):
     sarr = (_abi.SolveState * n)(*states)
     _abi.check(lib().fsmt_solve_batched(ct.cast(harr, ct.c_void_p), n, ct.byref(opts),
                                         ct.cast(sarr, ct.c_void_p), _stream(stream)))
+
+
+def fsmt_solve_batched_noalloc(handles, opts: _abi.SolveOpts, states, stream=None):
+    """The allocation-free solver call (persistent schedule, library-owned device scratch)."""
+    n = len(handles)
+    harr = (ct.c_void_p * n)(*[h.ptr for h in handles])
+    sarr = (_abi.SolveState * n)(*states)
+    _abi.check(lib().fsmt_solve_batched_noalloc(ct.cast(harr, ct.c_void_p), n, ct.byref(opts),
+                                                ct.cast(sarr, ct.c_void_p), _stream(stream)))
 
 
 def fsmt_solve_status(states, stream=None):

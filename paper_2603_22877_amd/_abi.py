@@ -16,7 +16,7 @@ FSMT_ACCUMULATE = 1
 
 EXPORTED = ["fsmt_last_error", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram",
             "cop_forward", "cop_backward", "pgd_step", "round_and_check", "erwa_update",
-            "fsmt_solve_batched", "fsmt_solve_status"]
+            "fsmt_solve_batched", "fsmt_solve_batched_noalloc", "fsmt_solve_status"]
 
 
 class Problem(ct.Structure):
@@ -97,6 +97,8 @@ def load() -> ct.CDLL:
     L.erwa_update.restype = i32
     L.fsmt_solve_batched.argtypes = [vp, i32, ct.POINTER(SolveOpts), vp, vp]
     L.fsmt_solve_batched.restype = i32
+    L.fsmt_solve_batched_noalloc.argtypes = [vp, i32, ct.POINTER(SolveOpts), vp, vp]
+    L.fsmt_solve_batched_noalloc.restype = i32
     L.fsmt_solve_status.argtypes = [vp, i32, vp]
     L.fsmt_solve_status.restype = i32
     _lib = L

@@ -597,9 +597,9 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
     std::lock_guard<std::mutex> lock(g_res_mutex);
     DeviceRes *res = nullptr;
     if (!fixed_scratch && (rc = device_res(device, &res))) return rc;
-    CallScratch scratch;
-    scratch.fixed = (char *)fixed;
-    scratch.cap = fixed_cap;
+    CallScratch mem;
+    mem.fixed = (char *)fixed;
+    mem.cap = fixed_cap;
 
     // ---- schedule choice per instance
     const size_t budget = (size_t)lds_budget_bytes();
@@ -738,7 +738,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
         const size_t off_flag = (desc_bytes + 255) / 256 * 256;
         const size_t n_int = desc.size() + 1 + 5 * (size_t)total_r;
         const size_t off_part = off_flag + (n_int * sizeof(int32_t) + 255) / 256 * 256;
-        rc = scratch.get(off_part + sizeof(float) * (size_t)part_floats, st, &dbuf);
+        rc = mem.get(off_part + sizeof(float) * (size_t)part_floats, st, &dbuf);
         if (!rc) {
             int32_t *ints = (int32_t *)((char *)dbuf + off_flag);
             int32_t *flags = ints, *abort_flag = ints + desc.size(), *bar = abort_flag + 1, *ctl = bar + total_r;
@@ -765,7 +765,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
                 rc = le != hipSuccess ? set_error(FSMT_EHIP, "solver kernel: %s", hipGetErrorString(le))
                                       : launch_status("solver kernel");
             }
-            scratch.put(dbuf, st);
+            mem.put(dbuf, st);
         }
     }
 
@@ -850,7 +850,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
         const size_t off_grd = off_flg + (sizeof(int32_t) * gi.size() + 255) / 256 * 256;
         const size_t total = off_grd + sizeof(float) * (size_t)scratch_floats;
         void *buf = nullptr;
-        if (!rc) rc = scratch.get(total, gst, &buf);
+        if (!rc) rc = mem.get(total, gst, &buf);
         if (!rc) {
             char *base = (char *)buf;
             float *grd = (float *)(base + off_grd);
@@ -918,7 +918,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
                 rc = run_grid_schedule((const GridInst *)buf, (int)gi.size(), S, plan, replays, gst, res->cap,
                                        res->retired);
             }
-            scratch.put(buf, gst);
+            mem.put(buf, gst);
         }
     }
 
@@ -936,6 +936,42 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
 extern "C" fsmt_status fsmt_solve_batched(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt_solve_opts *opts,
                                           const fsmt_solve_state *states, void *stream) {
     return solve_impl(insts, n_inst, opts, states, stream, nullptr, 0);
+}
+
+// ---- allocation-free variant: the call's device memory (descriptors, flags, cluster
+// barriers and partial gradients) is carved from this array, one copy per device, held until
+// the process ends. In host code the name is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device with that device current.
+static __device__ __align__(256) char scratch[FSMT_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mutex;
+static void *g_scratch_ptr[kMaxDevices];
+
+extern "C" fsmt_status fsmt_solve_batched_noalloc(const fsmt_xbdd *const *insts, int32_t n_inst,
+                                                  const fsmt_solve_opts *opts, const fsmt_solve_state *states,
+                                                  void *stream) {
+    clear_error();
+    if (!insts || n_inst <= 0 || !insts[0]) return set_error(FSMT_EINVAL, "null argument or no instance");
+    fsmt_status rc = select_device(insts[0]);
+    if (rc) return rc;
+    const int device = insts[0]->device;
+    if (device < 0 || device >= kMaxDevices) return set_error(FSMT_EINVAL, "device %d out of range", device);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                return set_error(FSMT_EHIP, "address of the solver scratch on device %d: %s", device,
+                                 hipGetErrorString(e));
+            }
+            g_scratch_ptr[device] = p;
+        }
+        base = g_scratch_ptr[device];
+    }
+    return solve_impl(insts, n_inst, opts, states, stream, base, (size_t)FSMT_NOALLOC_SCRATCH_BYTES);
 }
 
 extern "C" fsmt_status fsmt_solve_status(const fsmt_solve_state *states, int32_t n_inst, void *stream) {
