@@ -92,10 +92,16 @@ enum {
 };
 
 /* Where the diagram passes keep a lane's node messages (Eq. "dp" forward masses and
- * reverse probabilities). Both give the same results; the choice is performance only. */
+ * reverse probabilities), and whether recognized diagram families (pair disjunctions,
+ * guarded disjunctions: see fsmt_xbdd_stats) run as the same message passing with the
+ * graph fixed at compile time. All give the same results; the choice is performance only. */
 enum {
-    FSMT_MSG_AUTO = 0,    /* registers when the largest diagram fits a compiled bound, else LDS */
-    FSMT_MSG_LDS = 1      /* always the wave's LDS columns (any diagram size) */
+    FSMT_MSG_AUTO = 0,    /* closed forms where recognized; registers when the largest other
+                             diagram fits a compiled bound, else LDS */
+    FSMT_MSG_LDS = 1,     /* closed forms where recognized; the wave's LDS columns for the
+                             other diagrams (any size) */
+    FSMT_MSG_GENERIC = 2  /* every diagram through the general node-by-node passes (registers
+                             when small, else LDS) */
 };
 
 typedef struct {
@@ -104,7 +110,7 @@ typedef struct {
                                   xbdd_export_diagram accept such a handle) */
     int32_t max_nodes;         /* reject diagrams with more decision nodes (0 = 1024) */
     int32_t projection;        /* FSMT_PROJ_UNIT or FSMT_PROJ_BOX */
-    int32_t messages;          /* FSMT_MSG_AUTO or FSMT_MSG_LDS */
+    int32_t messages;          /* FSMT_MSG_AUTO, FSMT_MSG_LDS or FSMT_MSG_GENERIC */
     int32_t reserved[4];
 } fsmt_compile_opts;
 
@@ -128,7 +134,10 @@ typedef struct {
     int32_t hs_separable;      /* 1: one colour class and at most 4 distinct variables per
                                   half-space; the projection onto D (Prop. "qp") is then solved
                                   exactly per half-space instead of by Dykstra sweeps */
-    int32_t reserved;          /* set to 0 */
+    int32_t n_gd;              /* constraints that are guarded disjunctions: at most two selector
+                                  variables choose, per assignment, a disjunction of literals (a
+                                  clause; ITE over clauses); forward and reverse sweeps run in
+                                  closed form */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

@@ -66,8 +66,8 @@ def xbdd_compile(problem, device: Optional[int] = None, max_nodes: int = 0,
 
     ``device``: HIP device index, None for the current one, or FSMT_HOST_ONLY.
     ``projection``: FSMT_PROJ_UNIT (box + unit atoms, default) or FSMT_PROJ_BOX.
-    ``messages``: FSMT_MSG_AUTO (registers when the diagrams are small, default) or
-    FSMT_MSG_LDS.
+    ``messages``: FSMT_MSG_AUTO (closed forms for recognized families, registers when the
+    other diagrams are small; default), FSMT_MSG_LDS or FSMT_MSG_GENERIC (no closed forms).
     """
     keep = {}
     s = _abi.Problem()

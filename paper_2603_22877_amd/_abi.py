@@ -11,7 +11,7 @@ FSMT_OK, FSMT_EINVAL, FSMT_ENOMEM, FSMT_EUNSUPPORTED, FSMT_ELIMIT, FSMT_EHIP, FS
     0, -1, -2, -3, -4, -5, -6)
 FSMT_HOST_ONLY = -2
 FSMT_PROJ_UNIT, FSMT_PROJ_BOX = 0, 1
-FSMT_MSG_AUTO, FSMT_MSG_LDS = 0, 1
+FSMT_MSG_AUTO, FSMT_MSG_LDS, FSMT_MSG_GENERIC = 0, 1, 2
 FSMT_ACCUMULATE = 1
 
 EXPORTED = ["fsmt_last_error", "xbdd_compile", "xbdd_free", "xbdd_info", "xbdd_export_diagram",
@@ -39,7 +39,7 @@ class Stats(ct.Structure):
                 ("table_bytes", ct.c_int64), ("atom_nnz", ct.c_int64), ("n_box_units", ct.c_int32),
                 ("n_halfspaces", ct.c_int32), ("n_big", ct.c_int32),
                 ("n_hs_colors", ct.c_int32), ("n_pair", ct.c_int32),
-                ("hs_separable", ct.c_int32), ("reserved", ct.c_int32)]
+                ("hs_separable", ct.c_int32), ("n_gd", ct.c_int32)]
 
 
 class View(ct.Structure):

@@ -402,7 +402,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
     if (h->n_big < h->n_cons) {
-        const bool pair = h->n_pair > 0;
+        const bool pair = closed_forms(h);
         if (grad)
             pair ? launch_cop<true, true>(msg, g, bl, lds, st, A) : launch_cop<true, false>(msg, g, bl, lds, st, A);
         else

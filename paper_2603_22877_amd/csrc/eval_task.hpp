@@ -22,6 +22,7 @@ struct TabView {
     cptr<int32_t> sup;
     cptr<int32_t> con_bucket;
     cptr<int32_t> con_local;
+    cptr<GdInfo> gd;
     cptr<int32_t> atom_ptr;
     cptr<int32_t> atom_var;
     cptr<double> atom_coef;
@@ -44,6 +45,7 @@ struct TabView {
         t.sup = as_cptr(h->d.sup);
         t.con_bucket = as_cptr(h->d.con_bucket);
         t.con_local = as_cptr(h->d.con_local);
+        t.gd = as_cptr(h->d.gd);
         t.atom_ptr = as_cptr(h->d.atom_ptr);
         t.atom_var = as_cptr(h->d.atom_var);
         t.atom_coef = as_cptr(h->d.atom_coef);
@@ -599,8 +601,151 @@ __device__ __forceinline__ float pair_eval(const TabView &T, const TaskCtx &t, c
     return F;
 }
 
-// One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
-// scattered through the policy.
+// ---- guarded disjunctions (see GdInfo): selectors 0..k-1 (k <= 2) pick a disjunction of
+// literals per assignment g, so the false mass is F = sum_g pi_g prod_{s in S_g} l_s with
+// l_s = P[literal s False] (q_s for a positive literal, p_s for a negated one). The reverse
+// sweep's slot sensitivities follow from the same sum: dF/dl_s = sum_{g: s in S_g} pi_g
+// prod_{t in S_g, t != s} l_t (prefix and suffix products, no division), and for a
+// selector dF/dp_i = sum_g (+-1) (pi_g / P[slot i = g_i]) prod_g. Every index is static;
+// the masks are wave-uniform (one scalar record per template).
+__device__ __forceinline__ GdInfo load_gd(cptr<GdInfo> p) {
+    static_assert(sizeof(GdInfo) == 32, "guarded-disjunction record layout");
+    typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+    const i32x8 raw = *(cptr<i32x8>)p;
+    GdInfo g;
+    __builtin_memcpy(&g, &raw, sizeof(g));
+    return g;
+}
+
+template <int KS, bool kGrad, bool kInl, class St, class Sc>
+__device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, const GdInfo &g, const St &st,
+                                           double kappa, bool hard, float wc, const Sc &sc, int lane) {
+    const int S = t.B.n_slots, NB = t.B.n_bslots, k = g.k;
+    const int64_t np = t.B.n_pos;
+    float p[KS], q[KS], d[KS], l[KS];
+    // literal probabilities: every id and record is requested before the first is used
+    int id[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) id[s] = (s < NB && t.valid) ? t.sup[(int64_t)s * np] : 0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        p[s] = q[s] = 0.5f;
+        d[s] = 0.0f;
+        if (s < S && t.valid) {
+            if (s < NB) {
+                const float av = st.av(t.r, id[s]);
+                p[s] = (1.0f - av) * 0.5f;
+                q[s] = (1.0f + av) * 0.5f;
+            } else if (kInl || t.rec) {
+                const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
+                atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p[s], q[s], d[s]);
+            } else {
+                const int ka = t.sup[(int64_t)s * np] - T.n_bool;
+                atom_literal(atom_z_state(T, ka, st, t.r), T.atom_scale[ka], T.atom_strict[ka] != 0, kappa, hard, p[s],
+                             q[s], d[s]);
+            }
+        }
+        l[s] = ((g.neg >> s) & 1u) ? p[s] : q[s];
+    }
+    float F = 0.0f, gp0 = 0.0f, gp1 = 0.0f;
+    float gl[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) gl[s] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= (1 << k)) break;
+        const uint32_t m = g.mask[c];
+        if (m >> 31) continue;   // this assignment reaches the True terminal
+        const float pi0 = k > 0 ? ((c & 1) ? p[0] : q[0]) : 1.0f;
+        const float pi1 = k > 1 ? ((c & 2) ? p[1] : q[1]) : 1.0f;
+        float pre[KS];
+        float prod = 1.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            pre[s] = prod;
+            if (s < S && ((m >> s) & 1u)) prod *= l[s];
+        }
+        F += (pi0 * pi1) * prod;
+        if constexpr (kGrad) {
+            float suf = pi0 * pi1;
+#pragma unroll
+            for (int s = KS - 1; s >= 0; --s) {
+                if (s < S && ((m >> s) & 1u)) {
+                    gl[s] += pre[s] * suf;
+                    suf *= l[s];
+                }
+            }
+            if (k > 0) gp0 += ((c & 1) ? pi1 : -pi1) * prod;
+            if (k > 1) gp1 += ((c & 2) ? pi0 : -pi0) * prod;
+        }
+    }
+    if constexpr (kGrad) {
+        // G_s = dF/dp_s: a negated literal's l is p (dl/dp = 1), a positive one's is 1 - p
+        float G[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            G[s] = ((g.neg >> s) & 1u) ? gl[s] : -gl[s];
+            if (s == 0 && k > 0) G[s] = gp0;
+            if (s == 1 && k > 1) G[s] = gp1;
+        }
+        // Boolean slots: distinct variables within a constraint; dp/da = -1/2
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s < NB) {
+                const float gv = t.valid ? wc * G[s] * -0.5f : 0.0f;
+                sc.add_a(t.r, t.valid ? id[s] : -1, gv, lane);
+            }
+        }
+        if (kInl || t.rec) {
+            // atoms: consecutive atoms on the same variables are summed before the scatter
+            int v0 = -1, v1 = -1;
+            float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s >= NB && s < S) {
+                    AtomRec a;
+                    a.v0 = a.v1 = -1;
+                    a.c0 = a.c1 = 0.0f;
+                    a.flags = 0;
+                    if (t.valid) a = load_rec(t.rec + (int64_t)(s - NB) * np);
+                    const float gz = t.valid ? wc * G[s] * d[s] : 0.0f;
+                    const bool n0 = a.v0 != v0, n1 = a.v1 != v1;
+                    sc.add_b(t.r, n0 ? v0 : -1, n0 ? g0 : 0.0f, lane);
+                    sc.add_b(t.r, n1 ? v1 : -1, n1 ? g1 : 0.0f, lane);
+                    if (n0) { v0 = a.v0; g0 = 0.0f; }
+                    if (n1) { v1 = a.v1; g1 = 0.0f; }
+                    g0 += gz * a.c0;
+                    if (a.flags & 2u) g1 += gz * a.c1;
+                }
+            }
+            sc.add_b(t.r, v0, g0, lane);
+            sc.add_b(t.r, v1, g1, lane);
+        } else if (t.valid) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s >= NB && s < S) {
+                    const float gz = wc * G[s] * d[s];
+                    if (gz != 0.0f) {
+                        const int ka = t.sup[(int64_t)s * np] - T.n_bool;
+                        for (int e = T.atom_ptr[ka]; e < T.atom_ptr[ka + 1]; ++e)
+                            sc.add_b_direct(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
+                    }
+                }
+            }
+        }
+    }
+    return t.valid ? F : 0.0f;
+}
+
+// Guarded disjunction of the task's bucket: a short variant for supports of up to 4 slots
+// (clauses), the full one up to kGdMaxSlots.
+template <bool kGrad, bool kInl, class St, class Sc>
+__device__ __forceinline__ float gd_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
+                                         float wc, const Sc &sc, int lane) {
+    const GdInfo g = load_gd(T.gd + t.B.tpl);
+    if (t.B.n_slots <= 4) return gd_eval_n<4, kGrad, kInl>(T, t, g, st, kappa, hard, wc, sc, lane);
+    return gd_eval_n<kGdMaxSlots, kGrad, kInl>(T, t, g, st, kappa, hard, wc, sc, lane);
+}
 
 // Message-store variants: a kernel is instantiated per variant and the host picks the
 // smallest whose bounds hold for every diagram of the launch.
@@ -637,13 +782,15 @@ __device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, in
 
 // One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
 // scattered through the policy. Kernels are instantiated with kPair only for launches that
-// hold pair-disjunction templates (the closed-form path adds registers); there a register
-// store is declared per task, so its arrays are live only in the generic branch.
+// hold closed-form templates (pair or guarded disjunctions; the closed-form paths add
+// registers); there a register store is declared per task, so its arrays are live only in
+// the generic branch.
 template <bool kGrad, bool kPair, class St, class Sc, class Ms>
 __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
                                            float wc, const Sc &sc, Ms &W, int lane) {
     if constexpr (kPair) {
         if (t.B.pad > 0) return pair_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
+        if (t.B.pad < 0) return gd_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
         if constexpr (Ms::kNodes > 0) {
             FSMT_MSG_STORE(Ms, Wt, nullptr, 0, 0, lane);
             const float unsat = task_forward(T, t, st, kappa, hard, Wt);
@@ -660,7 +807,11 @@ __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, c
 // their kernels carry the closed-form path beside the generic one, and the generic
 // templates in LDS leave it the registers (scheduling 256 x 5: 4.2 ms per PGD step against
 // 5.4 ms with register stores; placement 64 x 8: 1.69 against 1.62 ms).
-inline bool lds_store(const fsmt_xbdd *h) { return h->lds_messages || h->n_pair > 0; }
+inline bool lds_store(const fsmt_xbdd *h) {
+    return h->lds_messages || ((h->n_pair > 0 || h->n_gd > 0) && h->small_max_nodes > 0);
+}
+// Kernels carry the closed-form families (pair and guarded disjunctions) for such instances.
+inline bool closed_forms(const fsmt_xbdd *h) { return h->n_pair > 0 || h->n_gd > 0; }
 
 // Register variants need every atom in an inline record (the CSR path is compiled out).
 inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inline) {

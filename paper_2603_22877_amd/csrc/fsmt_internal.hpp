@@ -28,7 +28,7 @@ struct TplInfo {
     int32_t n_bslots;   // Boolean slots (slots [0, n_bslots) are Booleans)
     int32_t root;       // 0, or n_nodes / n_nodes+1 for constant constraints
     int32_t lev_off;    // level starts: lev[lev_off + s] = first node of slot s (s <= n_slots)
-    int32_t pad[2];     // pad[0]: pair count L of a pair disjunction, else 0
+    int32_t pad[2];     // pad[0]: pair count L of a pair disjunction, -1 a guarded disjunction, else 0
 };
 
 // A diagram is "big" when its per-lane message columns would take more than 40 KB of LDS
@@ -44,6 +44,21 @@ constexpr int kLargeMaxNodes = 29, kLargeMaxSlots = 24;
 // differ, or one of T atoms) are evaluated in closed form (see pair_eval) up to these sizes;
 // their templates carry L in TplInfo::pad[0] / BucketInfo::pad (0: generic diagram).
 constexpr int kPairMaxL = 10, kPairMaxT = 4;
+// Guarded disjunctions: diagrams whose first k <= kGdMaxSel slots ("selectors") route every
+// assignment of them either to a terminal or to a chain in which each node has one edge to
+// the True terminal, i.e. to a disjunction of literals over the later slots (a clause, an
+// ITE over one or two Booleans of such clauses). The false-terminal mass is then
+//   F = sum_g pi_g prod_{s in S_g} l_s,   pi_g = prod_{i < k} P[slot i = g_i],
+// with l_s = P[literal s False], evaluated in closed form (see gd_eval) for supports of at
+// most kGdMaxSlots slots.
+constexpr int kGdMaxSel = 2, kGdMaxSlots = 12;
+struct GdInfo {
+    uint32_t mask[4];   // per selector assignment g (bit i = value of selector i): slots of its
+                        // disjunction; bit 31 set: the assignment reaches the True terminal
+    uint32_t neg;       // slots whose literal is negated (False iff the variable is True)
+    int32_t k;          // selector slots (slots 0 .. k-1)
+    int32_t pad[2];
+};
 // Unit-atom half-spaces that share no variable, each over at most this many distinct
 // variables, are projected onto in closed form (project_dykstra) instead of by sweeps.
 constexpr int kSeparableRowMax = 4;
@@ -63,7 +78,8 @@ struct BucketInfo {
     int32_t node_off, n_nodes, n_slots, n_bslots, root;
     int32_t lev_off;    // level starts of the template
     int32_t big;        // 1: big diagram (level-synchronous kernel), 0: one lane per constraint
-    int32_t pad;
+    int32_t pad;        // closed-form family: L > 0 pair disjunction with L pairs, -1 guarded
+                        // disjunction (record in gd[tpl]), 0 the generic message passing
 };
 
 // Inline atom record (atoms with at most two variables whose "<=" coefficients and
@@ -103,6 +119,7 @@ struct DeviceTables {
     uint8_t *atom_strict = nullptr;   // [A]
     int32_t *lev = nullptr;           // per template: n_slots + 1 level starts
     int32_t *big_pos = nullptr;       // positions of the constraints in big buckets
+    GdInfo *gd = nullptr;             // [n_tpl] guarded-disjunction records (k = -1: not one)
     float *real_lo = nullptr;         // [m] box of D (tightened by single-variable unit atoms)
     float *real_hi = nullptr;         // [m]
     int32_t *hs_ptr = nullptr;        // [H+1] half-spaces of D: q.y <= rhs (multi-variable unit atoms)
@@ -127,6 +144,7 @@ struct fsmt_xbdd {
     int n_box_units = 0, n_hs = 0, hs_nnz = 0, n_hs_colors = 0;
     int hs_separable = 0;   // one colour class, rows of at most kSeparableRowMax distinct variables
     int64_t n_pair = 0;               // constraints evaluated as pair disjunctions (closed form)
+    int64_t n_gd = 0;                 // constraints evaluated as guarded disjunctions (closed form)
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record
     std::vector<fsmt::TplInfo> h_tpl;

@@ -529,7 +529,7 @@ static PersistentGeom persistent_geom(const fsmt_xbdd *const *insts, const std::
         G.maxs = std::max(G.maxs, h->small_max_slots);
         lds_only = lds_only || lds_store(h);
         all_inline = all_inline && h->all_inline;
-        G.pair = G.pair || h->n_pair > 0;
+        G.pair = G.pair || closed_forms(h);
     }
     G.msg = msg_variant(G.maxn, G.maxs, lds_only, all_inline);
     G.wave_bytes = G.msg == kMsgLds ? WaveScratch::bytes(G.maxn + 2, G.maxs) : 0;
@@ -909,7 +909,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
                 plan.check_blocks = checks;
                 plan.use_graph = true;
                 plan.pair = false;
-                for (size_t q = 0; q < ib.size(); ++q) plan.pair = plan.pair || insts[ib[q]]->n_pair > 0;
+                for (size_t q = 0; q < ib.size(); ++q) plan.pair = plan.pair || closed_forms(insts[ib[q]]);
                 // each replay of the level sequence advances every running restart by one
                 // level (the kernels read each restart's level from memory and skip finished
                 // restarts); levels below level_begin are complete by the caller's word, so

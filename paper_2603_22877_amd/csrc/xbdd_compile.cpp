@@ -204,8 +204,58 @@ static fsmt_status check_expr(const ConView &cv, int n_lits, int c) {
 struct Template {
     int n_nodes = 0, n_slots = 0, n_bslots = 0, root = 0;
     int pair_l = 0;   // > 0: pair disjunction with this many XOR pairs (closed-form evaluation)
+    GdInfo gd{};      // guarded disjunction when gd.k >= 0 (closed-form evaluation)
     std::vector<Node> nodes;
 };
+
+// Guarded disjunction, read off the levelized diagram itself: for the smallest k <= kGdMaxSel
+// such that, for every assignment g of slots 0..k-1, the path that takes g's branches at
+// those slots reaches a terminal or a chain whose every node has one edge to the True
+// terminal (the literal of that node: positive when its true edge is that edge) and its
+// other edge to the next node of the chain or to the False terminal. A slot must keep its
+// polarity in every chain. The false-terminal mass of such a diagram is the sum over g of
+// P[g] times the product of the chain's literal-false probabilities, which is what the
+// forward pass accumulates (chains that share their tails add their masses into the shared
+// nodes, and a selector the path skips contributes both of its branches).
+static GdInfo gd_family(const Template &T) {
+    GdInfo g{};
+    g.k = -1;
+    const int N = T.n_nodes;
+    if (N == 0 || T.n_slots > kGdMaxSlots) return g;
+    for (int k = 0; k <= std::min(kGdMaxSel, T.n_slots); ++k) {
+        bool ok = true;
+        uint32_t neg = 0, seen = 0, mask[4] = {0, 0, 0, 0};
+        for (int c = 0; c < (1 << k) && ok; ++c) {
+            int v = 0;
+            while (v < N && T.nodes[v].slot < k) v = ((c >> T.nodes[v].slot) & 1) ? T.nodes[v].hi : T.nodes[v].lo;
+            if (v == N) { mask[c] = 1u << 31; continue; }   // True: no false mass
+            uint32_t m = 0;
+            while (v < N && ok) {
+                const Node &x = T.nodes[v];
+                uint32_t pol;
+                int next;
+                if (x.hi == N) { pol = 0; next = x.lo; }
+                else if (x.lo == N) { pol = 1; next = x.hi; }
+                else { ok = false; break; }
+                const uint32_t bit = 1u << x.slot;
+                if ((seen & bit) && ((neg & bit) != 0) != (pol != 0)) { ok = false; break; }
+                seen |= bit;
+                if (pol) neg |= bit;
+                m |= bit;
+                v = next;
+            }
+            if (ok && v != N + 1) ok = false;   // a chain ends at the False terminal
+            mask[c] = m;
+        }
+        if (ok) {
+            for (int c = 0; c < 4; ++c) g.mask[c] = c < (1 << k) ? mask[c] : 0;
+            g.neg = neg;
+            g.k = k;
+            return g;
+        }
+    }
+    return g;
+}
 
 // Pair disjunction: the EXPR program OR_i (l_{2i} XOR l_{2i+1}) OR l_{2L} OR ... OR
 // l_{2L+T-1}, written as [0 1 XOR (2i 2i+1 XOR OR)* (t OR)*], every literal positive and on
@@ -315,8 +365,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         return set_error(FSMT_EINVAL, "null array in problem");
     const int max_nodes = (opts && opts->max_nodes > 0) ? std::min(opts->max_nodes, 65000) : 1024;
     const bool host_only = opts && opts->device == FSMT_HOST_ONLY;
-    if (opts && opts->messages != FSMT_MSG_AUTO && opts->messages != FSMT_MSG_LDS)
-        return set_error(FSMT_EINVAL, "messages must be FSMT_MSG_AUTO or FSMT_MSG_LDS");
+    if (opts && opts->messages != FSMT_MSG_AUTO && opts->messages != FSMT_MSG_LDS && opts->messages != FSMT_MSG_GENERIC)
+        return set_error(FSMT_EINVAL, "messages must be FSMT_MSG_AUTO, FSMT_MSG_LDS or FSMT_MSG_GENERIC");
+    const bool closed = !(opts && opts->messages == FSMT_MSG_GENERIC);
     if (opts && opts->projection != FSMT_PROJ_UNIT && opts->projection != FSMT_PROJ_BOX)
         return set_error(FSMT_EINVAL, "projection must be FSMT_PROJ_UNIT or FSMT_PROJ_BOX");
     int h_box_units = 0;
@@ -418,7 +469,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             Template T;
             fsmt_status rc = emit_template(B, root, cv, max_nodes, T);
             if (rc) return set_error(rc, "constraint %d: %s", c, last_error());
-            if (T.n_nodes > 0) T.pair_l = pair_family(cv, L);
+            if (T.n_nodes > 0 && closed) T.pair_l = pair_family(cv, L);
+            T.gd.k = -1;
+            if (T.pair_l == 0 && closed) T.gd = gd_family(T);
             if (T.n_slots > 65535) return set_error(FSMT_ELIMIT, "constraint %d: support too large", c);
             t_id = (int)tpls.size();
             tpls.push_back(std::move(T));
@@ -453,12 +506,14 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         return ok;
     };
     std::vector<TplInfo> tinfo(T);
+    std::vector<GdInfo> gd_rec(T);
     std::vector<Node> nodes;
     std::vector<int32_t> lev;   // level starts: nodes are sorted by slot, so each level is a range
     for (int t = 0; t < T; ++t) {
         const Template &tp = tpls[t];
         tinfo[t] = TplInfo{(int32_t)nodes.size(), tp.n_nodes, tp.n_slots, tp.n_bslots, tp.root, (int32_t)lev.size(),
-                           {tp.pair_l, 0}};
+                           {tp.pair_l > 0 ? tp.pair_l : (tp.gd.k >= 0 ? -1 : 0), 0}};
+        gd_rec[t] = tp.gd;
         int v = 0;
         for (int sl = 0; sl <= tp.n_slots; ++sl) {
             while (v < tp.n_nodes && tp.nodes[v].slot < sl) ++v;
@@ -470,6 +525,8 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         if (members[t].empty()) continue;
         if (tp.pair_l > 0) {
             h->n_pair += (int64_t)members[t].size();   // closed form: no message store, never big
+        } else if (tp.gd.k >= 0) {
+            h->n_gd += (int64_t)members[t].size();     // likewise
         } else if (big_diagram(tp.n_nodes, tp.n_slots)) {
             h->big_max_nodes = std::max(h->big_max_nodes, tp.n_nodes);
             h->big_max_slots = std::max(h->big_max_slots, tp.n_slots);
@@ -691,6 +748,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.con_local, con_local, "constraint positions");
     if (!rc) rc = U.put(&h->d.lev, lev, "level starts");
     if (!rc) rc = U.put(&h->d.big_pos, big_pos, "big-diagram positions");
+    if (!rc) rc = U.put(&h->d.gd, gd_rec, "guarded disjunctions");
     h->all_inline = all_inline;
     if (all_inline) {   // every atom is reached through its inline record
         a_ptr.assign(1, 0);
@@ -757,7 +815,7 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->n_hs_colors = h->n_hs_colors;
     s->n_pair = (int32_t)h->n_pair;
     s->hs_separable = h->hs_separable;
-    s->reserved = 0;
+    s->n_gd = (int32_t)h->n_gd;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

@@ -112,6 +112,35 @@ def test_diagram_sizes_of_workload_constraints():
     assert feas["n_nodes"] in (1, 3)
 
 
+def test_guarded_disjunctions_are_recognized_from_the_diagram():
+    """A diagram is a guarded disjunction when at most two leading slots select, per
+    assignment, a terminal or a chain of literals each with one edge to True: clauses,
+    ITEs over clauses, short ANDs and XORs; not-all-equal over three variables is not one
+    (its chains give the last slot both polarities). FSMT_MSG_GENERIC turns the family off."""
+    from workloads.format import KIND_AND, KIND_NAE, X_ITE, X_OR
+    for cfg in (1, 2, 3):
+        p = W.make_config(cfg)
+        assert fsmt.xbdd_info(compile_host(p))["n_gd"] == p.n_cons
+        assert fsmt.xbdd_info(compile_host(p, messages=2))["n_gd"] == 0
+    b = Builder(3, 1, real_lo=np.zeros(1), real_hi=np.ones(1))
+    at = b.atom([0], [1.0], OP_LE, 0.5)
+    cases = [
+        (KIND_CLAUSE, [lit(0), lit(1, True), lit(at)], (), True),
+        (KIND_AND, [lit(0), lit(at, True)], (), True),
+        (KIND_XOR, [lit(0), lit(1)], (), True),
+        (KIND_XOR, [lit(0), lit(1), lit(2)], (), False),
+        (KIND_NAE, [lit(0), lit(1), lit(2)], (), False),
+        # ITE(x0, x1 OR atom, NOT x2 OR atom)
+        (KIND_EXPR, [lit(0), lit(1), lit(at), lit(2, True), lit(at)], (0, 1, 2, X_OR, 3, 4, X_OR, X_ITE), True),
+    ]
+    for kind, lits, ops, want in cases:
+        bb = Builder(3, 1, real_lo=np.zeros(1), real_hi=np.ones(1))
+        bb.atom([0], [1.0], OP_LE, 0.5)
+        bb.add(kind, lits, ops=ops)
+        got = fsmt.xbdd_info(compile_host(bb.build()))["n_gd"]
+        assert got == int(want), (kind, lits, ops)
+
+
 def test_variable_order_invariance_of_cop():
     """The same constraint with Boolean ids permuted has the same COP (order does not matter)."""
     rng = np.random.default_rng(4)
@@ -198,7 +227,7 @@ def test_errors_are_reported_not_thrown():
     p.real_lo = p.real_lo.copy()
     p.real_lo[0] = p.real_hi[0] + 1
     assert _err(p) == _abi.FSMT_EINVAL
-    assert _err(W.make_config(1), messages=2) == _abi.FSMT_EINVAL
+    assert _err(W.make_config(1), messages=3) == _abi.FSMT_EINVAL
     assert _err(W.make_config(1), projection=5) == _abi.FSMT_EINVAL
 
 

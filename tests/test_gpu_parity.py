@@ -42,7 +42,7 @@ def _run_cop(p, h, a, b, kap, w=None, layout="rows", grad=True):
     return out
 
 
-MSG = {"auto": 0, "lds": 1}
+MSG = {"auto": 0, "lds": 1, "generic": 2}
 
 
 def _compare(p, a, b, kap, w=None, layout="rows", messages="auto"):
@@ -59,7 +59,7 @@ def _compare(p, a, b, kap, w=None, layout="rows", messages="auto"):
     return g, o
 
 
-@pytest.mark.parametrize("messages", ["auto", "lds"])
+@pytest.mark.parametrize("messages", ["auto", "lds", "generic"])
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("R", [1, 3, 16, 64, 100])
 @pytest.mark.parametrize("kap", [0.0, 0.4, 2.5, INF])
@@ -137,7 +137,7 @@ def test_fig2_toy_values():
 
 @pytest.mark.parametrize("cfg,R,kap", [(1, 1, 0.3), (1, 1, INF), (2, 64, 0.05), (2, 64, 0.5),
                                        (3, 16, 0.1), (3, 16, 1.0)])
-@pytest.mark.parametrize("messages", ["auto", "lds"])
+@pytest.mark.parametrize("messages", ["auto", "lds", "generic"])
 def test_workload_configs(cfg, R, kap, messages):
     print(f"config {cfg} R={R} kappa={kap} messages={messages}", flush=True)
     p = W.make_config(cfg)

@@ -22,8 +22,8 @@ def _bits_of(st):
     return st.sat_bits.cpu().numpy().view(np.uint32)
 
 
-def _one_step(p, R, kap, eta_a, eta_b, seed, schedule=0):
-    h = fsmt.xbdd_compile(p)
+def _one_step(p, R, kap, eta_a, eta_b, seed, schedule=0, messages=0):
+    h = fsmt.xbdd_compile(p, messages=messages)
     a0, b0 = W.initial_points(p, R, 50, seed)
     st = S.BatchState(h, a0, b0)
     cfg = S.SolveConfig(kappas=[kap], steps_per_level=1, eta_a=eta_a, eta_b=eta_b, eps=0.0, stop_on_sat=0,
@@ -58,10 +58,11 @@ def _assert_step(p, a0, b0, st, kap, eta_a, eta_b):
 
 @pytest.mark.parametrize("schedule", [1, 2])
 @pytest.mark.parametrize("cfg,R,kap,eta_b", [(1, 4, 0.05, 5.0), (2, 8, 0.1, 5.0), (3, 4, 0.2, 8.0)])
-def test_fused_step_matches_oracle(cfg, R, kap, eta_b, schedule):
-    print(f"fused step config {cfg} R={R} schedule {schedule}", flush=True)
+@pytest.mark.parametrize("messages", [0, 2])   # closed forms / generic node-by-node passes
+def test_fused_step_matches_oracle(cfg, R, kap, eta_b, schedule, messages):
+    print(f"fused step config {cfg} R={R} schedule {schedule} messages {messages}", flush=True)
     p = W.make_config(cfg)
-    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg, schedule)
+    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg, schedule, messages)
     _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
 
 
