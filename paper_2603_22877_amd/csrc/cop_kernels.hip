@@ -40,7 +40,7 @@ struct CopArgs {
     int32_t lds_nodes, lds_slots;  // per-wave LDS geometry (max over templates)
 };
 
-template <bool kGrad, int V, bool kPair>
+template <bool kGrad, int V, int kCF>
 __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
         const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
         if (t.B.big) continue;   // evaluated by cop_level_kernel
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;   // requested before the forward pass
-        const float unsat = task_eval<kGrad, kPair>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
+        const float unsat = task_eval<kGrad, kCF>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         if (A.obj) {
             if (A.R_pad <= 64) {
@@ -297,12 +297,19 @@ static fsmt_status launch_status(const char *what) {
     return FSMT_OK;
 }
 
-template <bool kGrad, bool kPair>
-static void launch_cop(int msg, dim3 g, dim3 bl, size_t lds, hipStream_t st, const CopArgs &A) {
-    if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgSmall, kPair>), g, bl, 0, st, A);
-    else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgMedium, kPair>), g, bl, 0, st, A);
-    else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLarge, kPair>), g, bl, 0, st, A);
-    else hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLds, kPair>), g, bl, lds, st, A);
+template <bool kGrad, int kCF>
+static void launch_cop_v(int msg, dim3 g, dim3 bl, size_t lds, hipStream_t st, const CopArgs &A) {
+    if (msg == kMsgSmall) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgSmall, kCF>), g, bl, 0, st, A);
+    else if (msg == kMsgMedium) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgMedium, kCF>), g, bl, 0, st, A);
+    else if (msg == kMsgLarge) hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLarge, kCF>), g, bl, 0, st, A);
+    else hipLaunchKernelGGL((cop_kernel<kGrad, kMsgLds, kCF>), g, bl, lds, st, A);
+}
+template <bool kGrad>
+static void launch_cop(int cf, int msg, dim3 g, dim3 bl, size_t lds, hipStream_t st, const CopArgs &A) {
+    if (cf == 0) launch_cop_v<kGrad, 0>(msg, g, bl, lds, st, A);
+    else if (cf == 1) launch_cop_v<kGrad, 1>(msg, g, bl, lds, st, A);
+    else if (cf == 2) launch_cop_v<kGrad, 2>(msg, g, bl, lds, st, A);
+    else launch_cop_v<kGrad, 3>(msg, g, bl, lds, st, A);
 }
 
 static int blocks_for(int64_t n, int threads, int cap = 4096) {
@@ -402,11 +409,11 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
     if (h->n_big < h->n_cons) {
-        const bool pair = closed_forms(h);
+        const int cf = closed_level(h);
         if (grad)
-            pair ? launch_cop<true, true>(msg, g, bl, lds, st, A) : launch_cop<true, false>(msg, g, bl, lds, st, A);
+            launch_cop<true>(cf, msg, g, bl, lds, st, A);
         else
-            pair ? launch_cop<false, true>(msg, g, bl, lds, st, A) : launch_cop<false, false>(msg, g, bl, lds, st, A);
+            launch_cop<false>(cf, msg, g, bl, lds, st, A);
         if ((rc = launch_status("cop kernel"))) return rc;
     }
     if (h->n_big > 0) {

@@ -601,13 +601,16 @@ __device__ __forceinline__ float pair_eval(const TabView &T, const TaskCtx &t, c
     return F;
 }
 
-// ---- guarded disjunctions (see GdInfo): selectors 0..k-1 (k <= 2) pick a disjunction of
-// literals per assignment g, so the false mass is F = sum_g pi_g prod_{s in S_g} l_s with
-// l_s = P[literal s False] (q_s for a positive literal, p_s for a negated one). The reverse
-// sweep's slot sensitivities follow from the same sum: dF/dl_s = sum_{g: s in S_g} pi_g
-// prod_{t in S_g, t != s} l_t (prefix and suffix products, no division), and for a
-// selector dF/dp_i = sum_g (+-1) (pi_g / P[slot i = g_i]) prod_g. Every index is static;
-// the masks are wave-uniform (one scalar record per template).
+// ---- guarded disjunctions (see GdInfo): Boolean selectors 0..k-1 (k <= 2) pick a
+// disjunction of literals per assignment g, so the false mass is
+//   F = sum_g pi_g prod_{s in S_g} l_s,   l_s = P[literal s False]
+// (q_s for a positive literal, p_s for a negated one). The reverse sweep's slot sensitivities
+// follow from the same sum: dF/dl_s = sum_{g: s in S_g} pi_g prod_{t in S_g, t != s} l_t
+// (prefix and suffix products, no division), and for a selector dF/dp_i = sum_g (+-1)
+// (pi_g / P[slot i = g_i]) prod_g. Boolean and atom slots sit in register arrays with static
+// indices; the masks and run flags are wave-uniform (one scalar record per template). Every
+// lane issues all of its table reads up front (lanes on padding positions or past the
+// restarts read position and restart 0, which exist), so their latencies overlap.
 __device__ __forceinline__ GdInfo load_gd(cptr<GdInfo> p) {
     static_assert(sizeof(GdInfo) == 32, "guarded-disjunction record layout");
     typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
@@ -617,134 +620,176 @@ __device__ __forceinline__ GdInfo load_gd(cptr<GdInfo> p) {
     return g;
 }
 
-template <int KS, bool kGrad, bool kInl, class St, class Sc>
-__device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, const GdInfo &g, const St &st,
-                                           double kappa, bool hard, float wc, const Sc &sc, int lane) {
-    const int S = t.B.n_slots, NB = t.B.n_bslots, k = g.k;
-    const int64_t np = t.B.n_pos;
-    float p[KS], q[KS], d[KS], l[KS];
-    // literal probabilities: every id and record is requested before the first is used
-    int id[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) id[s] = (s < NB && t.valid) ? t.sup[(int64_t)s * np] : 0;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        p[s] = q[s] = 0.5f;
-        d[s] = 0.0f;
-        if (s < S && t.valid) {
-            if (s < NB) {
-                const float av = st.av(t.r, id[s]);
-                p[s] = (1.0f - av) * 0.5f;
-                q[s] = (1.0f + av) * 0.5f;
-            } else if (kInl || t.rec) {
-                const AtomRec a = load_rec(t.rec + (int64_t)(s - NB) * np);
-                atom_literal(rec_z(a, st, t.r), (double)a.scale, (a.flags & 1u) != 0, kappa, hard, p[s], q[s], d[s]);
-            } else {
-                const int ka = t.sup[(int64_t)s * np] - T.n_bool;
-                atom_literal(atom_z_state(T, ka, st, t.r), T.atom_scale[ka], T.atom_strict[ka] != 0, kappa, hard, p[s],
-                             q[s], d[s]);
-            }
-        }
-        l[s] = ((g.neg >> s) & 1u) ? p[s] : q[s];
+// Literal probability of an atom from q.b already formed (lin), as atom_literal but with the
+// derivative's scale in FP32: p = erfc(u)/2, u = kappa scale (lin - rhs) (FP64 product,
+// rounded once), dp/dz = -kappa scale/sqrt(pi) e^{-u^2}.
+__device__ __forceinline__ void gd_atom(double lin, float rhs, float scale, bool strict, double kappa, bool hard,
+                                        float &p, float &q, float &d) {
+#pragma clang fp contract(off)
+    const double z = lin - (double)rhs;
+    if (hard) {
+        const bool tr = strict ? (z < 0.0) : (z <= 0.0);
+        p = tr ? 1.0f : 0.0f;
+        q = tr ? 0.0f : 1.0f;
+        d = 0.0f;
+    } else {
+        const double ks = kappa * (double)scale;
+        const float u = (float)(z * ks);
+        float emu2;
+        const float e = 0.5f * erfc_nr(fabsf(u), emu2);   // the smaller of p, 1-p
+        p = (u >= 0.0f) ? e : 1.0f - e;
+        q = (u >= 0.0f) ? 1.0f - e : e;
+        if (u != u) { p = u; q = u; }                    // NaN in, NaN out
+        d = -((float)ks * 0.56418958354775628695f) * emu2;
     }
+}
+
+template <int NBm, int NAm, bool kGrad, class St, class Sc>
+__device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, const St &st, double kappa, bool hard,
+                                           float wc, const Sc &sc, int lane) {
+    const int NB = t.B.n_bslots, NA = t.B.n_slots - t.B.n_bslots, k = g.k;
+    const int64_t np = t.B.n_pos;
+    const int rr = t.valid ? t.r : 0;   // a row that exists for the reads of invalid lanes
+    // ---- reads: Boolean ids and atom records (slots past the template's count re-read its
+    // last one, so no read depends on a per-slot branch), then the state values they name
+    const int S = NB + NA;
+    int idb[NBm];
+#pragma unroll
+    for (int i = 0; i < NBm; ++i) idb[i] = t.sup[(int64_t)(i < S ? i : S - 1) * np];
+    AtomRec rec[NAm];
+    if (NA > 0) {
+#pragma unroll
+        for (int j = 0; j < NAm; ++j) rec[j] = load_rec(t.rec + (int64_t)(j < NA ? j : NA - 1) * np);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NAm; ++j) rec[j] = AtomRec{0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u};
+    }
+    float av[NBm], y0[NAm], y1[NAm];
+#pragma unroll
+    for (int i = 0; i < NBm; ++i) av[i] = st.av(rr, i < NB ? idb[i] : 0);
+#pragma unroll
+    for (int j = 0; j < NAm; ++j) {
+        // a run of atoms on the same variables reads their values once
+        const bool same = j > 0 && ((g.same_vars >> j) & 1u);
+        y0[j] = same ? y0[j - 1] : st.bv(rr, rec[j].v0);
+        y1[j] = same ? y1[j - 1] : st.bv(rr, rec[j].v1);   // v1 = v0 for one-variable atoms
+    }
+    // Booleans: P[True] = (1 - a)/2; literal-false probabilities l (negated literal: P[True])
+    float pb[NBm], qb[NBm], lb[NBm];
+#pragma unroll
+    for (int i = 0; i < NBm; ++i) {
+        pb[i] = (1.0f - av[i]) * 0.5f;
+        qb[i] = (1.0f + av[i]) * 0.5f;
+        lb[i] = ((g.neg >> i) & 1u) ? pb[i] : qb[i];
+    }
+    // atoms: q.b in FP64 in the stored multiply-then-add order, once per run of equal forms;
+    // only the coefficients (for the scatter), l and dp/dz stay live past this loop
+    const uint32_t negA = g.neg >> NB;
+    float la[NAm], da[NAm], c0[NAm], c1[NAm];
+    {
+        double lin = 0.0;
+#pragma unroll
+        for (int j = 0; j < NAm; ++j) {
+            const AtomRec &a = rec[j];
+            if (j == 0 || !((g.same_lin >> j) & 1u)) {
+#pragma clang fp contract(off)
+                double acc = 0.0;
+                const double p0 = (double)a.c0 * (double)y0[j];
+                acc = acc + p0;
+                if (a.flags & 2u) {
+                    const double p1 = (double)a.c1 * (double)y1[j];
+                    acc = acc + p1;
+                }
+                lin = acc;
+            }
+            float pj, qj;
+            gd_atom(lin, a.rhs, a.scale, (a.flags & 1u) != 0, kappa, hard, pj, qj, da[j]);
+            la[j] = ((negA >> j) & 1u) ? pj : qj;
+            c0[j] = a.c0;
+            c1[j] = a.c1;   // 0 for one-variable atoms
+        }
+    }
+    // ---- sum over the selector assignments
     float F = 0.0f, gp0 = 0.0f, gp1 = 0.0f;
-    float gl[KS];
+    float glb[NBm], gla[NAm];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) gl[s] = 0.0f;
+    for (int i = 0; i < NBm; ++i) glb[i] = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int j = 0; j < NAm; ++j) gla[j] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < (1 << kGdMaxSel); ++c) {
         if (c >= (1 << k)) break;
         const uint32_t m = g.mask[c];
         if (m >> 31) continue;   // this assignment reaches the True terminal
-        const float pi0 = k > 0 ? ((c & 1) ? p[0] : q[0]) : 1.0f;
-        const float pi1 = k > 1 ? ((c & 2) ? p[1] : q[1]) : 1.0f;
-        float pre[KS];
+        const uint32_t mA = m >> NB;
+        const float pi0 = k > 0 ? ((c & 1) ? pb[0] : qb[0]) : 1.0f;
+        const float pi1 = k > 1 ? ((c & 2) ? pb[1] : qb[1]) : 1.0f;
+        // factors: l where the slot is in the disjunction, else 1
+        float fb[NBm], fa[NAm], preb[NBm], prea[NAm];
         float prod = 1.0f;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            pre[s] = prod;
-            if (s < S && ((m >> s) & 1u)) prod *= l[s];
+        for (int i = 0; i < NBm; ++i) {
+            fb[i] = (i < NB && ((m >> i) & 1u)) ? lb[i] : 1.0f;
+            preb[i] = prod;
+            prod *= fb[i];
+        }
+#pragma unroll
+        for (int j = 0; j < NAm; ++j) {
+            fa[j] = (j < NA && ((mA >> j) & 1u)) ? la[j] : 1.0f;
+            prea[j] = prod;
+            prod *= fa[j];
         }
         F += (pi0 * pi1) * prod;
         if constexpr (kGrad) {
             float suf = pi0 * pi1;
 #pragma unroll
-            for (int s = KS - 1; s >= 0; --s) {
-                if (s < S && ((m >> s) & 1u)) {
-                    gl[s] += pre[s] * suf;
-                    suf *= l[s];
-                }
+            for (int j = NAm - 1; j >= 0; --j) {
+                if (j < NA && ((mA >> j) & 1u)) gla[j] += prea[j] * suf;
+                suf *= fa[j];
+            }
+#pragma unroll
+            for (int i = NBm - 1; i >= 0; --i) {
+                if (i < NB && ((m >> i) & 1u)) glb[i] += preb[i] * suf;
+                suf *= fb[i];
             }
             if (k > 0) gp0 += ((c & 1) ? pi1 : -pi1) * prod;
             if (k > 1) gp1 += ((c & 2) ? pi0 : -pi0) * prod;
         }
     }
     if constexpr (kGrad) {
-        // G_s = dF/dp_s: a negated literal's l is p (dl/dp = 1), a positive one's is 1 - p
-        float G[KS];
+        const float wv = t.valid ? wc : 0.0f;
+        // Boolean slots (distinct variables): G = dF/dp (a negated literal's l is p, a
+        // positive one's 1 - p; a selector's from the sum above), dp/da = -1/2
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            G[s] = ((g.neg >> s) & 1u) ? gl[s] : -gl[s];
-            if (s == 0 && k > 0) G[s] = gp0;
-            if (s == 1 && k > 1) G[s] = gp1;
-        }
-        // Boolean slots: distinct variables within a constraint; dp/da = -1/2
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            if (s < NB) {
-                const float gv = t.valid ? wc * G[s] * -0.5f : 0.0f;
-                sc.add_a(t.r, t.valid ? id[s] : -1, gv, lane);
+        for (int i = 0; i < NBm; ++i) {
+            if (i < NB) {
+                float G = ((g.neg >> i) & 1u) ? glb[i] : -glb[i];
+                if (i == 0 && k > 0) G = gp0;
+                if (i == 1 && k > 1) G = gp1;
+                sc.add_a(t.r, t.valid ? idb[i] : -1, wv * G * -0.5f, lane);
             }
         }
-        if (kInl || t.rec) {
-            // atoms: consecutive atoms on the same variables are summed before the scatter
-            int v0 = -1, v1 = -1;
-            float g0 = 0.0f, g1 = 0.0f;
+        // atoms: dz = w dF/dp dp/dz, summed over a run of atoms on the same variables and
+        // scattered at the run's end (its variables read again from the record)
+        float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                if (s >= NB && s < S) {
-                    AtomRec a;
-                    a.v0 = a.v1 = -1;
-                    a.c0 = a.c1 = 0.0f;
-                    a.flags = 0;
-                    if (t.valid) a = load_rec(t.rec + (int64_t)(s - NB) * np);
-                    const float gz = t.valid ? wc * G[s] * d[s] : 0.0f;
-                    const bool n0 = a.v0 != v0, n1 = a.v1 != v1;
-                    sc.add_b(t.r, n0 ? v0 : -1, n0 ? g0 : 0.0f, lane);
-                    sc.add_b(t.r, n1 ? v1 : -1, n1 ? g1 : 0.0f, lane);
-                    if (n0) { v0 = a.v0; g0 = 0.0f; }
-                    if (n1) { v1 = a.v1; g1 = 0.0f; }
-                    g0 += gz * a.c0;
-                    if (a.flags & 2u) g1 += gz * a.c1;
-                }
-            }
-            sc.add_b(t.r, v0, g0, lane);
-            sc.add_b(t.r, v1, g1, lane);
-        } else if (t.valid) {
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                if (s >= NB && s < S) {
-                    const float gz = wc * G[s] * d[s];
-                    if (gz != 0.0f) {
-                        const int ka = t.sup[(int64_t)s * np] - T.n_bool;
-                        for (int e = T.atom_ptr[ka]; e < T.atom_ptr[ka + 1]; ++e)
-                            sc.add_b_direct(t.r, T.atom_var[e], gz * (float)T.atom_coef[e]);
-                    }
+        for (int j = 0; j < NAm; ++j) {
+            if (j < NA) {
+                const float G = ((negA >> j) & 1u) ? gla[j] : -gla[j];
+                const float gz = wv * G * da[j];
+                g0 += gz * c0[j];
+                g1 += gz * c1[j];
+                const bool last = j + 1 >= NA || !((g.same_vars >> (j + 1)) & 1u);
+                if (last) {
+                    const u32x2 vv = *(cptr<u32x2>)(t.rec + (int64_t)j * np);
+                    sc.add_b(t.r, t.valid ? (int)vv.x : -1, g0, lane);
+                    sc.add_b(t.r, t.valid ? (int)vv.y : -1, g1, lane);   // g1 = 0 for one variable
+                    g0 = g1 = 0.0f;
                 }
             }
         }
     }
     return t.valid ? F : 0.0f;
-}
-
-// Guarded disjunction of the task's bucket: a short variant for supports of up to 4 slots
-// (clauses), the full one up to kGdMaxSlots.
-template <bool kGrad, bool kInl, class St, class Sc>
-__device__ __forceinline__ float gd_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
-                                         float wc, const Sc &sc, int lane) {
-    const GdInfo g = load_gd(T.gd + t.B.tpl);
-    if (t.B.n_slots <= 4) return gd_eval_n<4, kGrad, kInl>(T, t, g, st, kappa, hard, wc, sc, lane);
-    return gd_eval_n<kGdMaxSlots, kGrad, kInl>(T, t, g, st, kappa, hard, wc, sc, lane);
 }
 
 // Message-store variants: a kernel is instantiated per variant and the host picks the
@@ -781,16 +826,24 @@ __device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, in
     bind_msgs(W, base, NN, SS, lane, W##_m, W##_b, W##_p, W##_q, W##_d, W##_g)
 
 // One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
-// scattered through the policy. Kernels are instantiated with kPair only for launches that
-// hold closed-form templates (pair or guarded disjunctions; the closed-form paths add
-// registers); there a register store is declared per task, so its arrays are live only in
-// the generic branch.
-template <bool kGrad, bool kPair, class St, class Sc, class Ms>
+// scattered through the policy. With kCF > 0 a register message store is declared per task,
+// so its arrays are live only in the generic branch.
+template <bool kGrad, int kCF, class St, class Sc, class Ms>
 __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
                                            float wc, const Sc &sc, Ms &W, int lane) {
-    if constexpr (kPair) {
-        if (t.B.pad > 0) return pair_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
-        if (t.B.pad < 0) return gd_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
+    if constexpr (kCF > 0) {
+        if constexpr (kCF >= 3) {
+            if (t.B.pad > 0) return pair_eval<kGrad, Ms::kInlineOnly>(T, t, st, kappa, hard, wc, sc, lane);
+        }
+        if (t.B.pad < 0) {
+            const GdInfo g = load_gd(T.gd + t.B.tpl);
+            const int NB = t.B.n_bslots, NA = t.B.n_slots - t.B.n_bslots;
+            if (NB <= 1 && NA <= 2) return gd_eval_n<1, 2, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+            if constexpr (kCF >= 2) {
+                if (NB <= 2) return gd_eval_n<2, kGdMaxAtoms, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+            }
+            if constexpr (kCF >= 3) return gd_eval_n<kGdMaxBool, kGdMaxAtoms, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+        }
         if constexpr (Ms::kNodes > 0) {
             FSMT_MSG_STORE(Ms, Wt, nullptr, 0, 0, lane);
             const float unsat = task_forward(T, t, st, kappa, hard, Wt);
@@ -810,8 +863,8 @@ __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, c
 inline bool lds_store(const fsmt_xbdd *h) {
     return h->lds_messages || ((h->n_pair > 0 || h->n_gd > 0) && h->small_max_nodes > 0);
 }
-// Kernels carry the closed-form families (pair and guarded disjunctions) for such instances.
-inline bool closed_forms(const fsmt_xbdd *h) { return h->n_pair > 0 || h->n_gd > 0; }
+// Closed-form level an instance needs (see gd_level_of; 0 when it has no closed-form template).
+inline int closed_level(const fsmt_xbdd *h) { return h->n_pair > 0 ? 3 : h->gd_level; }
 
 // Register variants need every atom in an inline record (the CSR path is compiled out).
 inline int msg_variant(int max_nodes, int max_slots, bool lds_only, bool all_inline) {

@@ -51,14 +51,24 @@ constexpr int kPairMaxL = 10, kPairMaxT = 4;
 //   F = sum_g pi_g prod_{s in S_g} l_s,   pi_g = prod_{i < k} P[slot i = g_i],
 // with l_s = P[literal s False], evaluated in closed form (see gd_eval) for supports of at
 // most kGdMaxSlots slots.
-constexpr int kGdMaxSel = 2, kGdMaxSlots = 12;
+// Selectors are Boolean slots; the evaluation keeps every slot in registers, so the family is
+// bounded to kGdMaxBool Boolean and kGdMaxAtoms atom slots, each atom with an inline record.
+constexpr int kGdMaxSel = 2, kGdMaxBool = 4, kGdMaxAtoms = 8;
 struct GdInfo {
     uint32_t mask[4];   // per selector assignment g (bit i = value of selector i): slots of its
                         // disjunction; bit 31 set: the assignment reaches the True terminal
     uint32_t neg;       // slots whose literal is negated (False iff the variable is True)
     int32_t k;          // selector slots (slots 0 .. k-1)
-    int32_t pad[2];
+    uint32_t same_vars; // bit j: atom slot j has the variables of atom slot j-1 in every constraint
+                        // of the template (their values are read once, their gradients summed)
+    uint32_t same_lin;  // bit j: ... and the same coefficients (q.y is computed once)
 };
+// Closed-form levels a kernel carries (chosen by the host from the instances of a launch, so
+// that a kernel holds only the register footprint it needs): 0 none; 1 guarded disjunctions
+// of at most one Boolean and two atom slots (clauses, feasibility ITEs); 2 also two Boolean
+// selectors over up to kGdMaxAtoms atoms; 3 every guarded disjunction and the pair
+// disjunctions.
+inline int gd_level_of(int n_bslots, int n_aslots) { return (n_bslots <= 1 && n_aslots <= 2) ? 1 : n_bslots <= 2 ? 2 : 3; }
 // Unit-atom half-spaces that share no variable, each over at most this many distinct
 // variables, are projected onto in closed form (project_dykstra) instead of by sweeps.
 constexpr int kSeparableRowMax = 4;
@@ -145,6 +155,7 @@ struct fsmt_xbdd {
     int hs_separable = 0;   // one colour class, rows of at most kSeparableRowMax distinct variables
     int64_t n_pair = 0;               // constraints evaluated as pair disjunctions (closed form)
     int64_t n_gd = 0;                 // constraints evaluated as guarded disjunctions (closed form)
+    int gd_level = 0;                 // largest closed-form level of its guarded disjunctions (1..3)
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record
     std::vector<fsmt::TplInfo> h_tpl;

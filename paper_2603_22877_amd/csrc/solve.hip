@@ -155,17 +155,19 @@ __device__ __forceinline__ float read_partials2(float *g, gptr<float> buf, int64
     return (0.0f + o0) + o1;
 }
 
-// Waves per workgroup of the solver kernel for each message variant: register-resident
-// messages of the medium bound take about 200 VGPRs (8 waves per workgroup), those of the
-// large bound all 256 (one wave per SIMD, 4 waves per workgroup).
-template <int V> struct SolveWaves { static constexpr int value = 16; };
-template <> struct SolveWaves<kMsgMedium> { static constexpr int value = 8; };
-template <> struct SolveWaves<kMsgLarge> { static constexpr int value = 4; };
+// Waves per workgroup of the solver kernel for each message variant and closed-form level:
+// register-resident messages of the medium bound take about 200 VGPRs (8 waves per
+// workgroup), those of the large bound all 256 (one wave per SIMD, 4 waves per workgroup);
+// the closed forms of two selectors over eight atoms need more than the 128 VGPRs that 16
+// waves leave (8 waves).
+template <int V, int kCF> struct SolveWaves { static constexpr int value = kCF >= 2 ? 8 : 16; };
+template <int kCF> struct SolveWaves<kMsgMedium, kCF> { static constexpr int value = 8; };
+template <int kCF> struct SolveWaves<kMsgLarge, kCF> { static constexpr int value = 4; };
 
 // kCluster: k workgroups per restart (k read from the descriptor); otherwise k = 1 and the
 // kernel carries none of the cluster's exchange state.
-template <int V, bool kCluster, bool kPair>
-__global__ void __launch_bounds__(64 * SolveWaves<V>::value)
+template <int V, bool kCluster, int kCF>
+__global__ void __launch_bounds__((64 * SolveWaves<V, kCF>::value))
     solve_wg_kernel(const InstDesc *insts, SolveParams P, int32_t *stop_flags, int32_t *abort_flag) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
@@ -226,7 +228,7 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             for (int task = rank + k * wave; task < n_tasks; task += k * P.waves) {
                 const TaskCtx t = task_ctx(T, task * 64 + lane, r, true);
                 const float wc = t.valid ? wload(t.c) : 0.0f;   // requested before the forward pass
-                oacc += wc * task_eval<true, kPair>(T, t, st, kappa, hard, wc, sc, W, lane);
+                oacc += wc * task_eval<true, kCF>(T, t, st, kappa, hard, wc, sc, W, lane);
             }
             if (kCluster) {
                 // publish this workgroup's partial gradient and objective, then sum the
@@ -287,12 +289,25 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
             if (red.y <= P.eps2) break;
         }
         if (aborted) break;
-        // rounding, exact check and ERWA (Alg. "CLS with Annealing"): rank 0 of the cluster
+        // rounding, exact check and ERWA (Alg. "CLS with Annealing"): every rank of the
+        // cluster checks its share of the constraints (64-constraint blocks dealt round-robin
+        // over ranks and waves). The violated counts and the sums of the updated weights are
+        // exchanged like the partial gradients; only then does each rank store its share's new
+        // history and (normalized) weights, recomputed from its check bits, so a cluster that
+        // gives up at the exchange leaves the weights of the last completed level.
         int stop = 0;
-        if (rank == 0) {
+        {
             const bool update = ((level + 1) % P.tau) == 0;
+            auto erwa = [&](bool sat, float h0, float w0, float &h, float &wv) {
+                h = P.rho * h0 + (sat ? 0.0f : 1.0f);
+                wv = w0;
+                if (update) {
+                    wv *= powf(P.gamma, h);
+                    h = 1.0f;
+                }
+            };
             float nu_acc = 0.0f, wsum = 0.0f;
-            for (int c0 = wave * 64; c0 < C; c0 += P.waves * 64) {
+            for (int c0 = (rank + k * wave) * 64; c0 < C; c0 += k * P.waves * 64) {
                 const int c = c0 + lane;
                 const bool sat = c < C ? walk_state(T, st, c, r) : false;
                 const uint64_t mask = __ballot(sat);
@@ -301,51 +316,68 @@ __global__ void __launch_bounds__(64 * SolveWaves<V>::value)
                     if ((c0 >> 5) + 1 < nw) brow[(c0 >> 5) + 1] = (uint32_t)(mask >> 32);
                 }
                 if (c < C) {
-                    const float viol = sat ? 0.0f : 1.0f;
-                    float h = P.rho * hrow[c] + viol;
-                    float wv = wload(c);
-                    if (update) {
-                        wv *= powf(P.gamma, h);
-                        h = 1.0f;
-                        wstore(c, wv);
-                    }
-                    hrow[c] = h;
+                    float h, wv;
+                    erwa(sat, hrow[c], wload(c), h, wv);
                     wsum += wv;
-                    nu_acc += viol;
+                    nu_acc += sat ? 0.0f : 1.0f;
                 }
             }
-            n_unsat = (int)block_sum(nu_acc);
-            if (update && P.normalize) {
-                const float ws = block_sum(wsum);
-                const float scale = (float)C / ws;
-                for (int c = threadIdx.x; c < C; c += blockDim.x) wstore(c, wload(c) * scale);
+            float2 tot = block_sum2(nu_acc, wsum);   // also orders the bit stores before the reads below
+            if (kCluster) {
+                const gptr<float> buf = prow + (int64_t)xpar * k * pstride;
+                xpar ^= 1;
+                if (threadIdx.x == 0) {
+                    publish(buf + (int64_t)rank * pstride, tot.x);
+                    publish(buf + (int64_t)rank * pstride + 1, tot.y);
+                }
+                bar_target += k;
+                if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag, P.spin_limit)) {
+                    aborted = true;
+                    break;
+                }
+                tot = make_float2(0.0f, 0.0f);
+                for (int q = 0; q < k; ++q) {   // rank order: every rank gets the same sums
+                    tot.x += fetch(buf + (int64_t)q * pstride);
+                    tot.y += fetch(buf + (int64_t)q * pstride + 1);
+                }
             }
-            if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
-            stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
-            // the level is complete: its point and counters go to memory together with the
-            // weights just written, so a call that ends early (a cluster that gives up
-            // below) leaves a state that a later call resumes consistently
-            for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
-            for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
-            if (threadIdx.x == 0) {
-                I.level_done[r] = level + 1;
-                I.steps_done[r] = steps_done;
-                I.n_unsat[r] = n_unsat;
-                I.obj[r] = obj;
-                I.verdict[r] = n_unsat == 0 ? 1 : verdict;
+            n_unsat = (int)tot.x;
+            const float scale = (update && P.normalize) ? (float)C / tot.y : 1.0f;
+            for (int c0 = (rank + k * wave) * 64; c0 < C; c0 += k * P.waves * 64) {
+                const int c = c0 + lane;
+                if (c < C) {
+                    const bool sat = (brow[c >> 5] >> (c & 31)) & 1u;
+                    float h, wv;
+                    erwa(sat, hrow[c], wload(c), h, wv);
+                    hrow[c] = h;
+                    if (update) wstore(c, (update && P.normalize) ? wv * scale : wv);
+                }
             }
-            if (kCluster && threadIdx.x == 0) {
-                publish(I.ctl + 4 * r + 2 * lpar, n_unsat);
-                publish(I.ctl + 4 * r + 2 * lpar + 1, stop);
+            if (rank == 0) {
+                if (n_unsat == 0 && P.stop_mode == 2 && threadIdx.x == 0) atomicExch(stop_flags + ii, 1);
+                stop = (P.stop_mode == 2 && __syncthreads_or(threadIdx.x == 0 && atomicAdd(stop_flags + ii, 0) != 0)) ? 1 : 0;
+                // the level is complete: its point and counters go to memory (the other ranks'
+                // weights are stored before they reach the barrier below, so a call that ends
+                // there leaves a state that a later call resumes consistently)
+                for (int i = threadIdx.x; i < n; i += blockDim.x) I.a[(int64_t)r * I.a_sr + i] = sa[i];
+                for (int j = threadIdx.x; j < m; j += blockDim.x) I.b[(int64_t)r * I.b_sr + j] = sb[j];
+                if (threadIdx.x == 0) {
+                    I.level_done[r] = level + 1;
+                    I.steps_done[r] = steps_done;
+                    I.n_unsat[r] = n_unsat;
+                    I.obj[r] = obj;
+                    I.verdict[r] = n_unsat == 0 ? 1 : verdict;
+                }
+                if (kCluster && threadIdx.x == 0) publish(I.ctl + 4 * r + 2 * lpar + 1, stop);
             }
         }
+        if (aborted) break;
         if (kCluster) {
             bar_target += k;
             if (!cluster_sync<V == kMsgSmall>(I.bar + r, bar_target, abort_flag, P.spin_limit)) {
                 aborted = true;
                 break;
             }
-            n_unsat = fetch(I.ctl + 4 * r + 2 * lpar);
             stop = fetch(I.ctl + 4 * r + 2 * lpar + 1);
             lpar ^= 1;
         }
@@ -365,20 +397,23 @@ static fsmt_status launch_status(const char *what) {
     return FSMT_OK;
 }
 
-template <int V, bool kPair>
+template <int V, int kCF>
 static const void *solve_kernel_fn_v(bool cl) {
-    return cl ? (const void *)solve_wg_kernel<V, true, kPair> : (const void *)solve_wg_kernel<V, false, kPair>;
+    return cl ? (const void *)solve_wg_kernel<V, true, kCF> : (const void *)solve_wg_kernel<V, false, kCF>;
 }
-template <bool kPair>
+template <int kCF>
 static const void *solve_kernel_fn_p(int msg, bool cl) {
-    if (msg == kMsgSmall) return solve_kernel_fn_v<kMsgSmall, kPair>(cl);
-    if (msg == kMsgMedium) return solve_kernel_fn_v<kMsgMedium, kPair>(cl);
-    if (msg == kMsgLarge) return solve_kernel_fn_v<kMsgLarge, kPair>(cl);
-    return solve_kernel_fn_v<kMsgLds, kPair>(cl);
+    if (msg == kMsgSmall) return solve_kernel_fn_v<kMsgSmall, kCF>(cl);
+    if (msg == kMsgMedium) return solve_kernel_fn_v<kMsgMedium, kCF>(cl);
+    if (msg == kMsgLarge) return solve_kernel_fn_v<kMsgLarge, kCF>(cl);
+    return solve_kernel_fn_v<kMsgLds, kCF>(cl);
 }
-// The persistent solver kernel for a message variant, cluster mode and pair-disjunction path.
-static const void *solve_kernel_fn(int msg, bool cl, bool pair) {
-    return pair ? solve_kernel_fn_p<true>(msg, cl) : solve_kernel_fn_p<false>(msg, cl);
+// The persistent solver kernel for a message variant, cluster mode and closed-form level.
+static const void *solve_kernel_fn(int msg, bool cl, int cf) {
+    return cf == 0 ? solve_kernel_fn_p<0>(msg, cl)
+           : cf == 1 ? solve_kernel_fn_p<1>(msg, cl)
+           : cf == 2 ? solve_kernel_fn_p<2>(msg, cl)
+                     : solve_kernel_fn_p<3>(msg, cl);
 }
 
 // Dynamic LDS a persistent workgroup may take: the device's per-block maximum (opted into
@@ -395,7 +430,7 @@ static int lds_budget_bytes() {
         std::vector<const void *> fns;
         for (int msg : {kMsgLds, kMsgSmall, kMsgMedium, kMsgLarge})
             for (int cl = 0; cl < 2; ++cl)
-                for (int pair = 0; pair < 2; ++pair) fns.push_back(solve_kernel_fn(msg, cl != 0, pair != 0));
+                for (int cf = 0; cf < 4; ++cf) fns.push_back(solve_kernel_fn(msg, cl != 0, cf));
         size_t static_lds = 0;
         for (const void *f : fns) {
             hipFuncAttributes fa{};
@@ -414,10 +449,10 @@ static int lds_budget_bytes() {
     return budget;
 }
 
-static int solve_waves(int msg) {
-    return msg == kMsgMedium  ? SolveWaves<kMsgMedium>::value
-           : msg == kMsgLarge ? SolveWaves<kMsgLarge>::value
-                              : SolveWaves<kMsgSmall>::value;
+static int solve_waves(int msg, int cf) {
+    if (msg == kMsgMedium) return SolveWaves<kMsgMedium, 0>::value;
+    if (msg == kMsgLarge) return SolveWaves<kMsgLarge, 0>::value;
+    return cf >= 2 ? SolveWaves<kMsgSmall, 2>::value : SolveWaves<kMsgSmall, 0>::value;
 }
 
 static size_t state_floats_of(const fsmt_xbdd *h) {
@@ -516,7 +551,7 @@ static bool prefer_grid(const fsmt_xbdd *h, int R, int64_t R_batch, int waves_a,
 struct PersistentGeom {
     int msg = kMsgSmall, waves = 0, maxn = 0, maxs = 1;
     size_t state_f = 0, wave_bytes = 0, lds = 0;
-    bool pair = false;
+    int cf = 0;
 };
 
 static PersistentGeom persistent_geom(const fsmt_xbdd *const *insts, const std::vector<int> &ids, size_t budget) {
@@ -529,7 +564,7 @@ static PersistentGeom persistent_geom(const fsmt_xbdd *const *insts, const std::
         G.maxs = std::max(G.maxs, h->small_max_slots);
         lds_only = lds_only || lds_store(h);
         all_inline = all_inline && h->all_inline;
-        G.pair = G.pair || closed_forms(h);
+        G.cf = std::max(G.cf, closed_level(h));
     }
     G.msg = msg_variant(G.maxn, G.maxs, lds_only, all_inline);
     G.wave_bytes = G.msg == kMsgLds ? WaveScratch::bytes(G.maxn + 2, G.maxs) : 0;
@@ -537,9 +572,9 @@ static PersistentGeom persistent_geom(const fsmt_xbdd *const *insts, const std::
     if (state_bytes > budget) {
         G.waves = 0;
     } else if (G.wave_bytes) {
-        G.waves = (int)std::min<size_t>(16, (budget - state_bytes) / G.wave_bytes);
+        G.waves = (int)std::min<size_t>(solve_waves(G.msg, G.cf), (budget - state_bytes) / G.wave_bytes);
     } else {
-        G.waves = solve_waves(G.msg);
+        G.waves = solve_waves(G.msg, G.cf);
     }
     G.lds = state_bytes + (size_t)G.waves * G.wave_bytes;
     return G;
@@ -677,7 +712,7 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
         }
         const int msg = G.msg, waves = G.waves;
         const size_t lds = G.lds;
-        auto kernel_of = [&](bool cl) -> const void * { return solve_kernel_fn(msg, cl, G.pair); };
+        auto kernel_of = [&](bool cl) -> const void * { return solve_kernel_fn(msg, cl, G.cf); };
         auto resident_of = [&](bool cl) -> int64_t {
             int occ = 1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel_of(cl), 64 * waves, lds) != hipSuccess) {
@@ -908,8 +943,8 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
                                                     : 0;
                 plan.check_blocks = checks;
                 plan.use_graph = true;
-                plan.pair = false;
-                for (size_t q = 0; q < ib.size(); ++q) plan.pair = plan.pair || closed_forms(insts[ib[q]]);
+                plan.cf = 0;
+                for (size_t q = 0; q < ib.size(); ++q) plan.cf = std::max(plan.cf, closed_level(insts[ib[q]]));
                 // each replay of the level sequence advances every running restart by one
                 // level (the kernels read each restart's level from memory and skip finished
                 // restarts); levels below level_begin are complete by the caller's word, so

@@ -56,7 +56,7 @@ __global__ void grid_begin_kernel(const GridInst *insts, int n_inst, GridShared 
 }
 
 // Forward + reverse sweep over every instance's (constraint, restart) lanes.
-template <int V, bool kPair>
+template <int V, int kCF>
 __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, int n_inst, GridShared S) {
     using Ms = typename MsgOf<V>::type;
     extern __shared__ float lds[];
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         const double kappa = t.valid ? S.kappas[I.level_done[r]] : 0.0;
         const bool hard = isinf(kappa);
         const float wc = t.valid ? I.w[(int64_t)r * T.n_cons + t.c] : 0.0f;   // requested before the forward pass
-        const float unsat = task_eval<true, kPair>(T, t, st, kappa, hard, wc, sc, W, lane);
+        const float unsat = task_eval<true, kCF>(T, t, st, kappa, hard, wc, sc, W, lane);
         if (I.R_pad <= 64) {
             oacc += wc * unsat;
         } else if (r < I.R && wc * unsat != 0.0f) {
@@ -269,17 +269,17 @@ static fsmt_status launch_status(const char *what) {
 }
 
 // Enqueue one level's kernel sequence on st.
-template <bool kPair>
+template <int kCF>
 static void launch_sweep(const GridPlan &P, dim3 g, dim3 b, hipStream_t st, const GridInst *d_insts, int n_inst,
                          const GridShared &S) {
     if (P.msg == kMsgSmall)
-        hipLaunchKernelGGL((grid_sweep_kernel<kMsgSmall, kPair>), g, b, 0, st, d_insts, n_inst, S);
+        hipLaunchKernelGGL((grid_sweep_kernel<kMsgSmall, kCF>), g, b, 0, st, d_insts, n_inst, S);
     else if (P.msg == kMsgMedium)
-        hipLaunchKernelGGL((grid_sweep_kernel<kMsgMedium, kPair>), g, b, 0, st, d_insts, n_inst, S);
+        hipLaunchKernelGGL((grid_sweep_kernel<kMsgMedium, kCF>), g, b, 0, st, d_insts, n_inst, S);
     else if (P.msg == kMsgLarge)
-        hipLaunchKernelGGL((grid_sweep_kernel<kMsgLarge, kPair>), g, b, 0, st, d_insts, n_inst, S);
+        hipLaunchKernelGGL((grid_sweep_kernel<kMsgLarge, kCF>), g, b, 0, st, d_insts, n_inst, S);
     else
-        hipLaunchKernelGGL((grid_sweep_kernel<kMsgLds, kPair>), g, b, P.sweep_lds, st, d_insts, n_inst, S);
+        hipLaunchKernelGGL((grid_sweep_kernel<kMsgLds, kCF>), g, b, P.sweep_lds, st, d_insts, n_inst, S);
 }
 
 static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const GridShared &S, const GridPlan &P,
@@ -289,10 +289,14 @@ static fsmt_status enqueue_level(const GridInst *d_insts, int n_inst, const Grid
     if ((rc = launch_status("grid begin"))) return rc;
     for (int k = 0; k < P.steps; ++k) {
         const dim3 g(P.sweep_blocks), b(64 * P.sweep_wpb);
-        if (P.pair)
-            launch_sweep<true>(P, g, b, st, d_insts, n_inst, S);
+        if (P.cf == 0)
+            launch_sweep<0>(P, g, b, st, d_insts, n_inst, S);
+        else if (P.cf == 1)
+            launch_sweep<1>(P, g, b, st, d_insts, n_inst, S);
+        else if (P.cf == 2)
+            launch_sweep<2>(P, g, b, st, d_insts, n_inst, S);
         else
-            launch_sweep<false>(P, g, b, st, d_insts, n_inst, S);
+            launch_sweep<3>(P, g, b, st, d_insts, n_inst, S);
         if ((rc = launch_status("grid sweep"))) return rc;
         if (P.level_blocks > 0) {
             hipLaunchKernelGGL(grid_level_kernel, dim3(P.level_blocks), dim3(64 * P.level_wpb), P.level_lds, st, d_insts,

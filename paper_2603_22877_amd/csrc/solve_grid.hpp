@@ -46,7 +46,7 @@ struct GridPlan {
     size_t sweep_lds, step_lds;
     int64_t check_blocks;
     bool use_graph;
-    bool pair;                      // some instance has pair-disjunction templates
+    int cf;                         // closed-form level of the sweep (largest over the instances)
 };
 
 // An instantiated level graph whose replays may still be running: destroyed once the event

@@ -221,8 +221,8 @@ static GdInfo gd_family(const Template &T) {
     GdInfo g{};
     g.k = -1;
     const int N = T.n_nodes;
-    if (N == 0 || T.n_slots > kGdMaxSlots) return g;
-    for (int k = 0; k <= std::min(kGdMaxSel, T.n_slots); ++k) {
+    if (N == 0 || T.n_bslots > kGdMaxBool || T.n_slots - T.n_bslots > kGdMaxAtoms) return g;
+    for (int k = 0; k <= std::min(kGdMaxSel, T.n_bslots); ++k) {   // selectors are Booleans
         bool ok = true;
         uint32_t neg = 0, seen = 0, mask[4] = {0, 0, 0, 0};
         for (int c = 0; c < (1 << k) && ok; ++c) {
@@ -505,6 +505,40 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         for (int64_t e = e0; e < e1 && ok; ++e) ok = (double)(float)a_coef[e] == a_coef[e];
         return ok;
     };
+    // guarded disjunctions keep their atoms in inline records (every atom of every member
+    // must qualify, else the template takes the generic passes); the run flags record which
+    // consecutive atom slots share variables (and coefficients) in every member
+    for (int t = 0; t < T; ++t) {
+        Template &tp = tpls[t];
+        if (tp.gd.k < 0 || members[t].empty()) continue;
+        const int nb = tp.n_bslots, na = tp.n_slots - tp.n_bslots;
+        bool ok = true;
+        uint32_t same_vars = 0, same_lin = 0;
+        for (int j = 1; j < na; ++j) same_vars |= 1u << j;
+        same_lin = same_vars;
+        for (int c : members[t]) {
+            const int32_t *ids = con_ids.data() + con_sup_off[c];
+            for (int j = 0; j < na && ok; ++j) {
+                const int kj = ids[nb + j] - n;
+                ok = atom_inline_ok(kj);
+                if (!ok || j == 0) continue;
+                const int ki = ids[nb + j - 1] - n;
+                const int ni = a_ptr[ki + 1] - a_ptr[ki], nj = a_ptr[kj + 1] - a_ptr[kj];
+                const int ei = a_ptr[ki], ej = a_ptr[kj];
+                const bool vars = ni == nj && a_var[ei] == a_var[ej] && (ni < 2 || a_var[ei + 1] == a_var[ej + 1]);
+                const bool coef = vars && a_coef[ei] == a_coef[ej] && (ni < 2 || a_coef[ei + 1] == a_coef[ej + 1]);
+                if (!vars) same_vars &= ~(1u << j);
+                if (!coef) same_lin &= ~(1u << j);
+            }
+            if (!ok) break;
+        }
+        if (!ok) {
+            tp.gd.k = -1;
+            continue;
+        }
+        tp.gd.same_vars = same_vars;
+        tp.gd.same_lin = same_lin;
+    }
     std::vector<TplInfo> tinfo(T);
     std::vector<GdInfo> gd_rec(T);
     std::vector<Node> nodes;
@@ -527,6 +561,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             h->n_pair += (int64_t)members[t].size();   // closed form: no message store, never big
         } else if (tp.gd.k >= 0) {
             h->n_gd += (int64_t)members[t].size();     // likewise
+            h->gd_level = std::max(h->gd_level, gd_level_of(tp.n_bslots, tp.n_slots - tp.n_bslots));
         } else if (big_diagram(tp.n_nodes, tp.n_slots)) {
             h->big_max_nodes = std::max(h->big_max_nodes, tp.n_nodes);
             h->big_max_slots = std::max(h->big_max_slots, tp.n_slots);
