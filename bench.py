@@ -1,9 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the FourierSMT hot path on one MI355X.
 
-Workload: job-shop scheduling, 200 jobs on 10 machines (~2,000 order Booleans, ~4,100
-constraints), 64 restarts, seeded synthetic instances (the paper's instances are not
-public; the generator is in workloads/scheduling.py).
+Workload of the main line: placement of 1,200 rectangles with rotation bits (721,800
+constraints: 719,400 pairwise non-overlap ITEs over eight separation atoms and 2,400
+feasibility ITEs; 1,200 Booleans, 2,400 reals), 16 restarts, seeded synthetic instance (the
+paper's instances are not public; the generator is in workloads/placement.py). This is the
+size of the paper's scale claim (about 700,000 constraints).
 
 * value: constraint-evals/s of the fused batched solver. A step is one annealing level:
   100 PGD iterations, each the literal probabilities, forward + reverse sweep with the
@@ -11,18 +13,24 @@ public; the generator is in workloads/scheduling.py).
   check and the ERWA weight update. One constraint-eval = one (constraint, restart)
   forward + backward; evals per step = C x R x 100. Inputs are resident on the device
   before the timed region; no early exit (eps = 0, no stop on SAT) so the work is fixed.
-* time_to_sat: solver wall time until a SAT verdict (from each solve launch to the host
-  reading the verdict; initial points drawn and uploaded outside the clock), batched fused
-  (64 restarts in one launch) against the plain per-call path (one restart at a time,
-  separate launches per step),
-  same hyperparameters, median and PAR-2 over instance seeds; time_to_sat_index_encoding:
-  the same comparison on the paper's scheduling encoding (16 workers x 32 jobs), where a
-  single restart rarely reaches SAT.
-* roofline: the solver kernel's duration from HIP events on its stream; algorithmic
-  FLOP and byte counts per launch (the per-eval model in algorithmic_cost and
-  flops_per_pass / bytes_per_pass below).
-* cpu_baseline: the FP64 oracle on a bounded sample (~10 s, one thread);
-  cpu_baseline_all_cores: the same on up to 16 host threads.
+* roofline: the solver kernel's duration from HIP events on its stream (the launch is the
+  kernel: one persistent launch per call); algorithmic bytes per PGD iteration T + R S
+  (compiled tables once per pass over the restarts, plus each restart's state) and
+  modelled FLOPs per constraint-eval (flops_per_pass), against the HBM peak and the FP32
+  FMA issue rate without packed math; `bound` names the larger fraction. `traffic` is the
+  measured HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) of the committed rocprofv3
+  summary, per iteration, times the launch's iterations.
+* time_to_sat: solver wall time until a SAT verdict on job-shop scheduling 200 jobs x 10
+  machines (from each solve launch to the host reading the verdict; initial points drawn
+  and uploaded outside the clock), batched fused (64 restarts in one launch) against the
+  plain per-call path (one restart at a time, separate launches per step), same
+  hyperparameters, median and PAR-2 over instance seeds; time_to_sat_index_encoding: the
+  same comparison on the paper's scheduling encoding (16 workers x 32 jobs), where a single
+  restart rarely reaches SAT.
+* other_workloads: fixed-work rates of the same solver on scheduling 200 x 10 (64 restarts)
+  and the uneven batch of 48 instances (16 restarts each, 2.0M constraints).
+* cpu_baseline: the FP64 oracle on a bounded sample of the main workload (~10 s, one
+  thread); cpu_baseline_all_cores: the same on up to 16 host threads.
 * paper_protocol: the paper's gradient-timing protocol (Supplementary Note "Gradient
   Computation Time"): random hybrid instances with n Booleans, n reals and n atoms, 100
   annealing parameters x 100 points, one cop_backward call (objective + gradient) per
@@ -34,6 +42,7 @@ Other modes (each prints its own JSON line instead of the main one):
 * --suite scheduling|placement: PAR-2 of the fused solver on the paper's own encodings
   (Booleanized worker / macro / layer indices, XOR disjunctions; workloads/paper_suite.py).
 * --scale-mode: fixed-work fused-solver throughput at the largest sizes of those suites.
+* --configs-mode: fixed-work rates on placement 150 x 256 restarts and time-to-SAT there.
 * --pmc-mode, --percall-mode: short runs for hardware-counter collection.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-tts]
@@ -53,7 +62,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (published)
+# MI355X vector FP32: 157.3 TFLOP/s published with packed FP32; the library is built without
+# packed FP32, so its issue rate is 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+PEAK_FP32_TFLOPS = 78.6
 STEPS_PER_LEVEL = 100
 ETA_A, ETA_B, EPS = 0.5, 5.0, 1e-2
 LEVELS = 40
@@ -72,6 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-SAT comparison")
     ap.add_argument("--no-protocol", action="store_true", help="skip the paper's gradient-timing protocol")
+    ap.add_argument("--no-other", action="store_true", help="skip the rates on the other workloads")
     ap.add_argument("--tts-seeds", type=int, default=10)
     ap.add_argument("--tts-cap", type=float, default=30.0, help="time limit per instance (s)")
     ap.add_argument("--percall-mode", action="store_true",
@@ -89,9 +101,8 @@ def parse():
     ap.add_argument("--suite-restarts", type=int, default=0,
                     help="restarts per attempt (0: 64, fewer for instances past 125k constraints)")
     ap.add_argument("--configs-mode", action="store_true",
-                    help="fixed-work fused-solver throughput on placement 150 x 256 restarts, the "
-                         "uneven 48-instance batch and placement 1,200 x 16 restarts, and time-to-SAT "
-                         "on placement 150")
+                    help="fixed-work fused-solver throughput on placement 150 x 256 restarts and "
+                         "time-to-SAT on placement 150")
     ap.add_argument("--scale-mode", action="store_true",
                     help="fixed-work solver throughput on the paper's largest encodings "
                          "(scheduling 256 workers x 5, placement 64 macros x 8 layers)")
@@ -124,8 +135,9 @@ def flops_per_pass(cost, R):
 
 
 def bytes_per_pass(cost, p, R):
-    """Compiled tables read once per pass, plus per restart: a, b read, gradient written and
-    read, projected state written, and one weight per constraint read."""
+    """T + R S: the compiled tables read once per pass over the restarts, plus per restart a,
+    b read, gradient written and read, projected state written, and one weight per
+    constraint read."""
     return float(cost["table_bytes"]) + R * (4 * (p.n_bool + p.n_real) * 5 + 4 * p.n_cons)
 
 
@@ -152,21 +164,22 @@ def main():
     if args.configs_mode:
         print(json.dumps(other_configs(args, fsmt, S)))
         return
-    log("compiling scheduling 200 x 10")
-    p = W.make_config(2)
-    R = W.RESTARTS[2]
-    ell = p.meta["mean_duration"]
+    log("compiling placement 1200 rectangles")
+    p = W.make_config(5)
+    R = W.RESTARTS[5]
+    ell = p.meta["mean_side"]
     t0 = time.perf_counter()
     h = fsmt.xbdd_compile(p)
     compile_s = time.perf_counter() - t0
     stats = fsmt.xbdd_info(h)
     cost = algorithmic_cost(p, stats)
     st = torch.cuda.Stream(device=dev)
-    a0, b0 = W.initial_points(p, R, 2, 0)
-    kappas = S.kappa_schedule(ell, max(LEVELS, args.steps, args.warmup, 2))
+    a0, b0 = W.initial_points(p, R, 5, 0)
+    levels = max(1, min(args.steps, 128))
+    kappas = S.kappa_schedule(ell, max(LEVELS, levels, 2))
 
-    def fixed_cfg(n_levels):
-        return S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=STEPS_PER_LEVEL, eta_a=ETA_A,
+    def fixed_cfg(n_levels, steps=STEPS_PER_LEVEL):
+        return S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=steps, eta_a=ETA_A,
                              eta_b=ETA_B, eps=0.0, stop_on_sat=0)
 
     if args.pmc_mode or args.percall_mode:
@@ -181,16 +194,16 @@ def main():
         print(json.dumps({"percall_mode": True, "copy_bytes": src.numel() * 4}))
         return
     if args.pmc_mode:
+        # one launch of one level of PMC_STEPS PGD iterations (and its check)
         state = S.BatchState(h, a0, b0)
-        S.solve_batched([h], [state], fixed_cfg(2), stream=st)
+        S.solve_batched([h], [state], fixed_cfg(1, PMC_STEPS), stream=st)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4}))
+        print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4, "pgd_steps": PMC_STEPS}))
         return
 
     # the K timed steps (annealing levels) are one fused launch; each of the W warmup runs is
-    # an identical launch on a throwaway state, so every launch of the command carries the
+    # an identical launch on a throwaway state, so every launch of this kernel carries the
     # same work (the profiler's per-launch average is the timed launch's duration)
-    levels = max(1, min(args.steps, 128))
     for _ in range(args.warmup):
         warm = S.BatchState(h, a0, b0)
         S.solve_batched([h], [warm], fixed_cfg(levels), stream=st)
@@ -209,44 +222,34 @@ def main():
     assert pgd_steps == levels * STEPS_PER_LEVEL
     evals = p.n_cons * R * pgd_steps
     value = evals / dt
-
-    # per launch (K levels x STEPS_PER_LEVEL PGD iterations over C x R constraint-evals)
-    fl = flops_per_pass(cost, R) * pgd_steps
-    by = bytes_per_pass(cost, p, R) * pgd_steps
-    ach_tf = fl / kern_s / 1e12
-    ach_gbs = by / kern_s / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "solve_wg_kernel_sched200.md")
-    if os.path.exists(tfile):
-        # measured HBM bytes per PGD iteration (scaled FETCH_SIZE + WRITE_SIZE of the solver
-        # kernel in the committed rocprofv3 summary), times the launch's iterations
-        for line in open(tfile):
-            if line.startswith("hbm_bytes_per_pgd_step:"):
-                traffic = float(line.split(":")[1]) * pgd_steps
+    log(f"timed launch: {levels} levels, {value:.3e} constraint-evals/s")
 
     out = {
         "metric": "constraint-evals/s (fwd+bwd) and time-to-SAT, batched fused vs plain, 1 GPU",
         "value": value, "unit": "constraint-evals/s", "n_gpus": 1, "steps": levels,
         "warmup": args.warmup, "ms_per_step": dt / levels * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "job-shop scheduling, 200 jobs on 10 machines, 64 restarts "
-                               "(fused batched solver; step = one annealing level of 100 PGD "
+        "config": {"workload": "placement of 1,200 rectangles with rotation bits (721,800 constraints), "
+                               "16 restarts (fused batched solver; step = one annealing level of 100 PGD "
                                "iterations + check + ERWA)",
                    "n_cons": p.n_cons, "n_bool": p.n_bool, "n_real": p.n_real, "restarts": R,
                    "pgd_steps_timed": pgd_steps, "compile_s": compile_s,
-                   "table_bytes": stats["table_bytes"]},
-        "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach_tf / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "solve_wg_kernel", "kernel_ms": kern_s * 1e3,
-                     "flop_per_launch": fl, "bytes_per_launch": by,
-                     "hbm_achieved_gbs": ach_gbs, "hbm_frac": ach_gbs / PEAK_HBM_GBS},
+                   "table_bytes": stats["table_bytes"], "closed_form_constraints": stats["n_gd"]},
+        "roofline": roofline(p, cost, R, pgd_steps, kern_s, "solve_wg_kernel",
+                             "solve_wg_kernel_placement1200.md"),
     }
-    log(f"timed launch: {levels} levels, {value:.3e} constraint-evals/s")
+    h.free()
     if not args.no_tts:
         out["time_to_sat"] = time_to_sat(args, fsmt, S, W, st)
         log("time-to-SAT on scheduling 200 x 10 done")
         out["time_to_sat_index_encoding"] = time_to_sat_hard(args, fsmt, S, W, st)
         log("time-to-SAT on the index encoding done")
+    if not args.no_other:
+        out["other_workloads"] = {
+            "scheduling 200 x 10, 64 restarts": _fixed_work(fsmt, S, [W.make_config(2)], 64, (2, 0), steps=100),
+            "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0)),
+        }
+        log("other workloads done")
     if not args.no_protocol:
         out["paper_protocol"] = paper_protocol(fsmt, W, st)
         log("gradient-timing protocol done")
@@ -255,6 +258,34 @@ def main():
         out["cpu_baseline_all_cores"] = cpu_baseline(p, a0, b0, kappas[0], threads=min(16, os.cpu_count() or 1))
         log("CPU baselines done")
     print(json.dumps(out))
+
+
+PMC_STEPS = 20   # PGD iterations of the --pmc-mode launch
+
+
+def roofline(p, cost, R, pgd_steps, kern_s, kernel, profile_name):
+    """Roofline of the solver launch: modelled FLOPs and algorithmic bytes per launch over the
+    launch's duration (HIP events on its stream), and the measured HBM bytes per PGD
+    iteration from the committed rocprofv3 summary."""
+    fl = flops_per_pass(cost, R) * pgd_steps
+    by = bytes_per_pass(cost, p, R) * pgd_steps
+    ach_tf = fl / kern_s / 1e12
+    ach_gbs = by / kern_s / 1e9
+    f_alu, f_hbm = ach_tf / PEAK_FP32_TFLOPS, ach_gbs / PEAK_HBM_GBS
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", profile_name)
+    if os.path.exists(tfile):
+        for line in open(tfile):
+            if line.startswith("hbm_bytes_per_pgd_step:"):
+                traffic = float(line.split(":")[1]) * pgd_steps
+    if f_alu >= f_hbm:
+        head = {"bound": "alu", "achieved": ach_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": f_alu}
+    else:
+        head = {"bound": "hbm", "achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": f_hbm}
+    return {**head, "traffic": traffic, "kernel": kernel, "kernel_ms": kern_s * 1e3,
+            "flop_per_launch": fl, "bytes_per_launch": by, "alu_achieved_tflops": ach_tf, "alu_frac": f_alu,
+            "hbm_achieved_gbs": ach_gbs, "hbm_frac": f_hbm,
+            "traffic_gbs": traffic / kern_s / 1e9 if traffic else None}
 
 
 def percall_placement(fsmt, W, st):
@@ -547,9 +578,7 @@ def other_configs(args, fsmt, S):
     """Rates of the fused solver on the other workloads, and time-to-SAT on placement 150."""
     import torch
     import workloads as W
-    out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_config(3)], 256, (3, 0)),
-           "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0)),
-           "placement 1200 x 16 restarts": _fixed_work(fsmt, S, [W.make_config(5)], 16, (5, 0), steps=10)}
+    out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_config(3)], 256, (3, 0))}
     # time to SAT with the paper-encoding hyperparameters (eta_b scaled by the side length)
     cap = min(args.tts_cap, 10.0)
     ts = []
