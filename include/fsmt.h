@@ -277,7 +277,9 @@ typedef struct {
                                  n_levels - level_begin levels in this call (0: no promise) */
     int32_t spin_limit;       /* polls of a cluster barrier before it gives up (0 = 2^22); a small
                                  value makes an incomplete cluster end the call early */
-    int32_t reserved[2];      /* set to 0 */
+    const int32_t *inst_schedule; /* host [n_inst] or NULL: per instance 0 = as `schedule`, 1 =
+                                 persistent, 2 = grid (a plan chosen by measurement, see the
+                                 package's autotuner) */
 } fsmt_solve_opts;
 
 /* Per-instance solver state, device memory owned by the caller ([R] rows each). The

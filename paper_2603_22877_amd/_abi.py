@@ -53,7 +53,7 @@ class SolveOpts(ct.Structure):
                 ("rho", ct.c_float), ("gamma", ct.c_float), ("tau", ct.c_int32),
                 ("normalize", ct.c_int32), ("stop_on_sat", ct.c_int32), ("schedule", ct.c_int32),
                 ("cluster", ct.c_int32), ("level_begin", ct.c_int32), ("spin_limit", ct.c_int32),
-                ("reserved", ct.c_int32 * 2)]
+                ("inst_schedule", ct.c_void_p)]
 
 
 class SolveState(ct.Structure):

@@ -722,8 +722,12 @@ __device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, co
         const uint32_t m = g.mask[c];
         if (m >> 31) continue;   // this assignment reaches the True terminal
         const uint32_t mA = m >> NB;
+        // selectors are Boolean slots (k <= NB <= NBm)
         const float pi0 = k > 0 ? ((c & 1) ? pb[0] : qb[0]) : 1.0f;
-        const float pi1 = k > 1 ? ((c & 2) ? pb[1] : qb[1]) : 1.0f;
+        float pi1 = 1.0f;
+        if constexpr (NBm > 1) {
+            if (k > 1) pi1 = (c & 2) ? pb[1] : qb[1];
+        }
         // factors: l where the slot is in the disjunction, else 1
         float fb[NBm], fa[NAm], preb[NBm], prea[NAm];
         float prod = 1.0f;

@@ -118,15 +118,45 @@ __device__ __forceinline__ bool cluster_sync(gptr<int32_t> bar_g, int target, in
 }
 
 // Sum of the cluster's k partial gradients into g[0..nm) in rank order (every rank gets the
-// same bits); returns the sum of the partial objectives.
+// same bits); returns the sum of the partial objectives. A thread issues the loads of kQ
+// partials of kB elements before summing them, so such a batch costs one round trip to
+// the coherence point (kernels with registers to spare take larger batches).
+template <int kB, int kQ>
 __device__ __forceinline__ float read_partials(float *g, gptr<float> buf, int64_t pstride, int nm, int k) {
-    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
-        float s = 0.0f;
-        for (int q = 0; q < k; ++q) s += fetch(buf + (int64_t)q * pstride + i);
-        g[i] = s;
-    }
     float os = 0.0f;
-    for (int q = 0; q < k; ++q) os += fetch(buf + (int64_t)q * pstride + nm);
+    for (int q0 = 0; q0 < k; q0 += kQ) {
+        float v[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) v[q] = q0 + q < k ? fetch(buf + (int64_t)(q0 + q) * pstride + nm) : 0.0f;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+            if (q0 + q < k) os += v[q];
+    }
+    for (int i0 = threadIdx.x; i0 < nm; i0 += kB * blockDim.x) {
+        float s[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) s[u] = 0.0f;
+        for (int q0 = 0; q0 < k; q0 += kQ) {
+            float v[kB][kQ];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    v[u][q] = (q0 + q < k && i < nm) ? fetch(buf + (int64_t)(q0 + q) * pstride + i) : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    if (q0 + q < k) s[u] += v[u][q];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < nm) g[i] = s[u];
+        }
+    }
     return os;
 }
 
@@ -245,10 +275,10 @@ __global__ void __launch_bounds__((64 * SolveWaves<V, kCF>::value))
                     break;
                 }
                 float os;
-                if constexpr (V == kMsgSmall) {
-                    os = k == 2 ? read_partials2(ga, buf, pstride, n + m) : read_partials(ga, buf, pstride, n + m, k);
+                if constexpr (SolveWaves<V, kCF>::value >= 16) {   // 128 VGPRs: small batches
+                    os = k == 2 ? read_partials2(ga, buf, pstride, n + m) : read_partials<1, 4>(ga, buf, pstride, n + m, k);
                 } else {
-                    os = read_partials(ga, buf, pstride, n + m, k);
+                    os = read_partials<2, 16>(ga, buf, pstride, n + m, k);
                 }
                 oacc = threadIdx.x == 0 ? os : 0.0f;
             }
@@ -647,14 +677,19 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
         const fsmt_xbdd *h = insts[i];
         const PersistentGeom G = persistent_geom(insts, std::vector<int>{i}, budget);
         const bool fits = G.waves > 0;
-        if ((O.schedule == 1 || fixed_scratch) && !fits)
+        // the instance's schedule: its entry of inst_schedule if set, else the call's
+        const int sched = (O.inst_schedule && O.inst_schedule[i] != 0) ? O.inst_schedule[i] : O.schedule;
+        if (sched < 0 || sched > 2) return set_error(FSMT_EINVAL, "instance %d: schedule %d unknown", i, sched);
+        if (fixed_scratch && sched == 2)
+            return set_error(FSMT_EUNSUPPORTED, "the allocation-free call runs the persistent schedule only");
+        if ((sched == 1 || fixed_scratch) && !fits)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: restart state (%zu B) does not fit the persistent "
                              "schedule's LDS (%zu B)", i, G.state_f * sizeof(float), budget);
         // big diagrams are evaluated level by level by their own kernel, in the grid schedule
-        if ((O.schedule == 1 || fixed_scratch) && h->n_big > 0)
+        if ((sched == 1 || fixed_scratch) && h->n_big > 0)
             return set_error(FSMT_EUNSUPPORTED, "instance %d: %d big diagrams need the grid schedule", i, h->n_big);
-        use_grid[i] = O.schedule == 2 || !fits || h->n_big > 0 ||
-                      (O.schedule == 0 && !fixed_scratch && prefer_grid(h, states[i].a.rows, r_batch, G.waves, n_cu));
+        use_grid[i] = sched == 2 || !fits || h->n_big > 0 ||
+                      (sched == 0 && !fixed_scratch && prefer_grid(h, states[i].a.rows, r_batch, G.waves, n_cu));
     }
     std::vector<int> ia, ib;
     for (int i = 0; i < n_inst; ++i) (use_grid[i] ? ib : ia).push_back(i);
@@ -665,7 +700,9 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
     while (!ia.empty()) {
         G = persistent_geom(insts, ia, budget);
         if (G.waves > 0) break;
-        if (O.schedule == 1 || fixed_scratch)
+        bool forced = O.schedule == 1 || fixed_scratch;
+        for (int i : ia) forced = forced || (O.inst_schedule && O.inst_schedule[i] == 1);
+        if (forced)
             return set_error(FSMT_EUNSUPPORTED, "the instances' combined restart state and message store do not fit "
                              "one persistent workgroup's LDS (%zu B)", budget);
         auto big = std::max_element(ia.begin(), ia.end(), [&](int x, int y) {

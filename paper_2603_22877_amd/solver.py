@@ -44,6 +44,7 @@ class SolveConfig:
     cluster: int = 0         # persistent schedule: workgroups per restart (0 automatic)
     level_begin: int = 0     # grid schedule: levels below this are complete for every restart
     spin_limit: int = 0      # cluster barrier polls before giving up (0: the library default)
+    inst_schedule: Optional[Sequence[int]] = None   # per instance 0 (as schedule) / 1 / 2
 
     def abi(self):
         kap = (ct.c_double * max(1, len(self.kappas)))(*self.kappas)
@@ -59,7 +60,12 @@ class SolveConfig:
         o.cluster = int(self.cluster)
         o.level_begin = int(self.level_begin)
         o.spin_limit = int(self.spin_limit)
-        return o, kap
+        keep = [kap]
+        if self.inst_schedule is not None:
+            sch = (ct.c_int32 * max(1, len(self.inst_schedule)))(*[int(v) for v in self.inst_schedule])
+            o.inst_schedule = ct.cast(sch, ct.c_void_p)
+            keep.append(sch)
+        return o, keep
 
 
 class BatchState:

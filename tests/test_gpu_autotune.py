@@ -1,0 +1,82 @@
+"""GPU tests of the measured plan selection (paper_2603_22877_amd.autotune): the plan it
+picks is never slower than the cost model's plan (within 5 %, measured again), it runs
+through the per-instance schedule of the C ABI with the same results, and it is cached."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+from gpu_util import torch
+
+pytestmark = pytest.mark.gpu
+fsmt = pytest.importorskip("paper_2603_22877_amd")
+from paper_2603_22877_amd import autotune as AT  # noqa: E402
+from paper_2603_22877_amd import solver as S  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _batch(cfg_id):
+    if cfg_id == 4:
+        probs = W.make_batch_config4()
+    else:
+        probs = [W.make_config(cfg_id)]
+    R = W.RESTARTS[cfg_id]
+    hs = [fsmt.xbdd_compile(p) for p in probs]
+    init = [W.initial_points(p, R, 70, cfg_id, i) for i, p in enumerate(probs)]
+    ell = min(p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)) for p in probs)
+    cfg = S.SolveConfig(kappas=S.kappa_schedule(ell, 4), steps_per_level=100, eta_a=0.5, eta_b=5.0, eps=0.0,
+                        stop_on_sat=0)
+    return probs, hs, init, cfg
+
+
+@pytest.mark.parametrize("cfg_id", [2, 3, 4])
+def test_tuned_plan_not_slower_than_model(cfg_id, tmp_path, monkeypatch):
+    monkeypatch.setenv(AT.CACHE_ENV, str(tmp_path / "tune.json"))
+    probs, hs, init, cfg = _batch(cfg_id)
+    plan = AT.tune(hs, init, cfg, log=lambda m: print(m, flush=True))
+    print(f"config {cfg_id}: chosen {plan.label} {plan.inst_schedule[:8]} cluster {plan.cluster}, "
+          f"candidates {plan.candidates}", flush=True)
+    assert not plan.cached and os.path.exists(tmp_path / "tune.json")
+    assert plan.us_per_level <= min(plan.candidates.values()) * (1 + 1e-9)
+    if plan.label != "model":
+        # measured again, alternating, best of several: the chosen plan against the model's
+        model, tuned = float("inf"), float("inf")
+        for _ in range(3):
+            model = min(model, AT.measure(hs, init, cfg, steps=8, reps=2)[1])
+            tuned = min(tuned, AT.measure(hs, init, plan.apply(cfg), steps=8, reps=2)[1])
+        print(f"config {cfg_id}: model {model / 1e3:.3f} ms per level, tuned {tuned / 1e3:.3f}", flush=True)
+        assert tuned <= 1.05 * model
+    again = AT.tune(hs, init, cfg)
+    assert again.cached and again.inst_schedule == plan.inst_schedule and again.cluster == plan.cluster
+    for h in hs:
+        h.free()
+
+
+def test_per_instance_schedule_gives_the_same_steps():
+    """Two instances, one forced persistent and one forced grid in one call, against the
+    same instances each alone under that schedule: one fused step (fixed work) must agree
+    (integer outputs exactly, the point within float rounding)."""
+    p1, p2 = W.make_config(1), W.make_config(3)
+    h1, h2 = fsmt.xbdd_compile(p1), fsmt.xbdd_compile(p2)
+    i1, i2 = W.initial_points(p1, 4, 71, 1), W.initial_points(p2, 4, 71, 3)
+    cfg = S.SolveConfig(kappas=[0.2], steps_per_level=1, eta_a=0.5, eta_b=5.0, eps=0.0, stop_on_sat=0)
+    both = [S.BatchState(h1, *i1), S.BatchState(h2, *i2)]
+    S.solve_batched([h1, h2], both, S.SolveConfig(**{**cfg.__dict__, "inst_schedule": [1, 2]}))
+    alone1, alone2 = S.BatchState(h1, *i1), S.BatchState(h2, *i2)
+    S.solve_batched([h1], [alone1], S.SolveConfig(**{**cfg.__dict__, "schedule": 1}))
+    S.solve_batched([h2], [alone2], S.SolveConfig(**{**cfg.__dict__, "schedule": 2}))
+    S.check_batched(both + [alone1, alone2])
+    for x, y in ((both[0], alone1), (both[1], alone2)):
+        for k in ("sat_bits", "n_unsat", "verdict", "level_done", "steps_done"):
+            np.testing.assert_array_equal(getattr(x, k).cpu().numpy(), getattr(y, k).cpu().numpy())
+        np.testing.assert_allclose(x.a.cpu().numpy(), y.a.cpu().numpy(), rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(x.b.cpu().numpy(), y.b.cpu().numpy(), rtol=1e-5, atol=1e-5)
+    h1.free()
+    h2.free()
