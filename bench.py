@@ -50,6 +50,7 @@ Other modes (each prints its own JSON line instead of the main one):
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import statistics
@@ -178,9 +179,12 @@ def main():
     levels = max(1, min(args.steps, 128))
     kappas = S.kappa_schedule(ell, max(LEVELS, levels, 2))
 
+    plan = None
+
     def fixed_cfg(n_levels, steps=STEPS_PER_LEVEL):
-        return S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=steps, eta_a=ETA_A,
-                             eta_b=ETA_B, eps=0.0, stop_on_sat=0)
+        c = S.SolveConfig(kappas=kappas[:n_levels], steps_per_level=steps, eta_a=ETA_A,
+                          eta_b=ETA_B, eps=0.0, stop_on_sat=0)
+        return plan.apply(c) if plan is not None else c
 
     if args.pmc_mode or args.percall_mode:
         # calibration: one element-wise shader kernel reading 256 MiB and writing 256 MiB
@@ -194,12 +198,22 @@ def main():
         print(json.dumps({"percall_mode": True, "copy_bytes": src.numel() * 4}))
         return
     if args.pmc_mode:
-        # one launch of one level of PMC_STEPS PGD iterations (and its check)
+        # one launch of one level of PMC_STEPS PGD iterations (and its check), under the plan
+        # the main line's autotuner cached (the model's plan when there is none)
+        from paper_2603_22877_amd import autotune as AT
+        plan = AT.cached_plan([h], [(a0, b0)], fixed_cfg(levels))
         state = S.BatchState(h, a0, b0)
         S.solve_batched([h], [state], fixed_cfg(1, PMC_STEPS), stream=st)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_mode": True, "copy_bytes": src.numel() * 4, "pgd_steps": PMC_STEPS}))
         return
+
+    # the solver plan (schedule, cluster size) measured by the autotuner, outside the clock
+    from paper_2603_22877_amd import autotune as AT
+    t0 = time.perf_counter()
+    plan = AT.tune([h], [(a0, b0)], fixed_cfg(levels), stream=st, log=log)
+    tune_s = time.perf_counter() - t0
+    log(f"autotuned plan: {plan.label} (cluster {plan.cluster}) in {tune_s:.1f} s")
 
     # the K timed steps (annealing levels) are one fused launch; each of the W warmup runs is
     # an identical launch on a throwaway state, so every launch of this kernel carries the
@@ -234,7 +248,10 @@ def main():
                                "iterations + check + ERWA)",
                    "n_cons": p.n_cons, "n_bool": p.n_bool, "n_real": p.n_real, "restarts": R,
                    "pgd_steps_timed": pgd_steps, "compile_s": compile_s,
-                   "table_bytes": stats["table_bytes"], "closed_form_constraints": stats["n_gd"]},
+                   "table_bytes": stats["table_bytes"], "closed_form_constraints": stats["n_gd"],
+                   "plan": {"label": plan.label, "cluster": plan.cluster, "inst_schedule": plan.inst_schedule,
+                            "candidates_ms_per_level": {k: v / 1e3 for k, v in plan.candidates.items()},
+                            "tune_s": tune_s, "cached": plan.cached}},
         "roofline": roofline(p, cost, R, pgd_steps, kern_s, "solve_wg_kernel",
                              "solve_wg_kernel_placement1200.md"),
     }
@@ -248,6 +265,8 @@ def main():
         out["other_workloads"] = {
             "scheduling 200 x 10, 64 restarts": _fixed_work(fsmt, S, [W.make_config(2)], 64, (2, 0), steps=100),
             "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0)),
+            "uneven batch, 48 instances x 16 restarts, autotuned plan":
+                _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0), tuned=True),
         }
         log("other workloads done")
     if not args.no_protocol:
@@ -549,8 +568,9 @@ def paper_suite(args, S):
                     "limit is 1000 s on its own instances and hardware"}
 
 
-def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20):
-    """One warm-up and one timed fused call of ``levels`` x ``steps`` PGD iterations."""
+def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20, tuned=False):
+    """One warm-up and one timed fused call of ``levels`` x ``steps`` PGD iterations (with
+    ``tuned``, under the autotuner's plan, measured outside the clock)."""
     import torch
     import workloads as W
     hs = [fsmt.xbdd_compile(p) for p in probs]
@@ -558,6 +578,11 @@ def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20):
     ell = [p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)) for p in probs]
     cfg = S.SolveConfig(kappas=S.kappa_schedule(min(ell), levels), steps_per_level=steps, eta_a=ETA_A,
                         eta_b=ETA_B, eps=0.0, stop_on_sat=0)
+    plan = None
+    if tuned:
+        from paper_2603_22877_amd import autotune as AT
+        plan = AT.tune(hs, init, dataclasses.replace(cfg, steps_per_level=STEPS_PER_LEVEL))
+        cfg = plan.apply(cfg)
     for _ in range(2):
         states = [S.BatchState(h, a, b) for h, (a, b) in zip(hs, init)]
         torch.cuda.synchronize()
@@ -569,9 +594,14 @@ def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20):
     evals = sum(p.n_cons for p in probs) * R * it
     for h in hs:
         h.free()
-    return {"instances": len(probs), "n_cons_total": int(sum(p.n_cons for p in probs)), "restarts": R,
-            "pgd_steps": it, "ms_per_pgd_step": dt / it * 1e3, "constraint_evals_per_s": evals / dt,
-            "includes": "one fused call: sweeps, projections, one check + ERWA"}
+    out = {"instances": len(probs), "n_cons_total": int(sum(p.n_cons for p in probs)), "restarts": R,
+           "pgd_steps": it, "ms_per_pgd_step": dt / it * 1e3, "constraint_evals_per_s": evals / dt,
+           "includes": "one fused call: sweeps, projections, one check + ERWA"}
+    if plan is not None:
+        out["plan"] = {"label": plan.label, "cluster": plan.cluster,
+                       "persistent_instances": sum(1 for v in plan.inst_schedule if v == 1),
+                       "grid_instances": sum(1 for v in plan.inst_schedule if v == 2)}
+    return out
 
 
 def other_configs(args, fsmt, S):

@@ -117,6 +117,16 @@ def measure(handles, init, cfg: SolveConfig, steps: int = 8, reps: int = 2, stre
     return it * 1e3, (cfg.steps_per_level * it + level_end) * 1e3
 
 
+def cached_plan(handles, init: Sequence[Tuple], cfg: SolveConfig) -> Optional[Plan]:
+    """The cached plan for this batch and configuration, or None (nothing is measured)."""
+    hit = _load_cache().get(signature(handles, [a.shape[0] for a, _ in init], cfg))
+    if hit is None:
+        return None
+    return Plan(inst_schedule=list(hit["inst_schedule"]), cluster=int(hit["cluster"]), label=hit["label"],
+                us_per_level=hit["us_per_level"], us_per_step=hit["us_per_step"],
+                candidates=dict(hit["candidates"]), cached=True)
+
+
 def tune(handles, init: Sequence[Tuple], cfg: SolveConfig, steps: int = 8, reps: int = 2, use_cache: bool = True,
          stream=None, log: Optional[Callable[[str], None]] = None) -> Plan:
     """Measure the candidate plans for this batch (handles with their initial points ``init``,
@@ -127,11 +137,9 @@ def tune(handles, init: Sequence[Tuple], cfg: SolveConfig, steps: int = 8, reps:
     n = len(handles)
     key = signature(handles, restarts, cfg)
     if use_cache:
-        hit = _load_cache().get(key)
+        hit = cached_plan(handles, init, cfg)
         if hit is not None:
-            return Plan(inst_schedule=list(hit["inst_schedule"]), cluster=int(hit["cluster"]), label=hit["label"],
-                        us_per_level=hit["us_per_level"], us_per_step=hit["us_per_step"],
-                        candidates=dict(hit["candidates"]), cached=True)
+            return hit
 
     results: Dict[str, Tuple[float, float, Plan]] = {}
 
