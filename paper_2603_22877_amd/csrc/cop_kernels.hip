@@ -131,6 +131,17 @@ __global__ void __launch_bounds__(256) cop_level_kernel(LevelArgs A) {
 }
 
 // ------------------------------------------------------------------ small kernels
+// out(r, v) (+)= stage[v * R + r]: the gradient accumulated restart-contiguous (see
+// cop_launch) moved into the caller's view.
+__global__ void unstage_kernel(View out, const float *stage, int R, int cols, int accumulate) {
+    const int64_t n = (int64_t)R * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(e / R), r = (int)(e - (int64_t)v * R);
+        const float g = stage[e];
+        if (accumulate) out.at(r, v) += g; else out.at(r, v) = g;
+    }
+}
+
 __global__ void fill_view_kernel(View v, float value) {
     const int64_t n = (int64_t)v.rows * v.cols;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -372,11 +383,45 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         return set_error(FSMT_ELIMIT, "diagram too large for the level-synchronous pass (%d nodes, %d slots)",
                          h->big_max_nodes, h->big_max_slots);
 
+    // With several restarts in a wavefront's lanes, the lanes of one constraint add into the
+    // same variable of consecutive restarts. Device-scope float atomics are performed past
+    // the per-XCD L2, one memory transaction per cache line touched, so when the caller's
+    // gradient rows are not restart-contiguous the sums go to a restart-contiguous stage
+    // ([n + m][R], one line per variable and 16 restarts) and are moved into the caller's
+    // views afterwards.
+    const int n = h->n_bool, m = h->n_real;
+    const bool stage = grad && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
+                       !(ga.stride_r == 1 && gb.stride_r == 1);
+    struct Stage {   // freed stream-ordered after whatever the call enqueued
+        float *p = nullptr;
+        hipStream_t st = nullptr;
+        ~Stage() {
+            if (p) (void)hipFreeAsync(p, st);
+        }
+    } sg;
+    sg.st = st;
+    if (stage) {
+        if (hipMallocAsync((void **)&sg.p, sizeof(float) * (size_t)(n + m) * R, st) != hipSuccess) {
+            (void)hipGetLastError();
+            sg.p = nullptr;
+            return set_error(FSMT_ENOMEM, "gradient stage allocation failed");
+        }
+        if ((rc = fill_f32(sg.p, (int64_t)(n + m) * R, 0.0f, st))) return rc;
+    }
+    float *const sbuf = sg.p;
     if (!(flags & FSMT_ACCUMULATE)) {
         if (obj && (rc = fill_f32(obj, R, 0.0f, st))) return rc;
-        if (grad && ((rc = fill_view(ga, 0.0f, st)) || (rc = fill_view(gb, 0.0f, st)))) return rc;
+        if (grad && !stage && ((rc = fill_view(ga, 0.0f, st)) || (rc = fill_view(gb, 0.0f, st)))) return rc;
     }
-    if (h->n_pos == 0) return FSMT_OK;
+    if (h->n_pos == 0) {
+        if (stage) {
+            hipLaunchKernelGGL(unstage_kernel, dim3(blocks_for((int64_t)R * n, 256)), dim3(256), 0, st, View::of(ga),
+                               (const float *)sbuf, R, n, flags & FSMT_ACCUMULATE);
+            hipLaunchKernelGGL(unstage_kernel, dim3(blocks_for((int64_t)R * m, 256)), dim3(256), 0, st, View::of(gb),
+                               (const float *)(sbuf + (size_t)n * R), R, m, flags & FSMT_ACCUMULATE);
+        }
+        return launch_status("gradient unstage");
+    }
 
     CopArgs A{};
     A.T = TabView::of(h);
@@ -398,6 +443,10 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     A.unsat = View::of(unsat);
     A.ga = grad ? View::of(ga) : View{};
     A.gb = grad ? View::of(gb) : View{};
+    if (stage) {
+        A.ga = View{as_gptr(sbuf), R, n, 1, R};
+        A.gb = View{as_gptr(sbuf + (size_t)n * R), R, m, 1, R};
+    }
     A.obj = obj;
     A.kappa = kappa;
     A.hard = std::isinf(kappa) ? 1 : 0;
@@ -445,6 +494,13 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         else
             hipLaunchKernelGGL(cop_level_kernel<false>, dim3(lblocks), dim3(64 * lwpb), level_wave_bytes * lwpb, st, L);
         if ((rc = launch_status("cop level kernel"))) return rc;
+    }
+    if (stage) {
+        hipLaunchKernelGGL(unstage_kernel, dim3(blocks_for((int64_t)R * n, 256)), dim3(256), 0, st, View::of(ga),
+                           (const float *)sbuf, R, n, flags & FSMT_ACCUMULATE);
+        hipLaunchKernelGGL(unstage_kernel, dim3(blocks_for((int64_t)R * m, 256)), dim3(256), 0, st, View::of(gb),
+                           (const float *)(sbuf + (size_t)n * R), R, m, flags & FSMT_ACCUMULATE);
+        if ((rc = launch_status("gradient unstage"))) return rc;
     }
     return FSMT_OK;
 }
