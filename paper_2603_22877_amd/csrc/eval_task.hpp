@@ -774,7 +774,7 @@ __device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, co
             }
         }
         // atoms: dz = w dF/dp dp/dz, summed over a run of atoms on the same variables and
-        // scattered at the run's end (its variables read again from the record)
+        // scattered at the run's end
         float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
         for (int j = 0; j < NAm; ++j) {
@@ -785,9 +785,8 @@ __device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, co
                 g1 += gz * c1[j];
                 const bool last = j + 1 >= NA || !((g.same_vars >> (j + 1)) & 1u);
                 if (last) {
-                    const u32x2 vv = *(cptr<u32x2>)(t.rec + (int64_t)j * np);
-                    sc.add_b(t.r, t.valid ? (int)vv.x : -1, g0, lane);
-                    sc.add_b(t.r, t.valid ? (int)vv.y : -1, g1, lane);   // g1 = 0 for one variable
+                    sc.add_b(t.r, t.valid ? rec[j].v0 : -1, g0, lane);
+                    sc.add_b(t.r, t.valid ? rec[j].v1 : -1, g1, lane);   // g1 = 0 for one variable
                     g0 = g1 = 0.0f;
                 }
             }
