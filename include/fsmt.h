@@ -289,7 +289,7 @@ typedef struct {
     fsmt_view a, b;           /* [R][n_bool], [R][n_real] in/out (row stride >= cols, unit column stride) */
     float *w;                 /* [R][n_cons] in/out weights */
     float *hist;              /* [R][n_cons] in/out ERWA history h */
-    float *grad_a, *grad_b;   /* unused by the persistent schedule (may be NULL) */
+    float *grad_a, *grad_b;   /* grid schedule work arrays, [n_bool][R], [n_real][R] (may be NULL) */
     uint32_t *sat_bits;       /* [R][ceil(n_cons/32)] out: last check */
     int32_t *n_unsat;         /* [R] out */
     int32_t *verdict;         /* [R] out: 1 = SAT found (state a, b holds the assignment) */
@@ -315,7 +315,8 @@ typedef struct {
  * in LDS, one launch; grid, one captured graph of grid-wide kernels replayed per level, for
  * states that do not fit in LDS, big diagrams, or too few restarts to fill the device. A
  * batch may mix both (they run concurrently). The grid schedule uses grad_a / grad_b of the
- * state as work arrays when given (else its own).
+ * state as work arrays when given (else its own): restart-contiguous, grad_a[i * R + r] and
+ * grad_b[j * R + r], zero at entry and left zero.
  *
  * Asynchronous on the stream: the call enqueues work and returns without waiting for the
  * device. A cluster whose workgroups were not all resident gives up at a bounded barrier

@@ -862,8 +862,6 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
             d.b_sr = S.b.stride_r;
             d.ga = as_gptr(S.grad_a);
             d.gb = as_gptr(S.grad_b);
-            d.ga_sr = h->n_bool;
-            d.gb_sr = h->n_real;
             d.w = as_gptr(S.w);
             d.hist = as_gptr(S.hist);
             d.sat_bits = as_gptr(S.sat_bits);

@@ -97,7 +97,9 @@ __global__ void __launch_bounds__(256) grid_sweep_kernel(const GridInst *insts, 
         const bool r_ok = r < I.R && S.stepping[I.rbase + r] != 0;
         const TabView T = I.T;
         const GlobalState st{View{I.a, I.R, T.n_bool, I.a_sr, 1}, View{I.b, I.R, T.n_real, I.b_sr, 1}};
-        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1},
+        // gradients restart-contiguous: one wave-wide atomic of a constraint group touches
+        // the R_pad consecutive restarts of one variable, one cache line for R_pad <= 16
+        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, 1, I.R}, View{I.gb, I.R, T.n_real, 1, I.R},
                                I.R_pad < 64 ? I.R_pad : 64};
         const TaskCtx t = task_ctx(T, pos, r, r_ok);
         if (t.B.big) continue;   // evaluated by grid_level_kernel
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(256) grid_level_kernel(const GridInst *insts, 
         oa.begin(I.rbase + r0, r1 - r0, lane);
         const TabView T = I.T;
         const GlobalState st{View{I.a, I.R, T.n_bool, I.a_sr, 1}, View{I.b, I.R, T.n_real, I.b_sr, 1}};
-        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, I.ga_sr, 1}, View{I.gb, I.R, T.n_real, I.gb_sr, 1}, 64};
+        const GlobalScatter sc{View{I.ga, I.R, T.n_bool, 1, I.R}, View{I.gb, I.R, T.n_real, 1, I.R}, 64};
         const LevelCtx L = level_ctx(T, I.lev, I.big_pos[q]);
         level_stage_nodes(T, L, W, lane);
         for (int r = r0; r < r1; ++r) {
@@ -157,30 +159,30 @@ __global__ void __launch_bounds__(256) grid_step_kernel(const GridInst *insts, i
     if (!S.stepping[g]) return;
     const int n = I.T.n_bool, m = I.T.n_real;
     const gptr<float> arow = I.a + (int64_t)r * I.a_sr, brow = I.b + (int64_t)r * I.b_sr;
-    const gptr<float> garow = I.ga + (int64_t)r * I.ga_sr, gbrow = I.gb + (int64_t)r * I.gb_sr;
+    const gptr<float> gacol = I.ga + r, gbcol = I.gb + r;   // element i at i * R
     float acc = 0.0f;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const float x = arow[i], y = x - S.eta_a * garow[i];
+        const float x = arow[i], y = x - S.eta_a * gacol[(int64_t)i * I.R];
         const float p = y < -1.0f ? -1.0f : (y > 1.0f ? 1.0f : y);
         arow[i] = p;
-        garow[i] = 0.0f;
+        gacol[(int64_t)i * I.R] = 0.0f;
         const float q = (x - p) / S.eta_a;
         acc += q * q;
     }
     if (I.hs.n == 0) {
         for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            const float x = brow[j], y = x - S.eta_b * gbrow[j];
+            const float x = brow[j], y = x - S.eta_b * gbcol[(int64_t)j * I.R];
             const float p = y < I.T.real_lo[j] ? I.T.real_lo[j] : (y > I.T.real_hi[j] ? I.T.real_hi[j] : y);
             brow[j] = p;
-            gbrow[j] = 0.0f;
+            gbcol[(int64_t)j * I.R] = 0.0f;
             const float q = (x - p) / S.eta_b;
             acc += q * q;
         }
     } else {
         float *y = sm, *pb = sm + m, *ph = sm + 2 * m;
         for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            y[j] = brow[j] - S.eta_b * gbrow[j];
-            gbrow[j] = 0.0f;
+            y[j] = brow[j] - S.eta_b * gbcol[(int64_t)j * I.R];
+            gbcol[(int64_t)j * I.R] = 0.0f;
         }
         project_dykstra(y, pb, ph, I.T.real_lo, I.T.real_hi, m, I.hs);
         for (int j = threadIdx.x; j < m; j += blockDim.x) {

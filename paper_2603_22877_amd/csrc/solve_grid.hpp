@@ -10,7 +10,7 @@ struct GridInst {
     TabView T;
     HalfSpaces hs;
     gptr<float> a, b, ga, gb;       // row-major [R][n] rows with unit column stride
-    int64_t a_sr, b_sr, ga_sr, gb_sr;
+    int64_t a_sr, b_sr;   // row strides of a, b; ga, gb are restart-contiguous [n][R] work arrays
     gptr<float> w, hist;            // [R][C]
     gptr<uint32_t> sat_bits;
     gptr<int32_t> n_unsat, verdict, level_done, steps_done;
