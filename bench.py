@@ -604,34 +604,43 @@ def _fixed_work(fsmt, S, probs, R, keys, levels=1, steps=20, tuned=False):
     return out
 
 
+# Placement time-to-SAT: the suite's sigma schedule sharpens too fast for dense packings (a
+# deep overlap's smoothed gradient vanishes once kappa * depth >> 1), so these runs end at a
+# gentler final kappa of 7 / (mean side) over 120 levels, run every level's 100 steps
+# (eps = 0) and grow ERWA weights by 1.5
+PLACE_HP = dict(SUITE_HP, levels=120, kmax=7.0, eps=0.0, gamma=1.5)
+
+
+def placement_tts(fsmt, S, fill: float, seeds: int, cap: float) -> dict:
+    """PAR-2 time to SAT on placement with 150 rectangles (compile and upload included),
+    256 restarts per attempt, fresh initial points per attempt until SAT or the cap."""
+    import workloads as W
+    from workloads import placement as PL
+    from paper_2603_22877_amd import par2 as P2
+    res = []
+    for seed in range(seeds):
+        p = W.make_config(3, seed) if fill == 0.6 else PL.make_placement(150, W.seed_seq(3, seed), fill=fill)
+        cfg = _suite_cfg(S, p, **{k: PLACE_HP[k] for k in ("levels", "kmax", "eps", "gamma")})
+        r = P2.run_instance(p, cfg, 256, cap, lambda q, R, att, seed=seed: W.initial_points(q, R, 3, seed, 100 + att),
+                            name=f"placement150 fill {fill} #{seed}")
+        res.append(r)
+        log(f"placement 150 fill {fill} seed {seed}: solved {r.solved} in {r.seconds:.2f} s, best {r.best_unsat}")
+    sc = [r.score(cap) for r in res]
+    return {"instances": seeds, "solved": sum(r.solved for r in res), "cap_s": cap, "fill": fill,
+            "median_s": float(statistics.median(sc)), "par2_s": P2.par2(res, cap),
+            "per_instance_s": [round(r.seconds, 3) if r.solved else None for r in res],
+            "best_violations_unsolved": [int(r.best_unsat) for r in res if not r.solved],
+            "attempts": [int(r.attempts) for r in res], "hyperparameters": PLACE_HP}
+
+
 def other_configs(args, fsmt, S):
-    """Rates of the fused solver on the other workloads, and time-to-SAT on placement 150."""
-    import torch
+    """Rates of the fused solver on placement 150, and time-to-SAT there (the generator's 60 %
+    area fill and, where the method solves, 50 %)."""
     import workloads as W
     out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_config(3)], 256, (3, 0))}
-    # time to SAT with the paper-encoding hyperparameters (eta_b scaled by the side length)
-    cap = min(args.tts_cap, 10.0)
-    ts = []
-    for seed in range(3):
-        p = W.make_config(3, seed)
-        h = fsmt.xbdd_compile(p)
-        cfg = _suite_cfg(S, p)
-        t0, done, att = time.perf_counter(), None, 0
-        while time.perf_counter() - t0 < cap:
-            st = S.BatchState(h, *W.initial_points(p, 256, 3, seed, 100 + att))
-            S.solve_batched([h], [st], cfg)
-            torch.cuda.synchronize()
-            if st.verdict.cpu().numpy().max() == 1:
-                done = time.perf_counter() - t0
-                break
-            att += 1
-        ts.append(done)
-        h.free()
-    sc = [t if t is not None else 2 * cap for t in ts]
-    out["time_to_sat placement 150, 256 restarts"] = {
-        "instances": len(ts), "solved": sum(t is not None for t in ts), "cap_s": cap,
-        "median_s": float(statistics.median(sc)), "par2_s": float(np.mean(sc)), "per_instance_s": ts,
-        "hyperparameters": SUITE_HP}
+    cap = min(args.tts_cap, 20.0)
+    out["time_to_sat placement 150 (60% fill), 256 restarts"] = placement_tts(fsmt, S, 0.6, 10, cap)
+    out["time_to_sat placement 150 at 50% fill, 256 restarts"] = placement_tts(fsmt, S, 0.5, 10, cap)
     return {"configs_mode": True, **out}
 
 
