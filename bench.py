@@ -120,8 +120,13 @@ def algorithmic_cost(p, stats):
         atoms = ids[ids >= p.n_bool] - p.n_bool
         n_atom += len(atoms)
         nnz_used += int(nnz[atoms].sum())
+    # the table stream of the method, independent of this library's layout: per constraint a
+    # 16-byte header, 8 bytes per decision node, 4 per support variable, and per atom 8 per
+    # nonzero plus 8
+    model = (16 * p.n_cons + 8 * int(stats["total_nodes"]) + 4 * (n_bool + n_atom)
+             + 8 * nnz_used + 8 * n_atom)
     return dict(total_nodes=int(stats["total_nodes"]), bool_slots=n_bool, atom_slots=n_atom,
-                atom_nnz=nnz_used, table_bytes=int(stats["table_bytes"]))
+                atom_nnz=nnz_used, table_bytes=int(stats["table_bytes"]), table_model_bytes=int(model))
 
 
 def flops_per_pass(cost, R):
@@ -136,10 +141,10 @@ def flops_per_pass(cost, R):
 
 
 def bytes_per_pass(cost, p, R):
-    """T + R S: the compiled tables read once per pass over the restarts, plus per restart a,
-    b read, gradient written and read, projected state written, and one weight per
-    constraint read."""
-    return float(cost["table_bytes"]) + R * (4 * (p.n_bool + p.n_real) * 5 + 4 * p.n_cons)
+    """T + R S: the method's table stream (``table_model_bytes``) read once per pass over the
+    restarts, plus per restart a, b read, gradient written and read, projected state
+    written, and one weight per constraint read."""
+    return float(cost["table_model_bytes"]) + R * (4 * (p.n_bool + p.n_real) * 5 + 4 * p.n_cons)
 
 
 def main():

@@ -127,10 +127,12 @@ def cached_plan(handles, init: Sequence[Tuple], cfg: SolveConfig) -> Optional[Pl
                 candidates=dict(hit["candidates"]), cached=True)
 
 
-def tune(handles, init: Sequence[Tuple], cfg: SolveConfig, steps: int = 8, reps: int = 2, use_cache: bool = True,
-         stream=None, log: Optional[Callable[[str], None]] = None) -> Plan:
+def tune(handles, init: Sequence[Tuple], cfg: SolveConfig, steps: int = 16, reps: int = 3, use_cache: bool = True,
+         stream=None, log: Optional[Callable[[str], None]] = None, margin: float = 0.03) -> Plan:
     """Measure the candidate plans for this batch (handles with their initial points ``init``,
-    one (a0, b0) pair per instance) under ``cfg`` and return the fastest."""
+    one (a0, b0) pair per instance) under ``cfg`` and return the fastest. The model's plan is
+    kept unless another is faster by more than ``margin`` (the per-level estimate extrapolates
+    a difference of two short launches, so plans that run the same kernels differ by noise)."""
     import torch
     stream = stream or torch.cuda.Stream()
     restarts = [a.shape[0] for a, _ in init]
@@ -178,6 +180,8 @@ def tune(handles, init: Sequence[Tuple], cfg: SolveConfig, steps: int = 8, reps:
     if not results:
         raise RuntimeError("autotune: no candidate plan could run")
     label = min(results, key=lambda k: results[k][1])
+    if "model" in results and results["model"][1] <= (1.0 + margin) * results[label][1]:
+        label = "model"
     it, lvl, plan = results[label]
     plan.us_per_step, plan.us_per_level = it, lvl
     plan.candidates = {k: v[1] for k, v in results.items()}

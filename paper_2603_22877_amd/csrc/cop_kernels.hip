@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
         const TaskCtx t = task_ctx(A.T, pos, r, r < A.R);
         if (t.B.big) continue;   // evaluated by cop_level_kernel
         const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;   // requested before the forward pass
-        const float unsat = task_eval<kGrad, kCF>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
+        const float unsat = task_eval<kGrad, kCF, true>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
         if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         if (A.obj) {
             if (A.R_pad <= 64) {

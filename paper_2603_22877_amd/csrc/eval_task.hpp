@@ -6,6 +6,8 @@
 // State access and gradient accumulation are template policies: global strided views with
 // L2 atomics (per-call path) or LDS-resident state with LDS atomics (fused solver).
 #pragma once
+#include <type_traits>
+
 #include "kernels_common.hpp"
 
 namespace fsmt {
@@ -23,6 +25,8 @@ struct TabView {
     cptr<int32_t> con_bucket;
     cptr<int32_t> con_local;
     cptr<GdInfo> gd;
+    cptr<GdForm> gdf;
+    cptr<SlimRec> srec;
     cptr<int32_t> atom_ptr;
     cptr<int32_t> atom_var;
     cptr<double> atom_coef;
@@ -46,6 +50,8 @@ struct TabView {
         t.con_bucket = as_cptr(h->d.con_bucket);
         t.con_local = as_cptr(h->d.con_local);
         t.gd = as_cptr(h->d.gd);
+        t.gdf = as_cptr(h->d.gdf);
+        t.srec = as_cptr(h->d.srec);
         t.atom_ptr = as_cptr(h->d.atom_ptr);
         t.atom_var = as_cptr(h->d.atom_var);
         t.atom_coef = as_cptr(h->d.atom_coef);
@@ -191,6 +197,7 @@ struct TaskCtx {
     BucketInfo B;         // bucket record with the template fields
     cptr<int32_t> sup;    // this lane's support column
     cptr<AtomRec> rec;    // this lane's first inline atom record (or null)
+    int local;            // position inside the bucket
     int c;                // original constraint id (or -1)
     int r;
     bool valid;
@@ -205,6 +212,7 @@ __device__ __forceinline__ TaskCtx task_ctx(const TabView &T, int pos, int r, bo
     const int local = pos - t.B.pos_begin;
     t.sup = T.sup + t.B.sup_base + local;
     t.rec = t.B.arec_base >= 0 ? T.arec + t.B.arec_base + local : nullptr;
+    t.local = local;
     t.c = T.pos_con[pos];
     t.r = r;
     t.valid = (t.c >= 0) && r_ok;
@@ -644,25 +652,42 @@ __device__ __forceinline__ void gd_atom(double lin, float rhs, float scale, bool
     }
 }
 
-template <int NBm, int NAm, bool kGrad, class St, class Sc>
-__device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, const St &st, double kappa, bool hard,
-                                           float wc, const Sc &sc, int lane) {
+__device__ __forceinline__ SlimRec load_slim(cptr<SlimRec> p) {
+    const cptr<int32_t> q = (cptr<int32_t>)p;
+    return SlimRec{q[0], q[1], __int_as_float(q[2])};
+}
+
+// kSlim: the atoms come from the slim records and the template's form (the per-call
+// kernel, where the table stream is the cost); otherwise from the 32-byte records, which
+// keep the form out of the scalar registers of the fused solver's kernels.
+template <int NBm, int NAm, bool kGrad, bool kSlim, class St, class Sc>
+__device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, const GdInfo &g, const St &st,
+                                           double kappa, bool hard, float wc, const Sc &sc, int lane) {
     const int NB = t.B.n_bslots, NA = t.B.n_slots - t.B.n_bslots, k = g.k;
     const int64_t np = t.B.n_pos;
     const int rr = t.valid ? t.r : 0;   // a row that exists for the reads of invalid lanes
-    // ---- reads: Boolean ids and atom records (slots past the template's count re-read its
-    // last one, so no read depends on a per-slot branch), then the state values they name
+    // the template's per-slot coefficients, scales and flags (wave-uniform, scalar loads)
+    const cptr<GdForm> form = T.gdf + t.B.tpl;
+    // ---- reads: Boolean ids and slim atom records (slots past the template's count re-read
+    // its last one, so no read depends on a per-slot branch), then the state values they name
     const int S = NB + NA;
     int idb[NBm];
 #pragma unroll
     for (int i = 0; i < NBm; ++i) idb[i] = t.sup[(int64_t)(i < S ? i : S - 1) * np];
-    AtomRec rec[NAm];
+    using Rec = typename std::conditional<kSlim, SlimRec, AtomRec>::type;
+    Rec rec[NAm];
     if (NA > 0) {
+        if constexpr (kSlim) {
+            const cptr<SlimRec> sp = T.srec + form->srec_base + t.local;
 #pragma unroll
-        for (int j = 0; j < NAm; ++j) rec[j] = load_rec(t.rec + (int64_t)(j < NA ? j : NA - 1) * np);
+            for (int j = 0; j < NAm; ++j) rec[j] = load_slim(sp + (int64_t)(j < NA ? j : NA - 1) * np);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NAm; ++j) rec[j] = load_rec(t.rec + (int64_t)(j < NA ? j : NA - 1) * np);
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < NAm; ++j) rec[j] = AtomRec{0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u};
+        for (int j = 0; j < NAm; ++j) rec[j] = Rec{};
     }
     float av[NBm], y0[NAm], y1[NAm];
 #pragma unroll
@@ -690,23 +715,36 @@ __device__ __forceinline__ float gd_eval_n(const TaskCtx &t, const GdInfo &g, co
         double lin = 0.0;
 #pragma unroll
         for (int j = 0; j < NAm; ++j) {
-            const AtomRec &a = rec[j];
+            float scale;
+            bool two, strict;
+            if constexpr (kSlim) {
+                const uint32_t fl = form->flags;
+                c0[j] = form->c0[j];   // slots past the template's count hold 0
+                c1[j] = form->c1[j];   // 0 for one-variable atoms
+                scale = form->scale[j];
+                two = (fl >> (8 + j)) & 1u;
+                strict = (fl >> j) & 1u;
+            } else {
+                c0[j] = rec[j].c0;
+                c1[j] = rec[j].c1;
+                scale = rec[j].scale;
+                two = (rec[j].flags & 2u) != 0;
+                strict = (rec[j].flags & 1u) != 0;
+            }
             if (j == 0 || !((g.same_lin >> j) & 1u)) {
 #pragma clang fp contract(off)
                 double acc = 0.0;
-                const double p0 = (double)a.c0 * (double)y0[j];
+                const double p0 = (double)c0[j] * (double)y0[j];
                 acc = acc + p0;
-                if (a.flags & 2u) {
-                    const double p1 = (double)a.c1 * (double)y1[j];
+                if (two) {
+                    const double p1 = (double)c1[j] * (double)y1[j];
                     acc = acc + p1;
                 }
                 lin = acc;
             }
             float pj, qj;
-            gd_atom(lin, a.rhs, a.scale, (a.flags & 1u) != 0, kappa, hard, pj, qj, da[j]);
+            gd_atom(lin, rec[j].rhs, scale, strict, kappa, hard, pj, qj, da[j]);
             la[j] = ((negA >> j) & 1u) ? pj : qj;
-            c0[j] = a.c0;
-            c1[j] = a.c1;   // 0 for one-variable atoms
         }
     }
     // ---- sum over the selector assignments
@@ -831,7 +869,7 @@ __device__ __forceinline__ void bind_msgs(Ms &W, float *base, int NN, int SS, in
 // One (constraint, restart) task: P[c False], and with kGrad the reverse sweep's gradient
 // scattered through the policy. With kCF > 0 a register message store is declared per task,
 // so its arrays are live only in the generic branch.
-template <bool kGrad, int kCF, class St, class Sc, class Ms>
+template <bool kGrad, int kCF, bool kSlim = false, class St, class Sc, class Ms>
 __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, const St &st, double kappa, bool hard,
                                            float wc, const Sc &sc, Ms &W, int lane) {
     if constexpr (kCF > 0) {
@@ -841,11 +879,11 @@ __device__ __forceinline__ float task_eval(const TabView &T, const TaskCtx &t, c
         if (t.B.pad < 0) {
             const GdInfo g = load_gd(T.gd + t.B.tpl);
             const int NB = t.B.n_bslots, NA = t.B.n_slots - t.B.n_bslots;
-            if (NB <= 1 && NA <= 2) return gd_eval_n<1, 2, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+            if (NB <= 1 && NA <= 2) return gd_eval_n<1, 2, kGrad, kSlim>(T, t, g, st, kappa, hard, wc, sc, lane);
             if constexpr (kCF >= 2) {
-                if (NB <= 2) return gd_eval_n<2, kGdMaxAtoms, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+                if (NB <= 2) return gd_eval_n<2, kGdMaxAtoms, kGrad, kSlim>(T, t, g, st, kappa, hard, wc, sc, lane);
             }
-            if constexpr (kCF >= 3) return gd_eval_n<kGdMaxBool, kGdMaxAtoms, kGrad>(t, g, st, kappa, hard, wc, sc, lane);
+            if constexpr (kCF >= 3) return gd_eval_n<kGdMaxBool, kGdMaxAtoms, kGrad, kSlim>(T, t, g, st, kappa, hard, wc, sc, lane);
         }
         if constexpr (Ms::kNodes > 0) {
             FSMT_MSG_STORE(Ms, Wt, nullptr, 0, 0, lane);

@@ -110,6 +110,22 @@ struct Node {
     uint16_t slot, hi, lo, pad;
 };
 
+// Guarded disjunctions stream slim atom records: in every member of such a template, atom
+// slot j has the same coefficients, scale and flags (kept once per template in GdForm), so
+// per (atom slot, position) only the variables and the right-hand side are stored, 12 bytes
+// instead of the 32 of an AtomRec: slim[srec_base + j * n_pos + local]. The AtomRec copies
+// stay for the exact check and the other passes.
+struct SlimRec {
+    int32_t v0, v1;   // real variables (v1 = v0 when the atom has one term)
+    float rhs;        // right-hand side in "<=" form
+};
+struct GdForm {
+    int64_t srec_base;             // offset of the template's bucket in the slim records
+    uint32_t flags;                // bit j: atom slot j strict; bit 8 + j: two variables
+    int32_t pad;
+    float c0[kGdMaxAtoms], c1[kGdMaxAtoms], scale[kGdMaxAtoms];
+};
+
 struct DeviceTables {
     TplInfo *tpl = nullptr;
     Node *nodes = nullptr;
@@ -130,6 +146,8 @@ struct DeviceTables {
     int32_t *lev = nullptr;           // per template: n_slots + 1 level starts
     int32_t *big_pos = nullptr;       // positions of the constraints in big buckets
     GdInfo *gd = nullptr;             // [n_tpl] guarded-disjunction records (k = -1: not one)
+    GdForm *gdf = nullptr;            // [n_tpl] their per-slot coefficients, scales and flags
+    SlimRec *srec = nullptr;          // slim atom records of the guarded-disjunction buckets
     float *real_lo = nullptr;         // [m] box of D (tightened by single-variable unit atoms)
     float *real_hi = nullptr;         // [m]
     int32_t *hs_ptr = nullptr;        // [H+1] half-spaces of D: q.y <= rhs (multi-variable unit atoms)

@@ -460,6 +460,24 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         key.push_back(cv.n_bslots);
         for (int t = 0; t < L; ++t) key.push_back(cv.lit_slot[t] * 2 + cv.lit_neg[t]);
         for (int64_t i = 0; i < cv.n_ops; ++i) key.push_back(cv.ops[i]);
+        // with the closed forms, small constraints are also keyed by their atoms' forms
+        // (terms, strictness, scale, coefficients with the larger first), so the members of a
+        // guarded-disjunction template share them slot by slot
+        if (closed && cv.n_bslots <= kGdMaxBool && (int)cv.ids.size() - cv.n_bslots <= kGdMaxAtoms) {
+            for (size_t s = cv.n_bslots; s < cv.ids.size(); ++s) {
+                const int k = cv.ids[s] - n;
+                const int64_t e0 = a_ptr[k], nt = a_ptr[k + 1] - e0;
+                float c0 = nt >= 1 ? (float)a_coef[e0] : 0.0f, c1 = nt >= 2 ? (float)a_coef[e0 + 1] : 0.0f;
+                if (nt == 2 && c1 > c0) std::swap(c0, c1);
+                const float sc = (float)a_scale[k];
+                int32_t w[3];
+                std::memcpy(&w[0], &c0, 4);
+                std::memcpy(&w[1], &c1, 4);
+                std::memcpy(&w[2], &sc, 4);
+                key.push_back((int32_t)(nt * 2 + a_strict[k]));
+                key.insert(key.end(), w, w + 3);
+            }
+        }
         std::string ks((const char *)key.data(), key.size() * sizeof(int32_t));
         auto it = tpl_index.find(ks);
         int t_id;
@@ -506,29 +524,61 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         return ok;
     };
     // guarded disjunctions keep their atoms in inline records (every atom of every member
-    // must qualify, else the template takes the generic passes); the run flags record which
-    // consecutive atom slots share variables (and coefficients) in every member
+    // must qualify, else the template takes the generic passes). The template's form holds
+    // each atom slot's coefficients, scale and flags, which must be the same in every member
+    // (the closed form streams only variables and right-hand sides); a two-variable atom may
+    // list its variables in either order to match (q.y is a sum of two exact FP64 products,
+    // so the order does not change it). The run flags record which consecutive atom slots
+    // share variables (and coefficients) in every member, in that matched order.
+    std::vector<GdForm> gd_form(T);
+    struct Canon { int32_t v0, v1; float c0, c1, sc; uint32_t fl; };
+    auto canon = [&](int k) {
+        const int64_t e0 = a_ptr[k];
+        const bool two = a_ptr[k + 1] - e0 == 2;
+        return Canon{a_var[e0], two ? a_var[e0 + 1] : a_var[e0], (float)a_coef[e0], two ? (float)a_coef[e0 + 1] : 0.0f,
+                     (float)a_scale[k], (a_strict[k] ? 1u : 0u) | (two ? 2u : 0u)};
+    };
+    auto matches = [](const GdForm &F, int j, Canon &a) {   // swaps a's terms if that matches
+        const uint32_t fl = ((F.flags >> j) & 1u) | (((F.flags >> (8 + j)) & 1u) << 1);
+        if (a.fl != fl || a.sc != F.scale[j]) return false;
+        if (a.c0 == F.c0[j] && a.c1 == F.c1[j]) return true;
+        if ((a.fl & 2u) && a.c1 == F.c0[j] && a.c0 == F.c1[j]) {
+            std::swap(a.v0, a.v1);
+            std::swap(a.c0, a.c1);
+            return true;
+        }
+        return false;
+    };
     for (int t = 0; t < T; ++t) {
         Template &tp = tpls[t];
+        gd_form[t] = GdForm{};
+        gd_form[t].srec_base = -1;
         if (tp.gd.k < 0 || members[t].empty()) continue;
         const int nb = tp.n_bslots, na = tp.n_slots - tp.n_bslots;
+        GdForm &F = gd_form[t];
+        {
+            const int32_t *ids0 = con_ids.data() + con_sup_off[members[t][0]];
+            for (int j = 0; j < na; ++j) {
+                const Canon a = canon(ids0[nb + j] - n);
+                F.c0[j] = a.c0;
+                F.c1[j] = a.c1;
+                F.scale[j] = a.sc;
+                F.flags |= ((a.fl & 1u) << j) | (((a.fl >> 1) & 1u) << (8 + j));
+            }
+        }
         bool ok = true;
-        uint32_t same_vars = 0, same_lin = 0;
+        uint32_t same_vars = 0;
         for (int j = 1; j < na; ++j) same_vars |= 1u << j;
-        same_lin = same_vars;
         for (int c : members[t]) {
             const int32_t *ids = con_ids.data() + con_sup_off[c];
+            Canon prev{};
             for (int j = 0; j < na && ok; ++j) {
                 const int kj = ids[nb + j] - n;
-                ok = atom_inline_ok(kj);
-                if (!ok || j == 0) continue;
-                const int ki = ids[nb + j - 1] - n;
-                const int ni = a_ptr[ki + 1] - a_ptr[ki], nj = a_ptr[kj + 1] - a_ptr[kj];
-                const int ei = a_ptr[ki], ej = a_ptr[kj];
-                const bool vars = ni == nj && a_var[ei] == a_var[ej] && (ni < 2 || a_var[ei + 1] == a_var[ej + 1]);
-                const bool coef = vars && a_coef[ei] == a_coef[ej] && (ni < 2 || a_coef[ei + 1] == a_coef[ej + 1]);
-                if (!vars) same_vars &= ~(1u << j);
-                if (!coef) same_lin &= ~(1u << j);
+                Canon a = canon(kj);
+                ok = atom_inline_ok(kj) && matches(F, j, a);
+                if (ok && j > 0 && !(a.v0 == prev.v0 && a.v1 == prev.v1 && (a.fl & 2u) == (prev.fl & 2u)))
+                    same_vars &= ~(1u << j);
+                prev = a;
             }
             if (!ok) break;
         }
@@ -536,6 +586,9 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             tp.gd.k = -1;
             continue;
         }
+        uint32_t same_lin = same_vars;
+        for (int j = 1; j < na; ++j)
+            if (F.c0[j] != F.c0[j - 1] || F.c1[j] != F.c1[j - 1]) same_lin &= ~(1u << j);
         tp.gd.same_vars = same_vars;
         tp.gd.same_lin = same_lin;
     }
@@ -599,6 +652,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     }
     // inline atom records for buckets whose atoms all qualify
     std::vector<AtomRec> arec;
+    std::vector<SlimRec> srec;
     bool all_inline = true;
     for (BucketInfo &bi : buckets) {
         const int na = bi.n_slots - bi.n_bslots;
@@ -628,6 +682,26 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
                 rr.atom = k;
                 rr.flags = (a_strict[k] ? 1u : 0u) | ((e1 - e0 == 2) ? 2u : 0u);
             }
+        if (bi.pad < 0) {
+            // guarded disjunction: both record kinds list a two-variable atom's terms in the
+            // order that matches the template's form (the run flags were found in that
+            // order), plus the slim copies (padding positions name variable 0)
+            GdForm &F = gd_form[bi.tpl];
+            F.srec_base = (int64_t)srec.size();
+            srec.resize(srec.size() + (size_t)na * bi.n_pos, SlimRec{0, 0, 0.0f});
+            for (int s = 0; s < na; ++s)
+                for (int i = 0; i < bi.n_con; ++i) {
+                    const int k = sup[bi.sup_base + (int64_t)(bi.n_bslots + s) * bi.n_pos + i] - n;
+                    Canon a = canon(k);
+                    (void)matches(F, s, a);   // holds for every member (checked above)
+                    AtomRec &rr = arec[bi.arec_base + (int64_t)s * bi.n_pos + i];
+                    rr.v0 = a.v0;
+                    rr.v1 = a.v1;
+                    rr.c0 = a.c0;
+                    rr.c1 = a.c1;
+                    srec[F.srec_base + (int64_t)s * bi.n_pos + i] = SlimRec{a.v0, a.v1, (float)a_rhs[k]};
+                }
+        }
     }
     std::vector<int32_t> task_bucket((size_t)bstart.back() / 64);
     for (size_t b = 0; b < buckets.size(); ++b)
@@ -784,6 +858,8 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
     if (!rc) rc = U.put(&h->d.lev, lev, "level starts");
     if (!rc) rc = U.put(&h->d.big_pos, big_pos, "big-diagram positions");
     if (!rc) rc = U.put(&h->d.gd, gd_rec, "guarded disjunctions");
+    if (!rc) rc = U.put(&h->d.gdf, gd_form, "guarded-disjunction forms");
+    if (!rc) rc = U.put(&h->d.srec, srec, "slim atom records");
     h->all_inline = all_inline;
     if (all_inline) {   // every atom is reached through its inline record
         a_ptr.assign(1, 0);

@@ -141,6 +141,28 @@ def test_guarded_disjunctions_are_recognized_from_the_diagram():
         assert got == int(want), (kind, lits, ops)
 
 
+def test_guarded_disjunction_members_share_their_atom_forms():
+    """The closed form streams only variables and right-hand sides: the members of one
+    guarded-disjunction template share each atom slot's coefficients, scale and strictness.
+    Atoms that differ only in which of their two variables carries which coefficient stay in
+    one template (the terms are matched in either order); other forms get templates of
+    their own, and every constraint keeps the closed form."""
+    def build(atoms):
+        b = Builder(len(atoms), 3, real_lo=np.zeros(3), real_hi=np.ones(3))
+        ks = [b.atom(v, c, OP_LE, r) for v, c, r in atoms]
+        for i, k in enumerate(ks):
+            b.add(KIND_CLAUSE, [lit(i, True), lit(k)])
+        return b.build()
+    same = build([([0, 1], [1.0, -1.0], 0.25), ([0, 2], [-1.0, 1.0], -0.5), ([1, 2], [1.0, -1.0], 0.0)])
+    i1 = fsmt.xbdd_info(compile_host(same))
+    assert i1["n_gd"] == 3 and i1["n_templates"] == 1
+    mixed = build([([0, 1], [1.0, -1.0], 0.25), ([0, 2], [2.0, -1.0], 0.0), ([1], [1.0], 0.5)])
+    i2 = fsmt.xbdd_info(compile_host(mixed))
+    assert i2["n_gd"] == 3 and i2["n_templates"] == 3
+    # the generic passes do not split shapes by atom forms
+    assert fsmt.xbdd_info(compile_host(mixed, messages=2))["n_templates"] == 1
+
+
 def test_variable_order_invariance_of_cop():
     """The same constraint with Boolean ids permuted has the same COP (order does not matter)."""
     rng = np.random.default_rng(4)

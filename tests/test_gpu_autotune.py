@@ -44,13 +44,16 @@ def test_tuned_plan_not_slower_than_model(cfg_id, tmp_path, monkeypatch):
     print(f"config {cfg_id}: chosen {plan.label} {plan.inst_schedule[:8]} cluster {plan.cluster}, "
           f"candidates {plan.candidates}", flush=True)
     assert not plan.cached and os.path.exists(tmp_path / "tune.json")
-    assert plan.us_per_level <= min(plan.candidates.values()) * (1 + 1e-9)
+    # the fastest candidate, or the model's plan when no candidate beats it by the margin
+    assert plan.us_per_level <= min(plan.candidates.values()) * (1 + 0.03 + 1e-9)
+    if plan.label != "model":
+        assert plan.us_per_level * 1.03 < plan.candidates["model"]
     if plan.label != "model":
         # measured again, alternating, best of several: the chosen plan against the model's
         model, tuned = float("inf"), float("inf")
         for _ in range(3):
-            model = min(model, AT.measure(hs, init, cfg, steps=8, reps=2)[1])
-            tuned = min(tuned, AT.measure(hs, init, plan.apply(cfg), steps=8, reps=2)[1])
+            model = min(model, AT.measure(hs, init, cfg, steps=16, reps=3)[1])
+            tuned = min(tuned, AT.measure(hs, init, plan.apply(cfg), steps=16, reps=3)[1])
         print(f"config {cfg_id}: model {model / 1e3:.3f} ms per level, tuned {tuned / 1e3:.3f}", flush=True)
         assert tuned <= 1.05 * model
     again = AT.tune(hs, init, cfg)
