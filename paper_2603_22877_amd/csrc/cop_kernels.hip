@@ -85,6 +85,64 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     }
 }
 
+// One restart, gradient summed per workgroup in LDS (small diagrams, register message
+// store): the workgroup's lanes add into an LDS copy of the whole gradient (n + m floats),
+// which is written out once as the workgroup's partial row; sum_rows_kernel adds the rows.
+// This replaces the device-scope atomics on the caller's gradient, which are performed at
+// the memory side and serialize on a variable that many waves share (the first rectangle of
+// consecutive placement pairs).
+template <int kCF>
+__global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *part) {
+    using Ms = typename MsgOf<kMsgSmall>::type;
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    const int wib = wave_id();
+    const int wpb = blockDim.x >> 6;
+    const int n = A.T.n_bool, nm = A.T.n_bool + A.T.n_real;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) lds[i] = 0.0f;
+    __syncthreads();
+    FSMT_MSG_STORE(Ms, W, nullptr, 0, 0, lane);
+    const GlobalState st{A.a, A.b};
+    const LdsScatter sc{lds, lds + n};
+    float oacc = 0.0f;
+    for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < A.n_tasks; task += (int64_t)gridDim.x * wpb) {
+        const TaskCtx t = task_ctx(A.T, (int)(task * 64) + lane, 0, true);
+        if (t.B.big) continue;   // evaluated by cop_level_kernel
+        const float wc = t.valid ? A.w.at(0, t.c) : 0.0f;   // requested before the forward pass
+        const float unsat = task_eval<true, kCF, true>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
+        if (t.valid && A.unsat.data) A.unsat.at(0, t.c) = unsat;
+        oacc += wc * unsat;
+    }
+    if (A.obj) {
+        for (int off = 32; off > 0; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
+        if (lane == 0 && oacc != 0.0f) atomic_add_f32(A.obj, oacc);
+    }
+    __syncthreads();
+    float *row = part + (int64_t)blockIdx.x * nm;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) row[i] = lds[i];
+}
+
+// Gradient of one restart from the workgroups' partial rows: 64 variables per block, the
+// rows split over 16 stripes and the stripes' sums added in LDS; stored into (or added to)
+// the caller's views.
+__global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int rows, int n, int m, View ga, View gb,
+                                                        int accumulate) {
+    __shared__ float red[16][64];
+    const int c = threadIdx.x & 63, s = threadIdx.x >> 6;
+    const int v = blockIdx.x * 64 + c, nm = n + m;
+    float acc = 0.0f;
+    if (v < nm)
+        for (int w = s; w < rows; w += 16) acc += part[(int64_t)w * nm + v];
+    red[s][c] = acc;
+    __syncthreads();
+    if (s == 0 && v < nm) {
+        float t = 0.0f;
+        for (int q = 0; q < 16; ++q) t += red[q][c];
+        gref<float> dst = v < n ? ga.at(0, v) : gb.at(0, v - n);
+        if (accumulate) dst += t; else dst = t;
+    }
+}
+
 // ------------------------------------------------------------------ big diagrams
 // Level-synchronous passes (see level_eval): one wavefront per (big constraint, chunk of
 // restarts); the wave stages the constraint's node table in its LDS rows once and evaluates
@@ -392,6 +450,15 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const int n = h->n_bool, m = h->n_real;
     const bool stage = grad && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
                        !(ga.stride_r == 1 && gb.stride_r == 1);
+    // One restart over small diagrams with a register message store: the gradient is
+    // summed per workgroup in LDS (cop_lds_grad_kernel) and the workgroups' rows are added
+    // afterwards, one row per CU.
+    int n_cu = 256;
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cf = closed_level(h);
+    const bool lds_grad = grad && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons && n + m > 0 &&
+                          (int64_t)(n + m) * (int64_t)sizeof(float) <= 64 * 1024;
+    const int grad_rows = lds_grad ? (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (h->n_pos / 64 + 15) / 16)) : 0;
     struct Stage {   // freed stream-ordered after whatever the call enqueued
         float *p = nullptr;
         hipStream_t st = nullptr;
@@ -400,6 +467,13 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         }
     } sg;
     sg.st = st;
+    if (lds_grad) {
+        if (hipMallocAsync((void **)&sg.p, sizeof(float) * (size_t)(n + m) * grad_rows, st) != hipSuccess) {
+            (void)hipGetLastError();
+            sg.p = nullptr;
+            return set_error(FSMT_ENOMEM, "gradient rows allocation failed");
+        }
+    }
     if (stage) {
         if (hipMallocAsync((void **)&sg.p, sizeof(float) * (size_t)(n + m) * R, st) != hipSuccess) {
             (void)hipGetLastError();
@@ -411,7 +485,8 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     float *const sbuf = sg.p;
     if (!(flags & FSMT_ACCUMULATE)) {
         if (obj && (rc = fill_f32(obj, R, 0.0f, st))) return rc;
-        if (grad && !stage && ((rc = fill_view(ga, 0.0f, st)) || (rc = fill_view(gb, 0.0f, st)))) return rc;
+        if (grad && !stage && !lds_grad && ((rc = fill_view(ga, 0.0f, st)) || (rc = fill_view(gb, 0.0f, st))))
+            return rc;
     }
     if (h->n_pos == 0) {
         if (stage) {
@@ -457,8 +532,19 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const int blocks = (int)((waves + wpb - 1) / wpb);
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
-    if (h->n_big < h->n_cons) {
-        const int cf = closed_level(h);
+    if (lds_grad) {
+        const size_t glds = sizeof(float) * (size_t)(n + m);
+        if (cf == 0)
+            hipLaunchKernelGGL(cop_lds_grad_kernel<0>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
+        else if (cf == 1)
+            hipLaunchKernelGGL(cop_lds_grad_kernel<1>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
+        else
+            hipLaunchKernelGGL(cop_lds_grad_kernel<2>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
+        if ((rc = launch_status("cop kernel (gradient in LDS)"))) return rc;
+        hipLaunchKernelGGL(sum_rows_kernel, dim3((n + m + 63) / 64), dim3(1024), 0, st, (const float *)sbuf, grad_rows, n,
+                           m, View::of(ga), View::of(gb), flags & FSMT_ACCUMULATE);
+        if ((rc = launch_status("gradient rows"))) return rc;
+    } else if (h->n_big < h->n_cons) {
         if (grad)
             launch_cop<true>(cf, msg, g, bl, lds, st, A);
         else
@@ -483,8 +569,6 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
         L.hard = A.hard;
         L.lds_nodes = h->big_max_nodes;
         L.lds_slots = std::max(h->big_max_slots, 1);
-        int n_cu = 256;
-        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
         L.chunk = level_chunk((int64_t)h->n_big * R, n_cu);
         const int lwpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / level_wave_bytes));
         const int64_t ltasks = (int64_t)h->n_big * ((R + L.chunk - 1) / L.chunk);

@@ -127,6 +127,32 @@ def test_mixed_small_and_big_diagrams(seed, R):
         _compare(p, a, b, kap, layout="cols")
 
 
+@pytest.mark.parametrize("cfg,R", [(2, 1), (3, 1), (3, 16)])
+def test_backward_accumulates_into_the_outputs(cfg, R):
+    """FSMT_ACCUMULATE adds into obj and the gradients instead of overwriting them: a
+    second call doubles them (one restart sums the gradient per workgroup in LDS and adds
+    the rows; 16 restarts go through the restart-contiguous stage)."""
+    p = W.make_config(cfg)
+    print(f"accumulate config {cfg} R={R}", flush=True)
+    a, b = W.initial_points(p, R, cfg, 3)
+    h = fsmt.xbdd_compile(p)
+    ta, tb, wt = T(a), T(b), T(np.ones(p.n_cons))
+    ga = torch.full((R, p.n_bool), 123.0, device=dev())
+    gb = torch.full((R, p.n_real), -7.0, device=dev())
+    obj = torch.full((R,), 5.0, device=dev())
+    fsmt.cop_backward(h, ta, tb, 0.3, wt, obj, ga, gb)              # overwrites the junk
+    g1, b1, o1 = ga.clone(), gb.clone(), obj.clone()
+    fsmt.cop_backward(h, ta, tb, 0.3, wt, obj, ga, gb, flags=fsmt.FSMT_ACCUMULATE)
+    o = oracle.objective(p, a, b, 0.3)
+    assert_objective(o1.cpu().numpy(), o["U"], np.full(R, float(p.n_cons)))
+    assert_gradient(g1.cpu().numpy(), o["grad_a"], o["absg_a"], "grad_a")
+    assert_gradient(b1.cpu().numpy(), o["grad_b"], o["absg_b"], "grad_b")
+    for two, one in ((ga, g1), (gb, b1), (obj, o1)):
+        d = (two - 2 * one).abs().max().item()
+        assert d <= 1e-5 * max(one.abs().max().item(), 1e-30), d
+    h.free()
+
+
 def test_fig2_toy_values():
     p = W.make_fig2_toy()
     a = np.array([[0.3], [-0.9], [1.0]], np.float32)
@@ -136,7 +162,7 @@ def test_fig2_toy_values():
 
 
 @pytest.mark.parametrize("cfg,R,kap", [(1, 1, 0.3), (1, 1, INF), (2, 64, 0.05), (2, 64, 0.5),
-                                       (3, 16, 0.1), (3, 16, 1.0)])
+                                       (3, 16, 0.1), (3, 16, 1.0), (2, 1, 0.3), (3, 1, 0.5)])
 @pytest.mark.parametrize("messages", ["auto", "lds", "generic"])
 def test_workload_configs(cfg, R, kap, messages):
     print(f"config {cfg} R={R} kappa={kap} messages={messages}", flush=True)
