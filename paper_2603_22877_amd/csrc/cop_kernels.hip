@@ -88,6 +88,8 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
 // One restart, gradient summed per workgroup in LDS (small diagrams, register message
 // store): the workgroup's lanes add into an LDS copy of the whole gradient (n + m floats),
 // which is written out once as the workgroup's partial row; sum_rows_kernel adds the rows.
+// The restart's point (a, b) is copied into LDS too, so the tasks' state gathers are LDS
+// reads.
 // This replaces the device-scope atomics on the caller's gradient, which are performed at
 // the memory side and serialize on a variable that many waves share (the first rectangle of
 // consecutive placement pairs).
@@ -99,10 +101,14 @@ __global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *pa
     const int wib = wave_id();
     const int wpb = blockDim.x >> 6;
     const int n = A.T.n_bool, nm = A.T.n_bool + A.T.n_real;
-    for (int i = threadIdx.x; i < nm; i += blockDim.x) lds[i] = 0.0f;
+    float *const sy = lds + nm;   // a then b
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
+        lds[i] = 0.0f;
+        sy[i] = i < n ? (float)A.a.at(0, i) : (float)A.b.at(0, i - n);
+    }
     __syncthreads();
     FSMT_MSG_STORE(Ms, W, nullptr, 0, 0, lane);
-    const GlobalState st{A.a, A.b};
+    const LdsState st{sy, sy + n};
     const LdsScatter sc{lds, lds + n};
     float oacc = 0.0f;
     for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < A.n_tasks; task += (int64_t)gridDim.x * wpb) {
@@ -457,7 +463,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
     const int cf = closed_level(h);
     const bool lds_grad = grad && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons && n + m > 0 &&
-                          (int64_t)(n + m) * (int64_t)sizeof(float) <= 64 * 1024;
+                          (int64_t)(n + m) * (int64_t)(2 * sizeof(float)) <= 96 * 1024;
     const int grad_rows = lds_grad ? (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (h->n_pos / 64 + 15) / 16)) : 0;
     struct Stage {   // freed stream-ordered after whatever the call enqueued
         float *p = nullptr;
@@ -533,7 +539,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
     if (lds_grad) {
-        const size_t glds = sizeof(float) * (size_t)(n + m);
+        const size_t glds = 2 * sizeof(float) * (size_t)(n + m);   // gradient, point
         if (cf == 0)
             hipLaunchKernelGGL(cop_lds_grad_kernel<0>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
         else if (cf == 1)
