@@ -463,7 +463,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
     const int cf = closed_level(h);
     const bool lds_grad = grad && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons && n + m > 0 &&
-                          (int64_t)(n + m) * (int64_t)(2 * sizeof(float)) <= 96 * 1024;
+                          (int64_t)(n + m) * (int64_t)(2 * sizeof(float)) <= 64 * 1024;   // default LDS limit
     const int grad_rows = lds_grad ? (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (h->n_pos / 64 + 15) / 16)) : 0;
     struct Stage {   // freed stream-ordered after whatever the call enqueued
         float *p = nullptr;
