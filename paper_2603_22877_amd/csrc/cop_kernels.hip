@@ -89,10 +89,8 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
 // store): the workgroup's lanes add into an LDS copy of the whole gradient (n + m floats),
 // which is written out once as the workgroup's partial row; sum_rows_kernel adds the rows.
 // The restart's point (a, b) is copied into LDS too, so the tasks' state gathers are LDS
-// reads.
-// This replaces the device-scope atomics on the caller's gradient, which are performed at
-// the memory side and serialize on a variable that many waves share (the first rectangle of
-// consecutive placement pairs).
+// reads. This replaces the device-scope atomics on the caller's gradient, which are
+// performed at the memory side (one line write per variable and wave-wide atomic).
 template <int kCF>
 __global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *part) {
     using Ms = typename MsgOf<kMsgSmall>::type;
