@@ -768,10 +768,10 @@ fsmt_status solve_impl(const fsmt_xbdd *const *insts, int32_t n_inst, const fsmt
                 return set_error(FSMT_EUNSUPPORTED, "cluster of %d workgroups per restart cannot be co-resident", k);
         } else if (ib.empty()) {
             // automatic: the largest power of two that leaves each wave at least two tasks
-            // per step and keeps every workgroup resident. Measured per PGD step: config 3
-            // (182 tasks per restart, 8 waves), 16 restarts: 306 us at k = 1, 163 at 2, 89 at
-            // 4, 59 at 8; config 2 (66 tasks, 16 waves), 64 restarts: 22.8 us at k = 1,
-            // 21.9 at 2, 22.9 at 4.
+            // per step and keeps every workgroup resident. Measured per PGD step: placement
+            // of 150 rectangles (182 tasks per restart, 8 waves), 16 restarts: 306 us at
+            // k = 1, 163 at 2, 89 at 4, 59 at 8; scheduling 200 jobs x 10 machines (66 tasks,
+            // 16 waves), 64 restarts: 22.8 us at k = 1, 21.9 at 2, 22.9 at 4.
             const int64_t resd = resident_of(true);
             while (k < 16 && min_tasks >= (int64_t)2 * (2 * k) * waves && total_r * 2 * k <= resd) k *= 2;
         }
