@@ -84,6 +84,33 @@ def test_config4_sampled_gradients():
         h.free()
 
 
+def test_one_restart_gradient_both_paths():
+    """cop_backward at one restart on the uneven batch's instances: those whose n + m fits
+    the per-workgroup LDS gradient take that path, the larger ones the device-atomic path;
+    sampled coordinates of both against the oracle, and the objective."""
+    probs = W.make_batch_config4()
+    picks = [i for i, p in enumerate(probs) if p.n_bool + p.n_real <= 8192][:3]
+    picks += [i for i, p in enumerate(probs) if p.n_bool + p.n_real > 8192][:2]
+    rng = np.random.default_rng(43)
+    for i in picks:
+        p = probs[i]
+        op = oracle.OracleProblem(p)
+        h = fsmt.xbdd_compile(p)
+        a, b = W.initial_points(p, 1, 4, 100 + i)
+        kap = 0.5 / p.meta.get("mean_duration", p.meta.get("mean_side", 1.0))
+        ga = torch.zeros(1, p.n_bool, device=dev())
+        gb = torch.zeros(1, p.n_real, device=dev())
+        obj = torch.zeros(1, device=dev())
+        fsmt.cop_backward(h, T(a), T(b), kap, T(np.ones(p.n_cons)), obj, ga, gb)
+        torch.cuda.synchronize()
+        bools, reals = _pick(p, rng, 4, 4)
+        print(f"one restart, instance {i} {p.meta['family']} n+m={p.n_bool + p.n_real} C={p.n_cons}", flush=True)
+        assert_sampled_gradient(op, p, a, b, kap, ga.cpu().numpy(), gb.cpu().numpy(), bools, reals)
+        o = oracle.objective(op, a, b, kap, grad=False, per_constraint=False)
+        assert_objective(obj.cpu().numpy(), o["U"], float(p.n_cons))
+        h.free()
+
+
 def test_config4_fused_step_sampled_instances():
     """One fused step of the whole uneven batch (persistent and grid schedules in one call):
     on the smaller instances of each family, the step against the oracle's projected step
