@@ -450,17 +450,20 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     // the per-XCD L2, one memory transaction per cache line touched, so when the caller's
     // gradient rows are not restart-contiguous the sums go to a restart-contiguous stage
     // ([n + m][R], one line per variable and 16 restarts) and are moved into the caller's
-    // views afterwards.
+    // views afterwards. With one restart over small diagrams with a register message store,
+    // the gradient is summed per workgroup in LDS (cop_lds_grad_kernel) and the workgroups'
+    // rows are added afterwards, one row per CU. Both are taken only for instances of at
+    // least 8 tasks (64-position groups) per CU: on smaller ones the atomics cost little and
+    // the extra allocation and launches would dominate the call.
     const int n = h->n_bool, m = h->n_real;
-    const bool stage = grad && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
-                       !(ga.stride_r == 1 && gb.stride_r == 1);
-    // One restart over small diagrams with a register message store: the gradient is
-    // summed per workgroup in LDS (cop_lds_grad_kernel) and the workgroups' rows are added
-    // afterwards, one row per CU.
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    const bool large = (int64_t)h->n_pos / 64 >= (int64_t)8 * n_cu;
+    const bool stage = grad && large && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
+                       !(ga.stride_r == 1 && gb.stride_r == 1);
     const int cf = closed_level(h);
-    const bool lds_grad = grad && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons && n + m > 0 &&
+    const bool lds_grad = grad && large && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons &&
+                          n + m > 0 &&
                           (int64_t)(n + m) * (int64_t)(2 * sizeof(float)) <= 64 * 1024;   // default LDS limit
     const int grad_rows = lds_grad ? (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (h->n_pos / 64 + 15) / 16)) : 0;
     struct Stage {   // freed stream-ordered after whatever the call enqueued

@@ -152,6 +152,37 @@ def test_config4_fused_step_sampled_instances():
         h.free()
 
 
+@pytest.mark.parametrize("R", [1, 16])
+def test_placement1200_per_call_sampled(R):
+    """Paper-scale placement per call (cop_backward), where the large-instance gradient
+    paths run: at one restart the gradient summed per workgroup in LDS and added from one
+    row per CU, at 16 the restart-contiguous stage. Sampled rectangles (rotation bit and
+    both coordinates) against the oracle's partial derivatives, and a second call with
+    FSMT_ACCUMULATE doubling them."""
+    p = W.make_config(5)
+    op = oracle.OracleProblem(p)
+    h = fsmt.xbdd_compile(p)
+    a, b = W.initial_points(p, R, 5, 11)
+    kap = 1.0 / p.meta["mean_side"]
+    ga = torch.zeros(R, p.n_bool, device=dev())
+    gb = torch.zeros(R, p.n_real, device=dev())
+    obj = torch.zeros(R, device=dev())
+    wt = T(np.ones(p.n_cons))
+    fsmt.cop_backward(h, T(a), T(b), kap, wt, obj, ga, gb)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(47)
+    rects = np.sort(rng.choice(p.n_bool, 4, replace=False))
+    print(f"placement 1200 per call R={R}: rectangles {rects.tolist()}", flush=True)
+    g1a, g1b, o1 = ga.cpu().numpy().copy(), gb.cpu().numpy().copy(), obj.cpu().numpy().copy()
+    assert_sampled_gradient(op, p, a, b, kap, g1a, g1b, rects, np.concatenate([rects, p.n_bool + rects]))
+    fsmt.cop_backward(h, T(a), T(b), kap, wt, obj, ga, gb, flags=fsmt.FSMT_ACCUMULATE)
+    torch.cuda.synchronize()
+    for two, one in ((ga.cpu().numpy(), g1a), (gb.cpu().numpy(), g1b), (obj.cpu().numpy(), o1)):
+        d = np.abs(two - 2 * one).max()
+        assert d <= 1e-5 * max(np.abs(one).max(), 1e-30), d
+    h.free()
+
+
 def test_config5_fused_step_sampled():
     """Paper-scale placement, 16 restarts, one fused step in the benchmark's launch
     configuration: the step at sampled rectangles (rotation bit and both coordinates)
