@@ -21,8 +21,10 @@
 //   scatter  : grad_a += w (-1/2) dP/dp; grad_b[j] += w dP/dp * dp/dz * q_j
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "fsmt_internal.hpp"
 #include "eval_task.hpp"
@@ -85,64 +87,92 @@ __global__ void __launch_bounds__(256) cop_kernel(CopArgs A) {
     }
 }
 
-// One restart, gradient summed per workgroup in LDS (small diagrams, register message
-// store): the workgroup's lanes add into an LDS copy of the whole gradient (n + m floats),
-// which is written out once as the workgroup's partial row; sum_rows_kernel adds the rows.
-// The restart's point (a, b) is copied into LDS too, so the tasks' state gathers are LDS
-// reads. This replaces the device-scope atomics on the caller's gradient, which are
-// performed at the memory side (one line write per variable and wave-wide atomic).
-template <int kCF>
-__global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *part) {
+// Restarts in groups of G (1, 2 or 4; small diagrams, register message store): each
+// workgroup serves one group, its waves holding 64 / G constraints x G restarts, and adds the
+// gradient into an LDS copy of the group's n + m variables x G restarts (restart-minor),
+// written out once as the workgroup's partial row; sum_rows_kernel adds the rows of each
+// group. The group's point is copied into LDS too, so the state gathers are LDS reads. This
+// replaces the device-scope atomics on the caller's gradient, which are performed at the
+// memory side (one line write per variable and wave-wide atomic).
+struct LdsStateG {
+    const float *a, *b;
+    int G, r0;
+    __device__ __forceinline__ float av(int r, int i) const { return a[i * G + ((r - r0) & (G - 1))]; }
+    __device__ __forceinline__ float bv(int r, int j) const { return b[j * G + ((r - r0) & (G - 1))]; }
+};
+struct LdsScatterG {
+    float *ga, *gb;
+    int G, r0;
+    __device__ __forceinline__ void add_a(int r, int i, float g, int) const {
+        if (i >= 0 && g != 0.0f) atomicAdd(ga + i * G + ((r - r0) & (G - 1)), g);
+    }
+    __device__ __forceinline__ void add_b(int r, int j, float g, int) const {
+        if (j >= 0 && g != 0.0f) atomicAdd(gb + j * G + ((r - r0) & (G - 1)), g);
+    }
+    __device__ __forceinline__ void add_b_direct(int r, int j, float g) const {
+        atomicAdd(gb + j * G + ((r - r0) & (G - 1)), g);
+    }
+};
+
+template <int kCF, int G>
+__global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *part, int n_groups) {
     using Ms = typename MsgOf<kMsgSmall>::type;
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wib = wave_id();
     const int wpb = blockDim.x >> 6;
     const int n = A.T.n_bool, nm = A.T.n_bool + A.T.n_real;
-    float *const sy = lds + nm;   // a then b
-    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
-        lds[i] = 0.0f;
-        sy[i] = i < n ? (float)A.a.at(0, i) : (float)A.b.at(0, i - n);
+    const int group = (int)(blockIdx.x % n_groups), r0 = group * G;
+    const int64_t wg = blockIdx.x / n_groups, n_wg = gridDim.x / n_groups;
+    float *const sy = lds + nm * G;   // a then b, [variable][G]
+    for (int e = threadIdx.x; e < nm * G; e += blockDim.x) {
+        const int v = e / G, r = r0 + (e - v * G);
+        lds[e] = 0.0f;
+        sy[e] = r < A.R ? (v < n ? (float)A.a.at(r, v) : (float)A.b.at(r, v - n)) : 0.0f;
     }
     __syncthreads();
     FSMT_MSG_STORE(Ms, W, nullptr, 0, 0, lane);
-    const LdsState st{sy, sy + n};
-    const LdsScatter sc{lds, lds + n};
+    const LdsStateG st{sy, sy + n * G, G, r0};
+    const LdsScatterG sc{lds, lds + n * G, G, r0};
+    const int64_t n_tasks = (int64_t)A.T.n_pos * G / 64;
+    const int r = r0 + (lane & (G - 1));
     float oacc = 0.0f;
-    for (int64_t task = (int64_t)blockIdx.x * wpb + wib; task < A.n_tasks; task += (int64_t)gridDim.x * wpb) {
-        const TaskCtx t = task_ctx(A.T, (int)(task * 64) + lane, 0, true);
+    for (int64_t task = wg * wpb + wib; task < n_tasks; task += n_wg * wpb) {
+        const TaskCtx t = task_ctx(A.T, (int)(task * (64 / G)) + lane / G, r, r < A.R);
         if (t.B.big) continue;   // evaluated by cop_level_kernel
-        const float wc = t.valid ? A.w.at(0, t.c) : 0.0f;   // requested before the forward pass
+        const float wc = t.valid ? A.w.at(r, t.c) : 0.0f;   // requested before the forward pass
         const float unsat = task_eval<true, kCF, true>(A.T, t, st, A.kappa, A.hard != 0, wc, sc, W, lane);
-        if (t.valid && A.unsat.data) A.unsat.at(0, t.c) = unsat;
+        if (t.valid && A.unsat.data) A.unsat.at(r, t.c) = unsat;
         oacc += wc * unsat;
     }
-    if (A.obj) {
-        for (int off = 32; off > 0; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
-        if (lane == 0 && oacc != 0.0f) atomic_add_f32(A.obj, oacc);
+    if (A.obj) {   // lanes G apart hold the same restart
+        for (int off = 32; off >= G; off >>= 1) oacc += __shfl_xor(oacc, off, 64);
+        if (lane < G && r0 + lane < A.R && oacc != 0.0f) atomic_add_f32(A.obj + r0 + lane, oacc);
     }
     __syncthreads();
-    float *row = part + (int64_t)blockIdx.x * nm;
-    for (int i = threadIdx.x; i < nm; i += blockDim.x) row[i] = lds[i];
+    float *row = part + (int64_t)blockIdx.x * nm * G;
+    for (int e = threadIdx.x; e < nm * G; e += blockDim.x) row[e] = lds[e];
 }
 
-// Gradient of one restart from the workgroups' partial rows: 64 variables per block, the
-// rows split over 16 stripes and the stripes' sums added in LDS; stored into (or added to)
-// the caller's views.
-__global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int rows, int n, int m, View ga, View gb,
-                                                        int accumulate) {
+// The groups' gradients from the workgroups' partial rows (row b belongs to group
+// b mod n_groups): 64 elements per block, the rows split over 16 stripes and the stripes'
+// sums added in LDS; stored into (or added to) the caller's views.
+__global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int n_groups, int n_wg, int G, int R, int n,
+                                                        int m, View ga, View gb, int accumulate) {
     __shared__ float red[16][64];
     const int c = threadIdx.x & 63, s = threadIdx.x >> 6;
-    const int v = blockIdx.x * 64 + c, nm = n + m;
+    const int nm = n + m, group = blockIdx.y;
+    const int e = blockIdx.x * 64 + c;
     float acc = 0.0f;
-    if (v < nm)
-        for (int w = s; w < rows; w += 16) acc += part[(int64_t)w * nm + v];
+    if (e < nm * G)
+        for (int w = s; w < n_wg; w += 16) acc += part[((int64_t)w * n_groups + group) * nm * G + e];
     red[s][c] = acc;
     __syncthreads();
-    if (s == 0 && v < nm) {
+    const int v = e / G, r = group * G + (e - v * G);
+    if (s == 0 && e < nm * G && r < R) {
         float t = 0.0f;
         for (int q = 0; q < 16; ++q) t += red[q][c];
-        gref<float> dst = v < n ? ga.at(0, v) : gb.at(0, v - n);
+        gref<float> dst = v < n ? ga.at(r, v) : gb.at(r, v - n);
         if (accumulate) dst += t; else dst = t;
     }
 }
@@ -409,6 +439,32 @@ fsmt_status fill_f32(float *p, int64_t n, float value, hipStream_t st) {
     return launch_status("fill");
 }
 
+// Dynamic LDS the gradient-in-LDS kernels may take: the device's per-block maximum, opted
+// into once for every instantiation (64 KB if the device reports no more).
+static size_t lds_grad_budget() {
+    static size_t budget = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, v = 0;
+        size_t b = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && (size_t)v > b)
+            b = (size_t)v;
+        const void *fns[] = {(const void *)cop_lds_grad_kernel<0, 1>, (const void *)cop_lds_grad_kernel<1, 1>,
+                             (const void *)cop_lds_grad_kernel<2, 1>, (const void *)cop_lds_grad_kernel<0, 2>,
+                             (const void *)cop_lds_grad_kernel<1, 2>, (const void *)cop_lds_grad_kernel<2, 2>,
+                             (const void *)cop_lds_grad_kernel<0, 4>, (const void *)cop_lds_grad_kernel<1, 4>,
+                             (const void *)cop_lds_grad_kernel<2, 4>};
+        for (const void *f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) != hipSuccess) {
+                (void)hipGetLastError();
+                b = 65536;
+            }
+        budget = b;
+    });
+    return budget;
+}
+
 static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double kappa, fsmt_view w, float *obj,
                               fsmt_view unsat, fsmt_view ga, fsmt_view gb, bool grad, int32_t flags, hipStream_t st) {
     const int R = a.rows;
@@ -450,22 +506,30 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     // the per-XCD L2, one memory transaction per cache line touched, so when the caller's
     // gradient rows are not restart-contiguous the sums go to a restart-contiguous stage
     // ([n + m][R], one line per variable and 16 restarts) and are moved into the caller's
-    // views afterwards. With one restart over small diagrams with a register message store,
-    // the gradient is summed per workgroup in LDS (cop_lds_grad_kernel) and the workgroups'
-    // rows are added afterwards, one row per CU. Both are taken only for instances of at
+    // views afterwards. With up to 16 restarts over small diagrams with a register message
+    // store, the gradient is summed per workgroup in LDS for groups of up to 4 restarts
+    // (cop_lds_grad_kernel) and the workgroups' rows are added afterwards, one row per CU;
+    // where it applies it replaces the stage. Both are taken only for instances of at
     // least 8 tasks (64-position groups) per CU: on smaller ones the atomics cost little and
     // the extra allocation and launches would dominate the call.
     const int n = h->n_bool, m = h->n_real;
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
     const bool large = (int64_t)h->n_pos / 64 >= (int64_t)8 * n_cu;
-    const bool stage = grad && large && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
-                       !(ga.stride_r == 1 && gb.stride_r == 1);
+    bool stage = grad && large && R >= 4 && R <= 64 && (int64_t)(n + m) * R > 0 &&
+                 !(ga.stride_r == 1 && gb.stride_r == 1);
     const int cf = closed_level(h);
-    const bool lds_grad = grad && large && R == 1 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons &&
-                          n + m > 0 &&
-                          (int64_t)(n + m) * (int64_t)(2 * sizeof(float)) <= 64 * 1024;   // default LDS limit
-    const int grad_rows = lds_grad ? (int)std::max<int64_t>(1, std::min<int64_t>(n_cu, (h->n_pos / 64 + 15) / 16)) : 0;
+    // restarts per LDS group: the largest of 4, 2, 1 not above R's padding whose gradient and
+    // point copies (8 (n + m) G bytes) fit the workgroup's LDS
+    const size_t lds_cap = lds_grad_budget();
+    int gsz = 4;
+    while (gsz > 1 && (gsz / 2 >= R || (size_t)8 * (n + m) * gsz > lds_cap)) gsz /= 2;
+    const bool lds_grad = grad && large && R <= 16 && msg == kMsgSmall && cf <= 2 && h->n_big < h->n_cons &&
+                          n + m > 0 && (size_t)8 * (n + m) * gsz <= lds_cap;
+    if (lds_grad) stage = false;
+    const int n_groups = lds_grad ? (R + gsz - 1) / gsz : 0;
+    const int grad_wg = lds_grad ? std::max(1, n_cu / n_groups) : 0;   // workgroups per group
+    const int grad_rows = n_groups * grad_wg;
     struct Stage {   // freed stream-ordered after whatever the call enqueued
         float *p = nullptr;
         hipStream_t st = nullptr;
@@ -475,7 +539,7 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     } sg;
     sg.st = st;
     if (lds_grad) {
-        if (hipMallocAsync((void **)&sg.p, sizeof(float) * (size_t)(n + m) * grad_rows, st) != hipSuccess) {
+        if (hipMallocAsync((void **)&sg.p, sizeof(float) * (size_t)(n + m) * gsz * grad_rows, st) != hipSuccess) {
             (void)hipGetLastError();
             sg.p = nullptr;
             return set_error(FSMT_ENOMEM, "gradient rows allocation failed");
@@ -540,16 +604,25 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
     const size_t lds = wave_bytes * wpb;
     const dim3 g(blocks), bl(64 * wpb);
     if (lds_grad) {
-        const size_t glds = 2 * sizeof(float) * (size_t)(n + m);   // gradient, point
-        if (cf == 0)
-            hipLaunchKernelGGL(cop_lds_grad_kernel<0>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
-        else if (cf == 1)
-            hipLaunchKernelGGL(cop_lds_grad_kernel<1>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
-        else
-            hipLaunchKernelGGL(cop_lds_grad_kernel<2>, dim3(grad_rows), dim3(1024), glds, st, A, sbuf);
+        const size_t glds = (size_t)8 * (n + m) * gsz;   // gradient and point, [variable][G] each
+        const dim3 gg(grad_rows), gb1(1024);
+        if (gsz == 1) {
+            if (cf == 0) hipLaunchKernelGGL((cop_lds_grad_kernel<0, 1>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else if (cf == 1) hipLaunchKernelGGL((cop_lds_grad_kernel<1, 1>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else hipLaunchKernelGGL((cop_lds_grad_kernel<2, 1>), gg, gb1, glds, st, A, sbuf, n_groups);
+        } else if (gsz == 2) {
+            if (cf == 0) hipLaunchKernelGGL((cop_lds_grad_kernel<0, 2>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else if (cf == 1) hipLaunchKernelGGL((cop_lds_grad_kernel<1, 2>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else hipLaunchKernelGGL((cop_lds_grad_kernel<2, 2>), gg, gb1, glds, st, A, sbuf, n_groups);
+        } else {
+            if (cf == 0) hipLaunchKernelGGL((cop_lds_grad_kernel<0, 4>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else if (cf == 1) hipLaunchKernelGGL((cop_lds_grad_kernel<1, 4>), gg, gb1, glds, st, A, sbuf, n_groups);
+            else hipLaunchKernelGGL((cop_lds_grad_kernel<2, 4>), gg, gb1, glds, st, A, sbuf, n_groups);
+        }
         if ((rc = launch_status("cop kernel (gradient in LDS)"))) return rc;
-        hipLaunchKernelGGL(sum_rows_kernel, dim3((n + m + 63) / 64), dim3(1024), 0, st, (const float *)sbuf, grad_rows, n,
-                           m, View::of(ga), View::of(gb), flags & FSMT_ACCUMULATE);
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(((n + m) * gsz + 63) / 64, n_groups), dim3(1024), 0, st,
+                           (const float *)sbuf, n_groups, grad_wg, gsz, R, n, m, View::of(ga), View::of(gb),
+                           flags & FSMT_ACCUMULATE);
         if ((rc = launch_status("gradient rows"))) return rc;
     } else if (h->n_big < h->n_cons) {
         if (grad)
