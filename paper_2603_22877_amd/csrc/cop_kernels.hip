@@ -122,8 +122,11 @@ __global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *pa
     const int wib = wave_id();
     const int wpb = blockDim.x >> 6;
     const int n = A.T.n_bool, nm = A.T.n_bool + A.T.n_real;
-    const int group = (int)(blockIdx.x % n_groups), r0 = group * G;
-    const int64_t wg = blockIdx.x / n_groups, n_wg = gridDim.x / n_groups;
+    // workgroup w of every group takes the same tasks; blocks are dealt to the XCDs round
+    // robin, so with group-major numbering and a multiple of 8 workgroups per group those
+    // workgroups share an XCD and its L2 serves the tables to all groups
+    const int64_t n_wg = gridDim.x / n_groups, wg = blockIdx.x % n_wg;
+    const int group = (int)(blockIdx.x / n_wg), r0 = group * G;
     float *const sy = lds + nm * G;   // a then b, [variable][G]
     for (int e = threadIdx.x; e < nm * G; e += blockDim.x) {
         const int v = e / G, r = r0 + (e - v * G);
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *pa
 }
 
 // The groups' gradients from the workgroups' partial rows (row b belongs to group
-// b mod n_groups): 64 elements per block, the rows split over 16 stripes and the stripes'
+// b / n_wg): 64 elements per block, the rows split over 16 stripes and the stripes'
 // sums added in LDS; stored into (or added to) the caller's views.
 __global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int n_groups, int n_wg, int G, int R, int n,
                                                         int m, View ga, View gb, int accumulate) {
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int n
     const int e = blockIdx.x * 64 + c;
     float acc = 0.0f;
     if (e < nm * G)
-        for (int w = s; w < n_wg; w += 16) acc += part[((int64_t)w * n_groups + group) * nm * G + e];
+        for (int w = s; w < n_wg; w += 16) acc += part[((int64_t)group * n_wg + w) * nm * G + e];
     red[s][c] = acc;
     __syncthreads();
     const int v = e / G, r = group * G + (e - v * G);
@@ -528,7 +531,8 @@ static fsmt_status cop_launch(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, doub
                           n + m > 0 && (size_t)8 * (n + m) * gsz <= lds_cap;
     if (lds_grad) stage = false;
     const int n_groups = lds_grad ? (R + gsz - 1) / gsz : 0;
-    const int grad_wg = lds_grad ? std::max(1, n_cu / n_groups) : 0;   // workgroups per group
+    // workgroups per group: a multiple of 8 (the XCDs) where the CUs allow
+    const int grad_wg = lds_grad ? (n_cu / n_groups >= 8 ? n_cu / n_groups / 8 * 8 : std::max(1, n_cu / n_groups)) : 0;
     const int grad_rows = n_groups * grad_wg;
     struct Stage {   // freed stream-ordered after whatever the call enqueued
         float *p = nullptr;
