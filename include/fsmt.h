@@ -205,7 +205,12 @@ fsmt_status cop_forward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double kap
  * chain rule dp/da = -1/2 and dp/db_j = -kappa q_j exp(-u^2) / (sqrt(2 pi) |q|)
  * (Supplementary Note 6). grad_a [R][n_bool], grad_b [R][n_real] receive grad U; obj
  * (optional, NULL to skip) receives U. Without FSMT_ACCUMULATE the outputs are zeroed
- * first. Gradient sums use float atomics, so the last bits vary between runs.
+ * first. Gradient sums use float atomics, so the last bits vary between runs. On instances
+ * of at least 8 x 64 constraints per compute unit the call takes stream-ordered work memory
+ * (hipMallocAsync / hipFreeAsync on `stream`: per-workgroup gradient rows for up to 16
+ * restarts on diagrams of the register message store, else a restart-contiguous gradient
+ * stage for 4-64 restarts in gradients that are not restart-contiguous already);
+ * FSMT_ENOMEM if that fails.
  */
 fsmt_status cop_backward(const fsmt_xbdd *h, fsmt_view a, fsmt_view b, double kappa,
                          fsmt_view w, float *obj, fsmt_view grad_a, fsmt_view grad_b,
