@@ -171,8 +171,8 @@ def main():
         print(json.dumps(other_configs(args, fsmt, S)))
         return
     log("compiling placement 1200 rectangles")
-    p = W.make_config(5)
-    R = W.RESTARTS[5]
+    p = W.make_workload("placement_1200")
+    R = W.RESTARTS["placement_1200"]
     ell = p.meta["mean_side"]
     t0 = time.perf_counter()
     h = fsmt.xbdd_compile(p)
@@ -268,10 +268,10 @@ def main():
         log("time-to-SAT on the index encoding done")
     if not args.no_other:
         out["other_workloads"] = {
-            "scheduling 200 x 10, 64 restarts": _fixed_work(fsmt, S, [W.make_config(2)], 64, (2, 0), steps=100),
-            "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0)),
+            "scheduling 200 x 10, 64 restarts": _fixed_work(fsmt, S, [W.make_workload("scheduling_200x10")], 64, (2, 0), steps=100),
+            "uneven batch, 48 instances x 16 restarts": _fixed_work(fsmt, S, W.uneven_batch(), 16, (4, 0)),
             "uneven batch, 48 instances x 16 restarts, autotuned plan":
-                _fixed_work(fsmt, S, W.make_batch_config4(), 16, (4, 0), tuned=True),
+                _fixed_work(fsmt, S, W.uneven_batch(), 16, (4, 0), tuned=True),
         }
         log("other workloads done")
     if not args.no_protocol:
@@ -317,7 +317,7 @@ def percall_placement(fsmt, W, st):
     1 restart (the tables stream from HBM) and 3 at 16 restarts."""
     import torch
     dev = torch.device("cuda", 0)
-    p = W.make_config(5)
+    p = W.make_workload("placement_1200")
     h = fsmt.xbdd_compile(p)
     for R in (1, 16):
         a0, b0 = W.initial_points(p, R, 5, 0)
@@ -337,7 +337,7 @@ def time_to_sat(args, fsmt, S, W, st):
     res = {"batched_s": [], "plain_s": [], "plain_restarts": [], "batched_level": []}
     cap = args.tts_cap
     for seed in range(args.tts_seeds):
-        p = W.make_config(2, seed)
+        p = W.make_workload("scheduling_200x10", seed)
         h = fsmt.xbdd_compile(p)
         kap = S.kappa_schedule(p.meta["mean_duration"], LEVELS)
         cfg = S.SolveConfig(kappas=kap, steps_per_level=STEPS_PER_LEVEL, eta_a=ETA_A, eta_b=ETA_B,
@@ -484,7 +484,7 @@ def paper_protocol(fsmt, W, st, ns=(100, 500, 1000)):
         rows[str(n)] = {"n_cons": p.n_cons, "max_nodes": info["max_nodes"], "ms_per_call_100_points": dt * 10,
                         "us_per_point": dt / 10000 * 1e6, "paper_L40S_ms_per_gradient": PAPER_L40S_MS.get(n)}
     # the same protocol on the benchmark's scheduling instance (200 jobs on 10 machines)
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 100, 2, 7)
     a, b = torch.as_tensor(a0, device=dev), torch.as_tensor(b0, device=dev)
@@ -626,7 +626,7 @@ def placement_tts(fsmt, S, fill: float, seeds: int, cap: float) -> dict:
     from paper_2603_22877_amd import par2 as P2
     res = []
     for seed in range(seeds):
-        p = W.make_config(3, seed) if fill == 0.6 else PL.make_placement(150, W.seed_seq(3, seed), fill=fill)
+        p = W.make_workload("placement_150", seed) if fill == 0.6 else PL.make_placement(150, W.seed_seq(3, seed), fill=fill)
         cfg = _suite_cfg(S, p, **{k: PLACE_HP[k] for k in ("levels", "kmax", "eps", "gamma")})
         r = P2.run_instance(p, cfg, 256, cap, lambda q, R, att, seed=seed: W.initial_points(q, R, 3, seed, 100 + att),
                             name=f"placement150 fill {fill} #{seed}")
@@ -644,7 +644,7 @@ def other_configs(args, fsmt, S):
     """Rates of the fused solver on placement 150, and time-to-SAT there (the generator's 60 %
     area fill and, where the method solves, 50 %)."""
     import workloads as W
-    out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_config(3)], 256, (3, 0))}
+    out = {"placement 150 x 256 restarts": _fixed_work(fsmt, S, [W.make_workload("placement_150")], 256, (3, 0))}
     cap = min(args.tts_cap, 20.0)
     out["time_to_sat placement 150 (60% fill), 256 restarts"] = placement_tts(fsmt, S, 0.6, 10, cap)
     out["time_to_sat placement 150 at 50% fill, 256 restarts"] = placement_tts(fsmt, S, 0.5, 10, cap)

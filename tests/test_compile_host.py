@@ -93,12 +93,12 @@ def test_compiled_diagrams_decide_like_the_formula(seed):
 
 
 def test_diagram_sizes_of_workload_constraints():
-    p1 = W.make_config(1)
+    p1 = W.make_workload("scheduling_10x2")
     h1 = compile_host(p1)
     P = p1.meta["n_pairs"]
     assert fsmt.xbdd_export_diagram(h1, 0)["n_nodes"] == 2       # 2-literal clause
     assert fsmt.xbdd_export_diagram(h1, 2 * P)["n_nodes"] == 1   # unit atom
-    p3 = W.make_config(3)
+    p3 = W.make_workload("placement_150")
     h3 = compile_host(p3)
     sizes = {}
     for c in range(0, p3.meta["n_pairs"], 97):
@@ -118,8 +118,8 @@ def test_guarded_disjunctions_are_recognized_from_the_diagram():
     ITEs over clauses, short ANDs and XORs; not-all-equal over three variables is not one
     (its chains give the last slot both polarities). FSMT_MSG_GENERIC turns the family off."""
     from workloads.format import KIND_AND, KIND_NAE, X_ITE, X_OR
-    for cfg in (1, 2, 3):
-        p = W.make_config(cfg)
+    for name in ("scheduling_10x2", "scheduling_200x10", "placement_150"):
+        p = W.make_workload(name)
         assert fsmt.xbdd_info(compile_host(p))["n_gd"] == p.n_cons
         assert fsmt.xbdd_info(compile_host(p, messages=2))["n_gd"] == 0
     b = Builder(3, 1, real_lo=np.zeros(1), real_hi=np.ones(1))
@@ -182,7 +182,7 @@ def test_variable_order_invariance_of_cop():
 
 
 def test_shapes_are_shared_by_placement_pairs_and_compile_is_fast():
-    p5 = W.make_config(5)
+    p5 = W.make_workload("placement_1200")
     t = time.time()
     h = compile_host(p5)
     dt = time.time() - t
@@ -232,7 +232,7 @@ def test_errors_are_reported_not_thrown():
     b = Builder(1, 1, [-1], [1])
     b.add(KIND_CLAUSE, [lit(b.atom([0], [1.0], OP_EQ, 0.0))])
     assert _err(b.build()) == _abi.FSMT_EUNSUPPORTED
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     p.con_lit = p.con_lit.copy()
     p.con_lit[0] = 2 * (p.n_bool + p.n_atoms + 5)
     assert _err(p) == _abi.FSMT_EINVAL
@@ -245,12 +245,12 @@ def test_errors_are_reported_not_thrown():
     b = Builder(30, 1, [-1], [1])
     b.add(KIND_CARD_LE, [lit(i) for i in range(30)], 15)
     assert _err(b.build(), max_nodes=50) == _abi.FSMT_ELIMIT
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     p.real_lo = p.real_lo.copy()
     p.real_lo[0] = p.real_hi[0] + 1
     assert _err(p) == _abi.FSMT_EINVAL
-    assert _err(W.make_config(1), messages=3) == _abi.FSMT_EINVAL
-    assert _err(W.make_config(1), projection=5) == _abi.FSMT_EINVAL
+    assert _err(W.make_workload("scheduling_10x2"), messages=3) == _abi.FSMT_EINVAL
+    assert _err(W.make_workload("scheduling_10x2"), projection=5) == _abi.FSMT_EINVAL
 
 
 def test_runtime_calls_reject_host_only_handles():
@@ -269,8 +269,8 @@ def test_big_diagrams_are_classified_and_levelized():
     h = compile_host(p)
     info = fsmt.xbdd_info(h)
     assert info["n_big"] == p.n_cons and info["max_nodes"] > 100
-    for cfg in (1, 2, 3):
-        assert fsmt.xbdd_info(compile_host(W.make_config(cfg)))["n_big"] == 0
+    for name in ("scheduling_10x2", "scheduling_200x10", "placement_150"):
+        assert fsmt.xbdd_info(compile_host(W.make_workload(name)))["n_big"] == 0
     for c in range(p.n_cons):
         d = fsmt.xbdd_export_diagram(h, c)
         nodes, N = d["nodes"], d["n_nodes"]

@@ -28,17 +28,17 @@ def _np(t, dtype=None):
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
-@pytest.mark.parametrize("cfg_id,R,eps", [(1, 6, 0.2), (2, 8, 1.5)])
-def test_anneal_levels_replay_oracle(cfg_id, R, eps, schedule):
+@pytest.mark.parametrize("name,R,eps", [("scheduling_10x2", 6, 0.2), ("scheduling_200x10", 8, 1.5)])
+def test_anneal_levels_replay_oracle(name, R, eps, schedule):
     """Alg. "CLS with Annealing" level by level: each call runs one level (resuming at
     level_done) with ERWA on and eps > 0, and the oracle's ``anneal_level`` runs the same
     level from the GPU's level-start state (per-call parity). Per restart: the number of
     projected-gradient steps (each restart stops on its own gradient map), the point after
     them, the exact check at the GPU's point (bit-exact), the ERWA weights and history, the
     level counter and SAT restarts that stop."""
-    p = W.make_config(cfg_id)
+    p = W.make_workload(name)
     h = fsmt.xbdd_compile(p)
-    a0, b0 = W.initial_points(p, R, cfg_id, 77)
+    a0, b0 = W.initial_points(p, R, W.STREAM[name], 77)
     st = S.BatchState(h, a0, b0)
     kap = S.kappa_schedule(p.meta["mean_duration"], 40)[:3]
     eta_a, eta_b, K = 0.5, 5.0, 5
@@ -46,7 +46,7 @@ def test_anneal_levels_replay_oracle(cfg_id, R, eps, schedule):
                         schedule=schedule, cluster=1)
     early, marginal, worst = 0, 0, 0.0
     for t in range(3):
-        print(f"anneal replay config {cfg_id} R={R} schedule {schedule} level {t + 1}", flush=True)
+        print(f"anneal replay {name} R={R} schedule {schedule} level {t + 1}", flush=True)
         a_s, b_s = _np(st.a).copy(), _np(st.b).copy()
         w_s, h_s = _np(st.w, np.float64), _np(st.hist, np.float64)
         ver_s, steps_s = _np(st.verdict), _np(st.steps_done)
@@ -101,7 +101,7 @@ def test_cluster_abort_reports_and_resumes():
     restarts report verdict -2, fsmt_solve_status raises FSMT_EABORTED, every restart's state
     is that of its last completed level, and a normal call resumes from there to the same
     end as an uninterrupted run."""
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R, levels = 16, 3
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 72, 0)
@@ -146,7 +146,7 @@ def test_stream_ordered_calls_without_host_sync():
     the results equal those of the same calls with a synchronization after each."""
     if not hasattr(torch.cuda, "_sleep"):
         pytest.skip("torch.cuda._sleep is not available")
-    probs = [W.make_config(1), W.make_random_hybrid(100)]
+    probs = [W.make_workload("scheduling_10x2"), W.make_random_hybrid(100)]
     Rs = [4, 3]
     hs = [fsmt.xbdd_compile(q) for q in probs]
     init = [W.initial_points(q, R, 73, i) for i, (q, R) in enumerate(zip(probs, Rs))]

@@ -22,26 +22,26 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _batch(cfg_id):
-    if cfg_id == 4:
-        probs = W.make_batch_config4()
+def _batch(name):
+    if name == "uneven_batch":
+        probs = W.uneven_batch()
     else:
-        probs = [W.make_config(cfg_id)]
-    R = W.RESTARTS[cfg_id]
+        probs = [W.make_workload(name)]
+    R = W.RESTARTS[name]
     hs = [fsmt.xbdd_compile(p) for p in probs]
-    init = [W.initial_points(p, R, 70, cfg_id, i) for i, p in enumerate(probs)]
+    init = [W.initial_points(p, R, 70, W.STREAM[name], i) for i, p in enumerate(probs)]
     ell = min(p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)) for p in probs)
     cfg = S.SolveConfig(kappas=S.kappa_schedule(ell, 4), steps_per_level=100, eta_a=0.5, eta_b=5.0, eps=0.0,
                         stop_on_sat=0)
     return probs, hs, init, cfg
 
 
-@pytest.mark.parametrize("cfg_id", [2, 3, 4])
-def test_tuned_plan_not_slower_than_model(cfg_id, tmp_path, monkeypatch):
+@pytest.mark.parametrize("name", ["scheduling_200x10", "placement_150", "uneven_batch"])
+def test_tuned_plan_not_slower_than_model(name, tmp_path, monkeypatch):
     monkeypatch.setenv(AT.CACHE_ENV, str(tmp_path / "tune.json"))
-    probs, hs, init, cfg = _batch(cfg_id)
+    probs, hs, init, cfg = _batch(name)
     plan = AT.tune(hs, init, cfg, log=lambda m: print(m, flush=True))
-    print(f"config {cfg_id}: chosen {plan.label} {plan.inst_schedule[:8]} cluster {plan.cluster}, "
+    print(f"{name}: chosen {plan.label} {plan.inst_schedule[:8]} cluster {plan.cluster}, "
           f"candidates {plan.candidates}", flush=True)
     assert not plan.cached and os.path.exists(tmp_path / "tune.json")
     # the fastest candidate, or the model's plan when no candidate beats it by the margin
@@ -54,7 +54,7 @@ def test_tuned_plan_not_slower_than_model(cfg_id, tmp_path, monkeypatch):
         for _ in range(3):
             model = min(model, AT.measure(hs, init, cfg, steps=16, reps=3)[1])
             tuned = min(tuned, AT.measure(hs, init, plan.apply(cfg), steps=16, reps=3)[1])
-        print(f"config {cfg_id}: model {model / 1e3:.3f} ms per level, tuned {tuned / 1e3:.3f}", flush=True)
+        print(f"{name}: model {model / 1e3:.3f} ms per level, tuned {tuned / 1e3:.3f}", flush=True)
         assert tuned <= 1.05 * model
     again = AT.tune(hs, init, cfg)
     assert again.cached and again.inst_schedule == plan.inst_schedule and again.cluster == plan.cluster
@@ -66,7 +66,7 @@ def test_per_instance_schedule_gives_the_same_steps():
     """Two instances, one forced persistent and one forced grid in one call, against the
     same instances each alone under that schedule: one fused step (fixed work) must agree
     (integer outputs exactly, the point within float rounding)."""
-    p1, p2 = W.make_config(1), W.make_config(3)
+    p1, p2 = W.make_workload("scheduling_10x2"), W.make_workload("placement_150")
     h1, h2 = fsmt.xbdd_compile(p1), fsmt.xbdd_compile(p2)
     i1, i2 = W.initial_points(p1, 4, 71, 1), W.initial_points(p2, 4, 71, 3)
     cfg = S.SolveConfig(kappas=[0.2], steps_per_level=1, eta_a=0.5, eta_b=5.0, eps=0.0, stop_on_sat=0)

@@ -127,14 +127,14 @@ def test_mixed_small_and_big_diagrams(seed, R):
         _compare(p, a, b, kap, layout="cols")
 
 
-@pytest.mark.parametrize("cfg,R", [(2, 1), (3, 1), (3, 16)])
-def test_backward_accumulates_into_the_outputs(cfg, R):
+@pytest.mark.parametrize("name,R", [("scheduling_200x10", 1), ("placement_150", 1), ("placement_150", 16)])
+def test_backward_accumulates_into_the_outputs(name, R):
     """FSMT_ACCUMULATE adds into obj and the gradients instead of overwriting them: a
     second call doubles them (one restart sums the gradient per workgroup in LDS and adds
     the rows; 16 restarts go through the restart-contiguous stage)."""
-    p = W.make_config(cfg)
-    print(f"accumulate config {cfg} R={R}", flush=True)
-    a, b = W.initial_points(p, R, cfg, 3)
+    p = W.make_workload(name)
+    print(f"accumulate {name} R={R}", flush=True)
+    a, b = W.initial_points(p, R, W.STREAM[name], 3)
     h = fsmt.xbdd_compile(p)
     ta, tb, wt = T(a), T(b), T(np.ones(p.n_cons))
     ga = torch.full((R, p.n_bool), 123.0, device=dev())
@@ -161,25 +161,27 @@ def test_fig2_toy_values():
         _compare(p, a, b, kap)
 
 
-@pytest.mark.parametrize("cfg,R,kap", [(1, 1, 0.3), (1, 1, INF), (2, 64, 0.05), (2, 64, 0.5),
-                                       (3, 16, 0.1), (3, 16, 1.0), (2, 1, 0.3), (3, 1, 0.5)])
+@pytest.mark.parametrize("name,R,kap", [("scheduling_10x2", 1, 0.3), ("scheduling_10x2", 1, INF),
+                                        ("scheduling_200x10", 64, 0.05), ("scheduling_200x10", 64, 0.5),
+                                        ("placement_150", 16, 0.1), ("placement_150", 16, 1.0),
+                                        ("scheduling_200x10", 1, 0.3), ("placement_150", 1, 0.5)])
 @pytest.mark.parametrize("messages", ["auto", "lds", "generic"])
-def test_workload_configs(cfg, R, kap, messages):
-    print(f"config {cfg} R={R} kappa={kap} messages={messages}", flush=True)
-    p = W.make_config(cfg)
-    a, b = W.initial_points(p, R, cfg, 0)
+def test_standard_workloads(name, R, kap, messages):
+    print(f"{name} R={R} kappa={kap} messages={messages}", flush=True)
+    p = W.make_workload(name)
+    a, b = W.initial_points(p, R, W.STREAM[name], 0)
     _compare(p, a, b, kap, messages=messages)
 
 
-@pytest.mark.parametrize("cfg,R", [(1, 5), (2, 64), (3, 16)])
-def test_variable_major_layout_matches(cfg, R):
-    p = W.make_config(cfg)
-    a, b = W.initial_points(p, R, cfg, 1)
+@pytest.mark.parametrize("name,R", [("scheduling_10x2", 5), ("scheduling_200x10", 64), ("placement_150", 16)])
+def test_variable_major_layout_matches(name, R):
+    p = W.make_workload(name)
+    a, b = W.initial_points(p, R, W.STREAM[name], 1)
     _compare(p, a, b, 0.3, layout="cols")
 
 
 def test_hard_objective_counts_violations_at_vertices():
-    p = W.make_config(3)
+    p = W.make_workload("placement_150")
     R = 8
     a, b = W.initial_points(p, R, 3, 2)
     a = np.where(a < 0, -1.0, 1.0).astype(np.float32)
@@ -193,7 +195,7 @@ def test_hard_objective_counts_violations_at_vertices():
 def test_pgd_step_matches_oracle(projection):
     """Box projection: the clamp, exact up to FP32 rounding. Box + unit atoms (Prop. qp):
     Dykstra in FP32 against the FP64 oracle run to convergence."""
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R = 8
     a, b = W.initial_points(p, R, 2, 3)
     rng = np.random.default_rng(3)
@@ -224,7 +226,7 @@ def test_pgd_step_matches_oracle(projection):
 def test_pgd_step_dykstra_matches_oracle():
     """Half-spaces that share variables (chained job dependencies of the paper's scheduling
     encoding): Dykstra's sweeps over colour classes in FP32 against the FP64 oracle run to
-    convergence (the test above takes the closed form: config 2's precedences are disjoint)."""
+    convergence (the test above takes the closed form: the precedences of scheduling 200 x 10 are disjoint)."""
     from workloads.paper_suite import make_paper_scheduling
     p = make_paper_scheduling(16, 3, W.seed_seq(8, 16, 3, 0), dep_prob=0.6)
     h = fsmt.xbdd_compile(p)
@@ -272,10 +274,10 @@ def _assert_check_equal(g, o):
     np.testing.assert_array_equal(g["x"], o["x"])
 
 
-@pytest.mark.parametrize("cfg,R", [(1, 4), (2, 16), (3, 16)])
-def test_round_and_check_bit_exact(cfg, R):
-    p = W.make_config(cfg)
-    a, b = W.initial_points(p, R, cfg, 4)
+@pytest.mark.parametrize("name,R", [("scheduling_10x2", 4), ("scheduling_200x10", 16), ("placement_150", 16)])
+def test_round_and_check_bit_exact(name, R):
+    p = W.make_workload(name)
+    a, b = W.initial_points(p, R, W.STREAM[name], 4)
     a[0] = p.cert_x
     b[0] = p.cert_y
     a[1] = p.cert_x
@@ -298,9 +300,9 @@ def test_check_boundary_atoms_and_random_formulas():
         _assert_check_equal(_check_gpu(p, h, a, b), oracle.check(p, a, b))
 
 
-def test_adjoint_central_differences_config2():
+def test_adjoint_central_differences_scheduling200x10():
     """FP32 central differences of the GPU objective on 32 random coordinates."""
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R = 4
     a, b = W.initial_points(p, R, 2, 5)
     kap = 0.2
@@ -339,12 +341,12 @@ def test_adjoint_central_differences_config2():
         assert abs(fd - ref) <= tol, (fd, ref, tol)
 
 
-def test_config5_sampled_parity():
+def test_placement1200_sampled_parity():
     """Paper-scale placement (721,800 constraints, 16 restarts): sampled constraints and
     sampled gradient coordinates against the oracle, in the launch configuration of the
     benchmark."""
-    print("config 5 sampled parity", flush=True)
-    p = W.make_config(5)
+    print("placement 1200 sampled parity", flush=True)
+    p = W.make_workload("placement_1200")
     R = 16
     a, b = W.initial_points(p, R, 5, 0)
     kap = 0.1
@@ -379,7 +381,7 @@ def test_config5_sampled_parity():
 
 
 def test_argument_errors_launch_nothing():
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     h = fsmt.xbdd_compile(p)
     a, b = W.initial_points(p, 2, 1, 0)
     ta, tb = T(a), T(b)
@@ -396,12 +398,12 @@ def test_argument_errors_launch_nothing():
     assert float(obj[0]) == 7.0
 
 
-def test_config4_per_instance_oracle_error():
+def test_uneven_batch_per_instance_oracle_error():
     """Uneven batch (48 instances, 16 restarts each): FP32 objective and false masses of every
     instance against the FP64 oracle (up to 3,000 sampled constraints per instance); the
     table of per-instance errors is printed."""
-    print("config 4 per-instance oracle error", flush=True)
-    probs = W.make_batch_config4()
+    print("uneven batch per-instance oracle error", flush=True)
+    probs = W.uneven_batch()
     R = 16
     rng = np.random.default_rng(4)
     worst = 0.0
@@ -429,13 +431,13 @@ def test_config4_per_instance_oracle_error():
     assert worst <= 1e-5
 
 
-def test_config5_autograd_and_full_check():
+def test_placement1200_autograd_and_full_check():
     """Paper-scale placement through torch.autograd.Function (16 restarts): the gradient equals
     the reverse sweep's, a few projected steps lower U, and the exact check of the final
     rounded assignment equals the oracle's over all 721,800 constraints."""
-    print("config 5 autograd + full check", flush=True)
+    print("placement 1200 autograd + full check", flush=True)
     from paper_2603_22877_amd import solver as S
-    p = W.make_config(5)
+    p = W.make_workload("placement_1200")
     R = 16
     a0, b0 = W.initial_points(p, R, 5, 1)
     h = fsmt.xbdd_compile(p)

@@ -61,10 +61,10 @@ def _pick(p, rng, nb, nr):
     return np.sort(bools), np.sort(reals)
 
 
-def test_config4_sampled_gradients():
+def test_uneven_batch_sampled_gradients():
     """Uneven batch: cop_backward of every instance (16 restarts, row-major), sampled Boolean
     and real coordinates of each against the oracle."""
-    probs = W.make_batch_config4()
+    probs = W.uneven_batch()
     rng = np.random.default_rng(41)
     R = 16
     for i, p in enumerate(probs):
@@ -78,7 +78,7 @@ def test_config4_sampled_gradients():
         fsmt.cop_backward(h, T(a), T(b), kap, T(np.ones(p.n_cons)), obj, ga, gb)
         torch.cuda.synchronize()
         bools, reals = _pick(p, rng, 3, 3)
-        print(f"config 4 instance {i} {p.meta['family']} C={p.n_cons}: booleans {bools.tolist()} "
+        print(f"uneven batch instance {i} {p.meta['family']} C={p.n_cons}: booleans {bools.tolist()} "
               f"reals {reals.tolist()}", flush=True)
         assert_sampled_gradient(op, p, a, b, kap, ga.cpu().numpy(), gb.cpu().numpy(), bools, reals)
         h.free()
@@ -88,7 +88,7 @@ def test_one_restart_gradient_both_paths():
     """cop_backward at one restart on the uneven batch's instances: those whose n + m fits
     the per-workgroup LDS gradient take that path, the larger ones the device-atomic path;
     sampled coordinates of both against the oracle, and the objective."""
-    probs = W.make_batch_config4()
+    probs = W.uneven_batch()
     picks = [i for i, p in enumerate(probs) if p.n_bool + p.n_real <= 8192][:3]
     picks += [i for i, p in enumerate(probs) if p.n_bool + p.n_real > 8192][:2]
     rng = np.random.default_rng(43)
@@ -111,12 +111,12 @@ def test_one_restart_gradient_both_paths():
         h.free()
 
 
-def test_config4_fused_step_sampled_instances():
+def test_uneven_batch_fused_step_sampled_instances():
     """One fused step of the whole uneven batch (persistent and grid schedules in one call):
     on the smaller instances of each family, the step against the oracle's projected step
     from its FP64 gradient, the objective at the start point, and the exact check at the
     GPU's post-step point."""
-    probs = W.make_batch_config4()
+    probs = W.uneven_batch()
     R = 16
     hs = [fsmt.xbdd_compile(p) for p in probs]
     init = [W.initial_points(p, R, 44, i) for i, p in enumerate(probs)]
@@ -135,7 +135,7 @@ def test_config4_fused_step_sampled_instances():
         picked += ids[:2]
     for i in picked:
         p, (a0, b0), st = probs[i], init[i], states[i]
-        print(f"config 4 fused step: instance {i} {p.meta['family']} C={p.n_cons}", flush=True)
+        print(f"uneven batch fused step: instance {i} {p.meta['family']} C={p.n_cons}", flush=True)
         o = oracle.objective(p, a0, b0, kap, per_constraint=False)
         ref = oracle.pgd(p, a0, b0, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32), eta_a, eta_b)
         a1, b1 = st.a.cpu().numpy(), st.b.cpu().numpy()
@@ -159,7 +159,7 @@ def test_placement1200_per_call_sampled(R):
     row per CU, at 16 the restart-contiguous stage. Sampled rectangles (rotation bit and
     both coordinates) against the oracle's partial derivatives, and a second call with
     FSMT_ACCUMULATE doubling them."""
-    p = W.make_config(5)
+    p = W.make_workload("placement_1200")
     op = oracle.OracleProblem(p)
     h = fsmt.xbdd_compile(p)
     a, b = W.initial_points(p, R, 5, 11)
@@ -183,12 +183,12 @@ def test_placement1200_per_call_sampled(R):
     h.free()
 
 
-def test_config5_fused_step_sampled():
+def test_placement1200_fused_step_sampled():
     """Paper-scale placement, 16 restarts, one fused step in the benchmark's launch
     configuration: the step at sampled rectangles (rotation bit and both coordinates)
     against the projected step of the oracle's partial derivatives, and the exact check of
     the post-step point over all 721,800 constraints."""
-    p = W.make_config(5)
+    p = W.make_workload("placement_1200")
     op = oracle.OracleProblem(p)
     R = 16
     h = fsmt.xbdd_compile(p)

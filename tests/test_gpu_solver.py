@@ -57,12 +57,13 @@ def _assert_step(p, a0, b0, st, kap, eta_a, eta_b):
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
-@pytest.mark.parametrize("cfg,R,kap,eta_b", [(1, 4, 0.05, 5.0), (2, 8, 0.1, 5.0), (3, 4, 0.2, 8.0)])
+@pytest.mark.parametrize("name,R,kap,eta_b", [("scheduling_10x2", 4, 0.05, 5.0), ("scheduling_200x10", 8, 0.1, 5.0),
+                                              ("placement_150", 4, 0.2, 8.0)])
 @pytest.mark.parametrize("messages", [0, 2])   # closed forms / generic node-by-node passes
-def test_fused_step_matches_oracle(cfg, R, kap, eta_b, schedule, messages):
-    print(f"fused step config {cfg} R={R} schedule {schedule} messages {messages}", flush=True)
-    p = W.make_config(cfg)
-    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, cfg, schedule, messages)
+def test_fused_step_matches_oracle(name, R, kap, eta_b, schedule, messages):
+    print(f"fused step {name} R={R} schedule {schedule} messages {messages}", flush=True)
+    p = W.make_workload(name)
+    h, a0, b0, st = _one_step(p, R, kap, 0.5, eta_b, W.STREAM[name], schedule, messages)
     _assert_step(p, a0, b0, st, kap, 0.5, eta_b)
 
 
@@ -114,7 +115,7 @@ def test_fused_step_paper_suite(fam, A, B, schedule):
 
 
 def test_multi_instance_batch_equals_single():
-    probs = [W.make_config(1), W.make_random_formula(3100, n_cons=60), W.make_fig2_toy(), W.make_config(2)]
+    probs = [W.make_workload("scheduling_10x2"), W.make_random_formula(3100, n_cons=60), W.make_fig2_toy(), W.make_workload("scheduling_200x10")]
     Rs = [3, 5, 2, 4]
     hs = [fsmt.xbdd_compile(p) for p in probs]
     init = [W.initial_points(p, R, 60, i) for i, (p, R) in enumerate(zip(probs, Rs))]
@@ -135,7 +136,7 @@ def test_multi_instance_batch_equals_single():
 def test_levels_replay_erwa_and_check():
     """Level by level (one call per level, resuming): the check bits equal the oracle's at the
     GPU point, and the weights equal the oracle's ERWA update of the previous weights."""
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R = 8
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 2, 3)
@@ -158,11 +159,11 @@ def test_levels_replay_erwa_and_check():
         assert np.all(st.steps_done.cpu().numpy() == 5 * t)
 
 
-@pytest.mark.parametrize("cfg,R", [(1, 16), (2, 64)])
-def test_batched_solver_reaches_sat(cfg, R):
-    p = W.make_config(cfg)
+@pytest.mark.parametrize("name,R", [("scheduling_10x2", 16), ("scheduling_200x10", 64)])
+def test_batched_solver_reaches_sat(name, R):
+    p = W.make_workload(name)
     h = fsmt.xbdd_compile(p)
-    a0, b0 = W.initial_points(p, R, cfg, 0)
+    a0, b0 = W.initial_points(p, R, W.STREAM[name], 0)
     st = S.BatchState(h, a0, b0)
     scfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100,
                          eta_a=0.5, eta_b=5.0, eps=1e-2, stop_on_sat=2)
@@ -175,8 +176,8 @@ def test_batched_solver_reaches_sat(cfg, R):
     assert ch["verdict"][0] == 1
 
 
-def test_plain_solver_reaches_sat_config1():
-    p = W.make_config(1)
+def test_plain_solver_reaches_sat_scheduling10x2():
+    p = W.make_workload("scheduling_10x2")
     h = fsmt.xbdd_compile(p)
     plain = S.PlainSolver(h, R=1)
     cfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100,
@@ -194,7 +195,7 @@ def test_plain_solver_reaches_sat_config1():
 
 
 def test_autograd_function_matches_reverse_sweep():
-    p = W.make_config(3)
+    p = W.make_workload("placement_150")
     R = 4
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 3, 7)
@@ -218,7 +219,7 @@ def test_autograd_function_matches_reverse_sweep():
 
 
 def test_solver_rejects_bad_options():
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 2, 1, 0)
     st = S.BatchState(h, a0, b0)
@@ -266,13 +267,13 @@ def _run(h, a, b, cfg):
     return st
 
 
-@pytest.mark.parametrize("cfg_id,R", [(1, 8), (2, 16), (3, 4)])
-def test_grid_and_persistent_schedules_agree(cfg_id, R):
+@pytest.mark.parametrize("name,R", [("scheduling_10x2", 8), ("scheduling_200x10", 16), ("placement_150", 4)])
+def test_grid_and_persistent_schedules_agree(name, R):
     """Both schedules run the same algorithm: over 3 levels x 4 steps (no early exit) the
     states agree to FP32 accumulation-order noise and the bookkeeping is identical."""
-    p = W.make_config(cfg_id)
+    p = W.make_workload(name)
     h = fsmt.xbdd_compile(p)
-    a0, b0 = W.initial_points(p, R, 70, cfg_id)
+    a0, b0 = W.initial_points(p, R, 70, W.STREAM[name])
     kap = S.kappa_schedule(p.meta.get("mean_duration", p.meta.get("mean_side", 1.0)), 3)
     res = []
     for sched in (1, 2):
@@ -291,7 +292,7 @@ def test_grid_and_persistent_schedules_agree(cfg_id, R):
 def test_levels_end_early_at_eps(schedule):
     """With kappa = 0 the b-gradient vanishes and the Booleans saturate at the box, so the
     gradient map falls below eps and every level ends before its step cap."""
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 8, 1, 12)
     cfg = S.SolveConfig(kappas=[0.0, 0.0], steps_per_level=100, eta_a=0.5, eta_b=5.0, eps=1e-2, stop_on_sat=0,
@@ -302,7 +303,7 @@ def test_levels_end_early_at_eps(schedule):
 
 
 def test_grid_schedule_reaches_sat_and_stops():
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 16, 2, 11)
     cfg = S.SolveConfig(kappas=S.kappa_schedule(p.meta["mean_duration"], 40), steps_per_level=100, eta_a=0.5,
@@ -317,11 +318,11 @@ def test_grid_schedule_reaches_sat_and_stops():
 
 
 def test_uneven_batch_mixes_schedules():
-    """Config 4 (48 instances, 16 restarts each): large scheduling instances go to the grid
+    """The uneven batch (48 instances, 16 restarts each): large scheduling instances go to the grid
     schedule, small ones to the persistent one, in one call; per-instance bookkeeping and
     check bits are verified against the oracle on a sample of instances."""
-    print("config 4 uneven batch", flush=True)
-    probs = W.make_batch_config4()
+    print("uneven batch", flush=True)
+    probs = W.uneven_batch()
     R = 16
     hs = [fsmt.xbdd_compile(p) for p in probs]
     states = [S.BatchState(h, *W.initial_points(p, R, 4, i)) for i, (h, p) in enumerate(zip(hs, probs))]
@@ -343,7 +344,7 @@ def test_uneven_batch_mixes_schedules():
 def test_cluster_split_step_matches_oracle(cluster):
     """Several workgroups per restart (partials summed in rank order): one step still
     matches the oracle, and every rank applies the same update."""
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R = 8
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 50, 2)
@@ -356,7 +357,7 @@ def test_cluster_split_step_matches_oracle(cluster):
 
 
 def test_cluster_split_agrees_with_single_workgroup_over_levels():
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     R = 16
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, R, 71, 0)

@@ -302,10 +302,10 @@ def test_check_boundary_and_nan():
     assert bits[0] == 0b00101 and bits[1] == 0b00101 and bits[2] == 0
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
-def test_generator_certificates_are_sat(cfg):
+@pytest.mark.parametrize("name", ["scheduling_10x2", "scheduling_200x10", "placement_150"])
+def test_generator_certificates_are_sat(name):
     """Thm. Soundness: the certificate satisfies every constraint, and there U = 0 at kappa = inf."""
-    p = W.make_config(cfg)
+    p = W.make_workload(name)
     a = p.cert_x.astype(np.float32)[None]
     b = p.cert_y.astype(np.float32)[None]
     ch = oracle.check(p, a, b)
@@ -328,7 +328,7 @@ def test_hard_objective_at_vertices_counts_violations(seed):
 
 
 def test_planted_violation_in_certificate():
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     a = p.cert_x.astype(np.float32).copy()
     b = p.cert_y.astype(np.float32).copy()
     b[0] = p.real_hi[0]                     # job 0 starts at the horizon: horizon atom fails
@@ -339,7 +339,7 @@ def test_planted_violation_in_certificate():
 
 # ------------------------------------------------------------------ PGD
 def test_pgd_projection_closed_form():
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     rng = np.random.default_rng(0)
     a = rng.uniform(-1, 1, (2, p.n_bool)).astype(np.float32)
     b = rng.uniform(0, p.real_hi[0], (2, p.n_real)).astype(np.float32)
@@ -497,9 +497,9 @@ def test_anneal_replays_fig2_toy_by_hand_two_restarts(stop_on_sat):
 
 def test_anneal_restarts_are_independent():
     """Batched restarts give exactly what each restart gives alone (Alg. "FourierSMT" is a
-    per-point loop): config 1 with 3 restarts, eps large enough that they stop at
+    per-point loop): scheduling 10 x 2 with 3 restarts, eps large enough that they stop at
     different steps."""
-    p = W.make_config(1)
+    p = W.make_workload("scheduling_10x2")
     a0, b0 = W.initial_points(p, 3, 1, 5)
     ell = p.meta["mean_duration"]
     kap = [4.0 * t / (40 * ell) for t in (1, 2, 3)]
@@ -582,11 +582,11 @@ def test_projection_onto_unit_atoms_matches_active_set_qp(seed):
         np.testing.assert_allclose(y, _active_set_projection(y0, G, h), atol=1e-9)
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_projected_points_satisfy_unit_atoms_after_rounding(cfg):
+@pytest.mark.parametrize("name", ["scheduling_10x2", "scheduling_200x10"])
+def test_projected_points_satisfy_unit_atoms_after_rounding(name):
     """The shifted half-spaces keep precedences and horizons true at the float32 point."""
-    p = W.make_config(cfg)
-    a, b = W.initial_points(p, 8, cfg, 9)
+    p = W.make_workload(name)
+    a, b = W.initial_points(p, 8, W.STREAM[name], 9)
     st = oracle.pgd(p, a, b, np.zeros_like(a), np.zeros_like(b), 0.1, 1.0)
     assert st["n_halfspaces"] == 5
     ch = oracle.check(p, a, st["b"].astype(np.float32))

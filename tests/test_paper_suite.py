@@ -263,7 +263,7 @@ def test_halfspace_colour_classes(make):
 def test_separable_halfspaces_flag():
     """The closed-form projection is chosen exactly when no two half-spaces share a
     variable (one colour class) and each has at most 4 distinct variables."""
-    p = W.make_config(2)      # 5 precedences on distinct jobs among 200
+    p = W.make_workload("scheduling_200x10")      # 5 precedences on distinct jobs among 200
     info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
     assert info["n_halfspaces"] == 5 and info["n_hs_colors"] == 1 and info["hs_separable"] == 1
     box = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY, projection=fsmt.FSMT_PROJ_BOX))
@@ -290,8 +290,8 @@ def test_pair_disjunctions_are_recognized():
     assert fsmt.xbdd_info(fsmt.xbdd_compile(p, device=host))["n_pair"] == p.meta["n_pairs"]
     q = place(4, 4)
     assert fsmt.xbdd_info(fsmt.xbdd_compile(q, device=host))["n_pair"] == q.meta["n_pairs"]
-    for cfg in (2, 3):
-        assert fsmt.xbdd_info(fsmt.xbdd_compile(W.make_config(cfg), device=host))["n_pair"] == 0
+    for name in ("scheduling_200x10", "placement_150"):
+        assert fsmt.xbdd_info(fsmt.xbdd_compile(W.make_workload(name), device=host))["n_pair"] == 0
     nd = p.meta["n_deps"]
     lit = p.con_lit.copy()
     lit[p.con_ptr[nd]] |= 1                      # negate the first literal of the first pair

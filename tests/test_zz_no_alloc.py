@@ -57,12 +57,12 @@ def _assert_same(ref, got, n_cons):
 def test_noalloc_matches_allocating_call_twice():
     # first call: scheduling 200 x 10, 8 restarts (clusters of workgroups use the partial
     # gradient buffers of the scratch)
-    p2 = W.make_config(2)
+    p2 = W.make_workload("scheduling_200x10")
     print("noalloc call 1: scheduling 200 x 10, R=8, 2 levels x 5 steps", flush=True)
     h2, ref, got = _run_pair(p2, 8, 2, 5, 0)
     _assert_same(ref, got, p2.n_cons)
     # second call, smaller input: scheduling 10 x 2, 3 restarts, 3 levels
-    p1 = W.make_config(1)
+    p1 = W.make_workload("scheduling_10x2")
     print("noalloc call 2: scheduling 10 x 2, R=3, 3 levels x 20 steps", flush=True)
     h1, ref, got = _run_pair(p1, 3, 3, 20, 1)
     _assert_same(ref, got, p1.n_cons)
@@ -71,7 +71,7 @@ def test_noalloc_matches_allocating_call_twice():
 
 
 def test_noalloc_rejects_what_it_cannot_run():
-    p = W.make_config(2)
+    p = W.make_workload("scheduling_200x10")
     h = fsmt.xbdd_compile(p)
     a0, b0 = W.initial_points(p, 4, 77, 2)
     st = S.BatchState(h, a0, b0)

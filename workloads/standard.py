@@ -1,14 +1,15 @@
-"""The five workload configurations, random formulas for tests, and seeded initial points.
+"""The standard workloads, random formulas for tests, and seeded initial points.
 
-Every generator is seeded through ``numpy.random.SeedSequence([config_id, instance_seed])``;
-initial points of restart r use ``SeedSequence([config_id, instance_seed, 1000 + r])``.
+Each standard workload is drawn from ``numpy.random.SeedSequence([stream, instance_seed])``
+with the workload's fixed stream key (``STREAM``); initial points of restart r use
+``SeedSequence([*keys, 1000 + r])`` with the caller's keys.
 
-1. scheduling, 10 jobs on 2 machines, 1 restart (plain path)
-2. scheduling, 200 jobs on 10 machines, 64 restarts (batched fused path)
-3. placement, 150 rectangles, 256 restarts
-4. uneven batch: 24 scheduling instances (J ~ logU[50, 1500], M ~ U{4..16}) and 24 placement
-   instances (N ~ logU[50, 400]), shuffled, 16 restarts each
-5. placement, 1200 rectangles (~720,000 pair constraints), 16 restarts
+* ``scheduling_10x2``: scheduling, 10 jobs on 2 machines, 1 restart (the plain path)
+* ``scheduling_200x10``: scheduling, 200 jobs on 10 machines, 64 restarts (batched fused path)
+* ``placement_150``: placement, 150 rectangles, 256 restarts
+* ``uneven_batch``: 24 scheduling instances (J ~ logU[50, 1500], M ~ U{4..16}) and 24
+  placement instances (N ~ logU[50, 400]), shuffled, 16 restarts each
+* ``placement_1200``: placement, 1200 rectangles (721,800 constraints), 16 restarts
 """
 from __future__ import annotations
 
@@ -22,32 +23,36 @@ from .format import (KIND_AND, KIND_CARD_GE, KIND_CARD_LE, KIND_CLAUSE, KIND_EXP
 from .placement import make_placement
 from .scheduling import make_scheduling
 
-RESTARTS = {1: 1, 2: 64, 3: 256, 4: 16, 5: 16}
+# seed stream of each standard workload (first key of its SeedSequence) and its restarts
+STREAM = {"scheduling_10x2": 1, "scheduling_200x10": 2, "placement_150": 3, "uneven_batch": 4, "placement_1200": 5}
+RESTARTS = {"scheduling_10x2": 1, "scheduling_200x10": 64, "placement_150": 256, "uneven_batch": 16,
+            "placement_1200": 16}
 
 
 def seed_seq(*keys: int) -> np.random.SeedSequence:
     return np.random.SeedSequence([int(k) for k in keys])
 
 
-def make_config(config_id: int, instance_seed: int = 0) -> Problem:
-    ss = seed_seq(config_id, instance_seed)
-    if config_id == 1:
-        p = make_scheduling(10, 2, ss)
-    elif config_id == 2:
-        p = make_scheduling(200, 10, ss)
-    elif config_id == 3:
-        p = make_placement(150, ss)
-    elif config_id == 5:
-        p = make_placement(1200, ss)
-    else:
-        raise ValueError("config 4 is a batch: use make_batch_config4")
-    p.meta.update(config=config_id, instance_seed=instance_seed)
+_SINGLE = {
+    "scheduling_10x2": lambda ss: make_scheduling(10, 2, ss),
+    "scheduling_200x10": lambda ss: make_scheduling(200, 10, ss),
+    "placement_150": lambda ss: make_placement(150, ss),
+    "placement_1200": lambda ss: make_placement(1200, ss),
+}
+
+
+def make_workload(name: str, instance_seed: int = 0) -> Problem:
+    """Instance ``instance_seed`` of the single-instance standard workload ``name``."""
+    if name not in _SINGLE:
+        raise ValueError(f"{name!r} is not a single-instance workload (the batch is uneven_batch())")
+    p = _SINGLE[name](seed_seq(STREAM[name], instance_seed))
+    p.meta.update(workload=name, instance_seed=instance_seed)
     return p
 
 
-def config4_sizes(instance_seed: int = 0) -> List[Tuple[str, int, int]]:
+def uneven_batch_sizes(instance_seed: int = 0) -> List[Tuple[str, int, int]]:
     """(family, size, machines) for the 48 instances of the uneven batch, shuffled."""
-    rng = np.random.Generator(np.random.PCG64(seed_seq(4, instance_seed)))
+    rng = np.random.Generator(np.random.PCG64(seed_seq(STREAM["uneven_batch"], instance_seed)))
     out = []
     for _ in range(24):
         J = int(round(math.exp(rng.uniform(math.log(50), math.log(1500)))))
@@ -60,12 +65,12 @@ def config4_sizes(instance_seed: int = 0) -> List[Tuple[str, int, int]]:
     return [out[i] for i in order]
 
 
-def make_batch_config4(instance_seed: int = 0, max_instances: int = 48) -> List[Problem]:
+def uneven_batch(instance_seed: int = 0, max_instances: int = 48) -> List[Problem]:
     probs = []
-    for k, (fam, size, M) in enumerate(config4_sizes(instance_seed)[:max_instances]):
-        ss = seed_seq(4, instance_seed, k)
+    for k, (fam, size, M) in enumerate(uneven_batch_sizes(instance_seed)[:max_instances]):
+        ss = seed_seq(STREAM["uneven_batch"], instance_seed, k)
         p = make_scheduling(size, M, ss) if fam == "scheduling" else make_placement(size, ss)
-        p.meta.update(config=4, instance_seed=instance_seed, batch_index=k)
+        p.meta.update(workload="uneven_batch", instance_seed=instance_seed, batch_index=k)
         probs.append(p)
     return probs
 
@@ -166,5 +171,5 @@ def make_random_hybrid(n: int, seed_keys=(6, 0), card_len=None, xor_len: int = 5
     return b.build(meta=dict(family="random_hybrid", n=n))
 
 
-__all__ = ["RESTARTS", "make_config", "make_batch_config4", "config4_sizes", "initial_points",
+__all__ = ["STREAM", "RESTARTS", "make_workload", "uneven_batch", "uneven_batch_sizes", "initial_points",
            "make_random_formula", "make_random_hybrid", "seed_seq", "OP_EQ"]
