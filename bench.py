@@ -150,7 +150,7 @@ def bytes_per_pass(cost, p, R):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(restarts and instances shard across GPUs without exchange)"}))
         sys.exit(2)
     import torch
