@@ -138,6 +138,9 @@ typedef struct {
                                   variables choose, per assignment, a disjunction of literals (a
                                   clause; ITE over clauses); forward and reverse sweeps run in
                                   closed form */
+    int32_t n_gd_sep;          /* of those, constraints whose two selectors pick their atoms
+                                  independently (a rectangle pair's rotation ITE), so the false
+                                  mass is the product of one sum per selector */
 } fsmt_xbdd_stats;
 
 /* A strided 2-D float view [rows][cols] of device memory: element (r, v) is at

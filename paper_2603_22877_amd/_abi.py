@@ -39,7 +39,7 @@ class Stats(ct.Structure):
                 ("table_bytes", ct.c_int64), ("atom_nnz", ct.c_int64), ("n_box_units", ct.c_int32),
                 ("n_halfspaces", ct.c_int32), ("n_big", ct.c_int32),
                 ("n_hs_colors", ct.c_int32), ("n_pair", ct.c_int32),
-                ("hs_separable", ct.c_int32), ("n_gd", ct.c_int32)]
+                ("hs_separable", ct.c_int32), ("n_gd", ct.c_int32), ("n_gd_sep", ct.c_int32)]
 
 
 class View(ct.Structure):

@@ -620,9 +620,9 @@ __device__ __forceinline__ float pair_eval(const TabView &T, const TaskCtx &t, c
 // lane issues all of its table reads up front (lanes on padding positions or past the
 // restarts read position and restart 0, which exist), so their latencies overlap.
 __device__ __forceinline__ GdInfo load_gd(cptr<GdInfo> p) {
-    static_assert(sizeof(GdInfo) == 32, "guarded-disjunction record layout");
-    typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
-    const i32x8 raw = *(cptr<i32x8>)p;
+    static_assert(sizeof(GdInfo) == 64, "guarded-disjunction record layout");
+    typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+    const i32x16 raw = *(cptr<i32x16>)p;
     GdInfo g;
     __builtin_memcpy(&g, &raw, sizeof(g));
     return g;
@@ -754,8 +754,34 @@ __device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, c
     for (int i = 0; i < NBm; ++i) glb[i] = 0.0f;
 #pragma unroll
     for (int j = 0; j < NAm; ++j) gla[j] = 0.0f;
+    if constexpr (NBm >= 2) {
+        if (g.sep) {   // the product of the two selectors' sums (see GdInfo::sep)
+            float lx[NAm + 1], L[8];
+#pragma unroll
+            for (int j = 0; j < NAm; ++j) lx[j] = la[j];
+            lx[NAm] = 1.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) L[i] = lx[(g.sep_slots >> (4 * i)) & 15u];
+            const float P00 = L[0] * L[1], P01 = L[2] * L[3], P10 = L[4] * L[5], P11 = L[6] * L[7];
+            const float SA = qb[0] * P00 + pb[0] * P01, SB = qb[1] * P10 + pb[1] * P11;
+            F = SA * SB;
+            if constexpr (kGrad) {
+                gp0 = (P01 - P00) * SB;
+                gp1 = (P11 - P10) * SA;
+                const float wq[4] = {qb[0] * SB, pb[0] * SB, qb[1] * SA, pb[1] * SA};
+                float gx[NAm + 1];
+#pragma unroll
+                for (int j = 0; j <= NAm; ++j) gx[j] = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) gx[(g.sep_slots >> (4 * i)) & 15u] = wq[i >> 1] * L[i ^ 1];
+#pragma unroll
+                for (int j = 0; j < NAm; ++j) gla[j] = gx[j];
+            }
+        }
+    }
 #pragma unroll
     for (int c = 0; c < (1 << kGdMaxSel); ++c) {
+        if (g.sep) break;
         if (c >= (1 << k)) break;
         const uint32_t m = g.mask[c];
         if (m >> 31) continue;   // this assignment reaches the True terminal

@@ -62,6 +62,15 @@ struct GdInfo {
     uint32_t same_vars; // bit j: atom slot j has the variables of atom slot j-1 in every constraint
                         // of the template (their values are read once, their gradients summed)
     uint32_t same_lin;  // bit j: ... and the same coefficients (q.y is computed once)
+    // Separable (k = 2, no other Boolean slot, no assignment reaching True): selector i's
+    // value v alone picks the atoms S_{i,v} of the disjunction, the four sets are disjoint
+    // and each has at most two atoms, so
+    //   F = (P[s0 F] L(S_{0,0}) + P[s0 T] L(S_{0,1})) (P[s1 F] L(S_{1,0}) + P[s1 T] L(S_{1,1})),
+    // L(S) the product of S's literal-false probabilities. sep_slots holds the atom slots of
+    // S_{0,0}, S_{0,1}, S_{1,0}, S_{1,1}, two 4-bit fields per group (kGdMaxAtoms: none).
+    uint32_t sep;
+    uint32_t sep_slots;
+    uint32_t pad[6];
 };
 // Closed-form levels a kernel carries (chosen by the host from the instances of a launch, so
 // that a kernel holds only the register footprint it needs): 0 none; 1 guarded disjunctions
@@ -173,6 +182,7 @@ struct fsmt_xbdd {
     int hs_separable = 0;   // one colour class, rows of at most kSeparableRowMax distinct variables
     int64_t n_pair = 0;               // constraints evaluated as pair disjunctions (closed form)
     int64_t n_gd = 0;                 // constraints evaluated as guarded disjunctions (closed form)
+    int64_t n_gd_sep = 0;             // ... of which separable (GdInfo::sep)
     int gd_level = 0;                 // largest closed-form level of its guarded disjunctions (1..3)
     bool lds_messages = false;   // FSMT_MSG_LDS: never the register-resident message variants
     bool all_inline = false;     // every atom slot of every bucket has an inline record

@@ -217,6 +217,45 @@ struct Template {
 // P[g] times the product of the chain's literal-false probabilities, which is what the
 // forward pass accumulates (chains that share their tails add their masses into the shared
 // nodes, and a selector the path skips contributes both of its branches).
+// Separable guarded disjunction (GdInfo::sep): two selectors and no other Boolean, every
+// assignment reaches a disjunction of atoms, and the disjunction of assignment (v0, v1) is
+// the union of a set picked by v0 alone and one picked by v1 alone: S_{0,v0} = the atoms
+// common to (v0, F) and (v0, T), S_{1,v1} likewise. The four sets must be disjoint and hold at
+// most two atoms each (a rectangle pair's rotation ITE: each rotation bit picks the two atoms
+// that use that rectangle's sides).
+static void gd_separable(GdInfo &g, int nb, int na) {
+    g.sep = 0;
+    g.sep_slots = 0;
+    if (g.k != 2 || nb != 2 || na > kGdMaxAtoms) return;
+    uint32_t mA[4];
+    for (int c = 0; c < 4; ++c) {
+        if ((g.mask[c] >> 31) || (g.mask[c] & 3u)) return;
+        mA[c] = g.mask[c] >> 2;
+    }
+    // assignment c: bit 0 = selector 0 True, bit 1 = selector 1 True
+    const uint32_t S[4] = {mA[0] & mA[2], mA[1] & mA[3], mA[0] & mA[1], mA[2] & mA[3]};
+    for (int c = 0; c < 4; ++c)
+        if (mA[c] != (S[c & 1] | S[2 + (c >> 1)])) return;
+    int total = 0;
+    uint32_t all = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int cnt = __builtin_popcount(S[q]);
+        if (cnt > 2) return;
+        total += cnt;
+        all |= S[q];
+    }
+    if (__builtin_popcount(all) != total) return;   // not disjoint
+    uint32_t slots = 0;
+    for (int q = 0; q < 4; ++q) {
+        int f = 0;
+        for (int j = 0; j < na; ++j)
+            if ((S[q] >> j) & 1u) slots |= (uint32_t)j << (4 * (2 * q + f++));
+        for (; f < 2; ++f) slots |= (uint32_t)kGdMaxAtoms << (4 * (2 * q + f));
+    }
+    g.sep = 1;
+    g.sep_slots = slots;
+}
+
 static GdInfo gd_family(const Template &T) {
     GdInfo g{};
     g.k = -1;
@@ -251,6 +290,7 @@ static GdInfo gd_family(const Template &T) {
             for (int c = 0; c < 4; ++c) g.mask[c] = c < (1 << k) ? mask[c] : 0;
             g.neg = neg;
             g.k = k;
+            gd_separable(g, T.n_bslots, T.n_slots - T.n_bslots);
             return g;
         }
     }
@@ -614,6 +654,7 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
             h->n_pair += (int64_t)members[t].size();   // closed form: no message store, never big
         } else if (tp.gd.k >= 0) {
             h->n_gd += (int64_t)members[t].size();     // likewise
+            if (tp.gd.sep) h->n_gd_sep += (int64_t)members[t].size();
             h->gd_level = std::max(h->gd_level, gd_level_of(tp.n_bslots, tp.n_slots - tp.n_bslots));
         } else if (big_diagram(tp.n_nodes, tp.n_slots)) {
             h->big_max_nodes = std::max(h->big_max_nodes, tp.n_nodes);
@@ -927,6 +968,7 @@ fsmt_status xbdd_info(const fsmt_xbdd *h, fsmt_xbdd_stats *s) {
     s->n_pair = (int32_t)h->n_pair;
     s->hs_separable = h->hs_separable;
     s->n_gd = (int32_t)h->n_gd;
+    s->n_gd_sep = (int32_t)h->n_gd_sep;
     s->n_positions = h->n_pos;
     s->table_bytes = h->table_bytes;
     s->atom_nnz = h->nnz;

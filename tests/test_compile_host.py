@@ -141,6 +141,33 @@ def test_guarded_disjunctions_are_recognized_from_the_diagram():
         assert got == int(want), (kind, lits, ops)
 
 
+def test_separable_guarded_disjunctions_are_recognized():
+    """Two selectors whose values pick their atoms independently (the assignment (v0, v1)
+    reaches S_{0,v0} OR S_{1,v1}, four disjoint sets of at most two atoms) are marked
+    separable; an ITE over the same atoms whose assignments do not split that way is not.
+    Rectangle pairs with two non-square rectangles are separable; scheduling clauses
+    (one selector) are not."""
+    from workloads.format import X_ITE, X_OR
+    def build(prog):
+        bb = Builder(2, 1, real_lo=np.zeros(1), real_hi=np.ones(1))
+        at = [bb.atom([0], [1.0], OP_LE, r) for r in (0.125, 0.25, 0.5, 0.75)]
+        lits = [lit(0), lit(1)] + [lit(k, j == 2) for j, k in enumerate(at)]
+        bb.add(KIND_EXPR, lits, ops=prog)
+        return bb.build()
+    # ITE(x0, ITE(x1, A1|A3, A1|A2), ITE(x1, A0|A3, A0|A2)): S = {A0}, {A1}, {A2}, {A3}
+    sep = build((0, 1, 3, 5, X_OR, 3, 4, X_OR, X_ITE, 1, 2, 5, X_OR, 2, 4, X_OR, X_ITE, X_ITE))
+    i = fsmt.xbdd_info(compile_host(sep))
+    assert i["n_gd"] == 1 and i["n_gd_sep"] == 1
+    # ITE(x0, ITE(x1, A1|A3, A2|A3), ITE(x1, A0|A2, A0|A1)): not a product of two choices
+    mix = build((0, 1, 3, 5, X_OR, 4, 5, X_OR, X_ITE, 1, 2, 4, X_OR, 2, 3, X_OR, X_ITE, X_ITE))
+    i = fsmt.xbdd_info(compile_host(mix))
+    assert i["n_gd"] == 1 and i["n_gd_sep"] == 0
+    p = W.make_workload("placement_150")
+    i = fsmt.xbdd_info(compile_host(p))
+    assert 0.8 * p.meta["n_pairs"] < i["n_gd_sep"] <= p.meta["n_pairs"]
+    assert fsmt.xbdd_info(compile_host(W.make_workload("scheduling_200x10")))["n_gd_sep"] == 0
+
+
 def test_guarded_disjunction_members_share_their_atom_forms():
     """The closed form streams only variables and right-hand sides: the members of one
     guarded-disjunction template share each atom slot's coefficients, scale and strictness.

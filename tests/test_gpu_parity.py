@@ -127,6 +127,38 @@ def test_mixed_small_and_big_diagrams(seed, R):
         _compare(p, a, b, kap, layout="cols")
 
 
+@pytest.mark.parametrize("seed,R", [(0, 1), (1, 5), (2, 64)])
+def test_separable_guarded_disjunctions(seed, R):
+    """ITEs over two Booleans whose values pick their atom groups independently (evaluated as
+    the product of one sum per selector) mixed with ITEs that do not factor, at every kappa
+    regime and with per-constraint weights; also the fused step of the persistent and grid
+    schedules."""
+    from paper_2603_22877_amd import solver as S
+    p = W.make_random_separable(seed)
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"separable seed={seed} R={R} sep={info['n_gd_sep']} gd={info['n_gd']} of {p.n_cons}", flush=True)
+    assert 0 < info["n_gd_sep"] < info["n_gd"]
+    a, b = W.initial_points(p, R, 95, seed)
+    a[0, :4] = [0.0, -1.0, 1.0, 0.5]
+    for kap in (0.0, 0.6, 4.0, INF):
+        _compare(p, a, b, kap, w=np.random.default_rng(seed).uniform(0.5, 2, (R, p.n_cons)))
+    for sched in (1, 2):
+        h = fsmt.xbdd_compile(p)
+        st = S.BatchState(h, a, b)
+        S.solve_batched([h], [st], S.SolveConfig(kappas=[0.6], steps_per_level=1, eta_a=0.5, eta_b=0.5, eps=0.0,
+                                                  stop_on_sat=0, schedule=sched))
+        torch.cuda.synchronize()
+        o = oracle.objective(p, a, b, 0.6, per_constraint=False)
+        ref = oracle.pgd(p, a, b, o["grad_a"].astype(np.float32), o["grad_b"].astype(np.float32), 0.5, 0.5)
+        assert_objective(st.obj.cpu().numpy(), o["U"], p.n_cons)
+        for r in range(R):
+            tol_a = 0.5 * (1e-5 * o["absg_a"][r] + 4e-7 * o["absg_a"][r].max()) + 3e-7 * (1 + np.abs(ref["a"][r]))
+            assert np.all(np.abs(st.a.cpu().numpy()[r] - ref["a"][r]) <= tol_a)
+            tol_b = 0.5 * (1e-5 * o["absg_b"][r] + 4e-7 * o["absg_b"][r].max()) + 2e-6 * (1 + np.abs(ref["b"][r]))
+            assert np.all(np.abs(st.b.cpu().numpy()[r] - ref["b"][r]) <= tol_b)
+        h.free()
+
+
 @pytest.mark.parametrize("name,R", [("scheduling_200x10", 1), ("placement_150", 1), ("placement_150", 16)])
 def test_backward_accumulates_into_the_outputs(name, R):
     """FSMT_ACCUMULATE adds into obj and the gradients instead of overwriting them: a

@@ -171,5 +171,50 @@ def make_random_hybrid(n: int, seed_keys=(6, 0), card_len=None, xor_len: int = 5
     return b.build(meta=dict(family="random_hybrid", n=n))
 
 
+def make_random_separable(seed: int, n_bool: int = 12, n_real: int = 6, n_cons: int = 240) -> Problem:
+    """ITEs over two Booleans u < v of disjunctions of atoms (test inputs):
+    ITE(u, ITE(v, A1 | B1, A1 | B0), ITE(v, A0 | B1, A0 | B0)) with A0, A1, B0, B1 disjoint
+    groups of one or two atoms, so u picks the A group and v the B group independently; a
+    quarter of the constraints instead mix the groups (ITE(u, ITE(v, A1 | B1, A0 | B1),
+    ITE(v, A0 | B0, A1 | B0))), which no choice of groups factors. Three shapes (group sizes,
+    literal polarities, atom coefficients) recur, with random variables and right-hand sides
+    that are multiples of 1/8, so constraints share templates."""
+    from .format import KIND_EXPR as _EXPR
+    rng = np.random.Generator(np.random.PCG64(seed_seq(7788, seed)))
+    b = Builder(n_bool, n_real, real_lo=np.full(n_real, -3.0), real_hi=np.full(n_real, 3.0))
+    shapes = [((2, 2, 2, 2), ((1.0, -1.0), (1.0, -1.0), (1.0, -1.0), (1.0, -1.0), (1.0, -1.0), (1.0, -1.0),
+                              (1.0, -1.0), (1.0, -1.0)), (0, 1, 0, 0, 1, 0, 0, 0)),
+              ((1, 2, 2, 1), ((2.0,), (1.0, -0.5), (1.0, 1.0), (-1.0,), (1.0, -1.0), (0.5,)), (1, 0, 0, 1, 0, 0)),
+              ((1, 1, 1, 1), ((1.0,), (-1.0,), (1.0, -1.0), (1.0, 2.0)), (0, 0, 1, 0))]
+    for c in range(n_cons):
+        sizes, forms, negs = shapes[c % len(shapes)]
+        u, v = (int(x) for x in np.sort(rng.choice(n_bool, 2, replace=False)))
+        atoms = []
+        for cf in forms:
+            vs = rng.choice(n_real, len(cf), replace=False)
+            atoms.append(b.atom(vs, list(cf), 0, float(rng.integers(-16, 17)) / 8.0))
+        groups, k = [], 0
+        for sz in sizes:
+            groups.append(list(range(k, k + sz)))
+            k += sz
+        lits = [lit(u), lit(v)] + [lit(a, bool(nb)) for a, nb in zip(atoms, negs)]
+
+        def disj(g1, g2):
+            ids = [2 + j for j in g1 + g2]
+            prog = [ids[0]]
+            for j in ids[1:]:
+                prog += [j, X_OR]
+            return prog
+        A0, A1, B0, B1 = groups
+        if c % 4 == 3:   # mixed: not a product of two independent choices
+            prog = ([0, 1] + disj(A1, B1) + disj(A0, B1) + [X_ITE] + [1] + disj(A0, B0) + disj(A1, B0)
+                    + [X_ITE, X_ITE])
+        else:
+            prog = ([0, 1] + disj(A1, B1) + disj(A1, B0) + [X_ITE] + [1] + disj(A0, B1) + disj(A0, B0)
+                    + [X_ITE, X_ITE])
+        b.add(_EXPR, lits, 0, prog)
+    return b.build(meta=dict(family="random_separable", seed=seed))
+
+
 __all__ = ["STREAM", "RESTARTS", "make_workload", "uneven_batch", "uneven_batch_sizes", "initial_points",
-           "make_random_formula", "make_random_hybrid", "seed_seq", "OP_EQ"]
+           "make_random_formula", "make_random_hybrid", "make_random_separable", "seed_seq", "OP_EQ"]
