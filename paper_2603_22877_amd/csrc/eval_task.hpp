@@ -644,10 +644,11 @@ __device__ __forceinline__ void gd_atom(double lin, float rhs, float scale, bool
         const double ks = kappa * (double)scale;
         const float u = (float)(z * ks);
         float emu2;
-        const float e = 0.5f * erfc_nr(fabsf(u), emu2);   // the smaller of p, 1-p
+        // the smaller of p, 1-p; a NaN u gives a NaN e (rcp, exp2 and fma keep NaN), so p
+        // and q are NaN too
+        const float e = 0.5f * erfc_nr(fabsf(u), emu2);
         p = (u >= 0.0f) ? e : 1.0f - e;
         q = (u >= 0.0f) ? 1.0f - e : e;
-        if (u != u) { p = u; q = u; }                    // NaN in, NaN out
         d = -((float)ks * 0.56418958354775628695f) * emu2;
     }
 }
@@ -733,9 +734,7 @@ __device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, c
             }
             if (j == 0 || !((g.same_lin >> j) & 1u)) {
 #pragma clang fp contract(off)
-                double acc = 0.0;
-                const double p0 = (double)c0[j] * (double)y0[j];
-                acc = acc + p0;
+                double acc = (double)c0[j] * (double)y0[j];   // the stored first product
                 if (two) {
                     const double p1 = (double)c1[j] * (double)y1[j];
                     acc = acc + p1;

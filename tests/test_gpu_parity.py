@@ -159,6 +159,28 @@ def test_separable_guarded_disjunctions(seed, R):
         h.free()
 
 
+@pytest.mark.parametrize("name", ["scheduling_200x10", "placement_150"])
+def test_nan_state_propagates_to_its_restart(name):
+    """A NaN coordinate makes its restart's objective NaN (forward and reverse) and the
+    gradient of the variables it shares a constraint with (the objective is multilinear, so
+    the derivative by the NaN variable itself does not involve its value), and leaves the
+    other restarts as the oracle computes them."""
+    p = W.make_workload(name)
+    a, b = W.initial_points(p, 3, W.STREAM[name], 8)
+    b[1, 0] = np.nan          # a real
+    a[2, 0] = np.nan          # a Boolean
+    h = fsmt.xbdd_compile(p)
+    kap = 0.5
+    g = _run_cop(p, h, a, b, kap)
+    o = oracle.objective(p, a[:1], b[:1], kap)
+    assert_objective(g["U"][:1], o["U"], p.n_cons)
+    assert_objective(g["U_fwd"][:1], o["U"], p.n_cons)
+    assert np.isnan(g["U"][1]) and np.isnan(g["U_fwd"][1]) and np.isnan(g["U"][2]) and np.isnan(g["U_fwd"][2])
+    assert np.isnan(g["grad_b"][1]).any() and np.isnan(g["grad_b"][2]).any()
+    assert np.all(np.isfinite(g["grad_a"][0])) and np.all(np.isfinite(g["grad_b"][0]))
+    h.free()
+
+
 @pytest.mark.parametrize("name,R", [("scheduling_200x10", 1), ("placement_150", 1), ("placement_150", 16)])
 def test_backward_accumulates_into_the_outputs(name, R):
     """FSMT_ACCUMULATE adds into obj and the gradients instead of overwriting them: a
