@@ -597,9 +597,19 @@ static fsmt_status compile_impl(const fsmt_problem *P, const fsmt_compile_opts *
         const int nb = tp.n_bslots, na = tp.n_slots - tp.n_bslots;
         GdForm &F = gd_form[t];
         {
+            // a two-variable atom on the previous slot's variables in the other order takes
+            // that order (its coefficients swapped with them), so the two slots form one run
+            // of the closed form's reads and scatter (a rectangle pair's x_i + w <= x_j and
+            // x_j + w' <= x_i); the other members are matched to these forms term by term
             const int32_t *ids0 = con_ids.data() + con_sup_off[members[t][0]];
+            Canon prev{};
             for (int j = 0; j < na; ++j) {
-                const Canon a = canon(ids0[nb + j] - n);
+                Canon a = canon(ids0[nb + j] - n);
+                if (j > 0 && (a.fl & 2u) && (prev.fl & 2u) && a.v0 != a.v1 && a.v0 == prev.v1 && a.v1 == prev.v0) {
+                    std::swap(a.v0, a.v1);
+                    std::swap(a.c0, a.c1);
+                }
+                prev = a;
                 F.c0[j] = a.c0;
                 F.c1[j] = a.c1;
                 F.scale[j] = a.sc;
