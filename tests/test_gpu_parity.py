@@ -159,6 +159,37 @@ def test_separable_guarded_disjunctions(seed, R):
         h.free()
 
 
+@pytest.mark.parametrize("R", [1, 16])
+def test_swapped_term_runs(R):
+    """Guarded disjunctions whose consecutive atoms name one variable pair in either stored
+    order (y_u - y_v <= c, then y_v - y_u <= c'): the compiler stores the second in the first's
+    order, so the two form one run of reads and scatter; objective and gradient against the
+    oracle at several kappa, with per-constraint weights."""
+    from workloads.format import Builder, KIND_CLAUSE, KIND_EXPR, X_ITE, X_OR, lit
+    rng = np.random.default_rng(61)
+    n_bool, n_real = 6, 8
+    bb = Builder(n_bool, n_real, real_lo=np.full(n_real, -2.0), real_hi=np.full(n_real, 2.0))
+    for c in range(300):
+        u, v = (int(x) for x in rng.choice(n_real, 2, replace=False))
+        q = float(rng.choice([1.0, 2.0, 0.5]))
+        a1 = bb.atom([u, v], [q, -q], 0, float(rng.integers(-8, 9)) / 8)
+        a2 = bb.atom([v, u], [q, -q], 0, float(rng.integers(-8, 9)) / 8)
+        a3 = bb.atom([v, u], [-2.0, 1.0], 0, float(rng.integers(-8, 9)) / 8)
+        s0, s1 = (int(x) for x in np.sort(rng.choice(n_bool, 2, replace=False)))
+        if c % 2:
+            bb.add(KIND_CLAUSE, [lit(s0, True), lit(a1), lit(a2, True), lit(a3)])
+        else:   # ITE(s0, a1 | a2, a2 | a3) over one more Boolean
+            bb.add(KIND_EXPR, [lit(s0), lit(a1), lit(a2), lit(a2), lit(a3), lit(s1)],
+                   ops=(0, 1, 2, X_OR, 3, 4, X_OR, 5, X_OR, X_ITE))
+    p = bb.build()
+    info = fsmt.xbdd_info(fsmt.xbdd_compile(p, device=fsmt.FSMT_HOST_ONLY))
+    print(f"swapped-term runs R={R} gd={info['n_gd']} of {p.n_cons} templates={info['n_templates']}", flush=True)
+    assert info["n_gd"] == p.n_cons
+    a, b = W.initial_points(p, R, 62, R)
+    for kap in (0.0, 0.8, 5.0, INF):
+        _compare(p, a, b, kap, w=np.random.default_rng(R).uniform(0.5, 2, (R, p.n_cons)))
+
+
 @pytest.mark.parametrize("name", ["scheduling_200x10", "placement_150"])
 def test_nan_state_propagates_to_its_restart(name):
     """A NaN coordinate makes its restart's objective NaN (forward and reverse) and the
