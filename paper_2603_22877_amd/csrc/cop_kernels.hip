@@ -167,8 +167,19 @@ __global__ void __launch_bounds__(1024) sum_rows_kernel(const float *part, int n
     const int nm = n + m, group = blockIdx.y;
     const int e = blockIdx.x * 64 + c;
     float acc = 0.0f;
-    if (e < nm * G)
-        for (int w = s; w < n_wg; w += 16) acc += part[((int64_t)group * n_wg + w) * nm * G + e];
+    if (e < nm * G) {
+        // a stripe's first 16 rows are requested together (one round trip, not 16)
+        const float *col = part + (int64_t)group * n_wg * nm * G + e;
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int w = s + 16 * q;
+            v[q] = w < n_wg ? col[(int64_t)w * nm * G] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc += v[q];
+        for (int w = s + 256; w < n_wg; w += 16) acc += col[(int64_t)w * nm * G];
+    }
     red[s][c] = acc;
     __syncthreads();
     const int v = e / G, r = group * G + (e - v * G);
