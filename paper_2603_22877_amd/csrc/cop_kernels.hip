@@ -128,10 +128,22 @@ __global__ void __launch_bounds__(1024) cop_lds_grad_kernel(CopArgs A, float *pa
     const int64_t n_wg = gridDim.x / n_groups, wg = blockIdx.x % n_wg;
     const int group = (int)(blockIdx.x / n_wg), r0 = group * G;
     float *const sy = lds + nm * G;   // a then b, [variable][G]
-    for (int e = threadIdx.x; e < nm * G; e += blockDim.x) {
-        const int v = e / G, r = r0 + (e - v * G);
-        lds[e] = 0.0f;
-        sy[e] = r < A.R ? (v < n ? (float)A.a.at(r, v) : (float)A.b.at(r, v - n)) : 0.0f;
+    // the point: four elements per thread requested together, then stored
+    for (int e0 = threadIdx.x; e0 < nm * G; e0 += 4 * blockDim.x) {
+        float x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * (int)blockDim.x, v = e / G, r = r0 + (e - v * G);
+            x[q] = (e < nm * G && r < A.R) ? (v < n ? (float)A.a.at(r, v) : (float)A.b.at(r, v - n)) : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * (int)blockDim.x;
+            if (e < nm * G) {
+                lds[e] = 0.0f;
+                sy[e] = x[q];
+            }
+        }
     }
     __syncthreads();
     FSMT_MSG_STORE(Ms, W, nullptr, 0, 0, lane);
