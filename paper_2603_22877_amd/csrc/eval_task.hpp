@@ -755,6 +755,7 @@ __device__ __forceinline__ float gd_eval_n(const TabView &T, const TaskCtx &t, c
     for (int j = 0; j < NAm; ++j) gla[j] = 0.0f;
     if constexpr (NBm >= 2) {
         if (g.sep) {   // the product of the two selectors' sums (see GdInfo::sep)
+            static_assert(NAm == kGdMaxAtoms, "sep_slots name a missing atom kGdMaxAtoms: lx[NAm] holds its 1");
             float lx[NAm + 1], L[8];
 #pragma unroll
             for (int j = 0; j < NAm; ++j) lx[j] = la[j];
